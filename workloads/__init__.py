@@ -1,0 +1,238 @@
+"""Seeded synthetic workloads for list ranking (input generators only).
+
+The inputs follow the paper's instance families (Section 3, "Input
+Instances"): random lists (List(n, gamma=1)), lists with locality, forests of
+lists, and Euler tours of trees. Each generator builds its lists from an
+explicit visiting order, so the expected ranks are known in closed form from
+that order; nothing here ranks a list.
+
+Both the CPU oracle tests and the GPU path draw their inputs from here, and
+this module imports neither of them.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB = os.path.join(_HERE, "libworkloads.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the generator library (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    u64, u32p = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)
+    vp = ctypes.c_void_p
+    lib.wl_draw.restype = u64
+    lib.wl_draw.argtypes = [u64, u64, u64]
+    lib.wl_perm.argtypes = [u64, u64, u64, vp]
+    lib.wl_link_order.argtypes = [vp, u64, vp]
+    lib.wl_block_order.argtypes = [u64, u64, u64, u64, vp]
+    lib.wl_forest_lengths.restype = u64
+    lib.wl_forest_lengths.argtypes = [u64, u64, ctypes.c_double, u64, u64, vp, u64]
+    lib.wl_link_chunks.argtypes = [vp, vp, u64, vp]
+    lib.wl_weights_i64.argtypes = [u64, u64, u64, ctypes.c_int64, ctypes.c_int64, vp]
+    lib.wl_weights_i32.argtypes = [u64, u64, u64, ctypes.c_int32, ctypes.c_int32, vp]
+    lib.wl_recursive_tree.argtypes = [u64, u64, vp]
+    lib.wl_tree_depth.argtypes = [vp, u64, vp]
+    lib.wl_euler_tour.restype = ctypes.c_int
+    lib.wl_euler_tour.argtypes = [u64, vp, u64, vp, vp, vp]
+    del u32p
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def draw(seed: int, stream: int, i: int) -> int:
+    return int(_load().wl_draw(seed, stream, i))
+
+
+def perm(n: int, seed: int, stream: int = 0) -> np.ndarray:
+    """Pseudorandom permutation of [0, n) as uint32 (keyed Feistel + cycle walking)."""
+    out = np.empty(n, dtype=np.uint32)
+    if n:
+        _load().wl_perm(seed, stream, n, _ptr(out))
+    return out
+
+
+def link_order(order: np.ndarray) -> np.ndarray:
+    """Successor array of the single list visiting `order` (last element is the terminal)."""
+    order = np.ascontiguousarray(order, dtype=np.uint32)
+    succ = np.empty(order.size, dtype=np.uint32)
+    if order.size:
+        _load().wl_link_order(_ptr(order), order.size, _ptr(succ))
+    return succ
+
+
+def block_order(n: int, block: int, seed: int, stream: int = 0) -> np.ndarray:
+    """Visiting order with locality: blocks of `block` consecutive ids in random
+    order, each block's ids in random order (the last block may be shorter)."""
+    out = np.empty(n, dtype=np.uint32)
+    if n:
+        _load().wl_block_order(seed, stream, n, block, _ptr(out))
+    return out
+
+
+@dataclass
+class ListInput:
+    succ: np.ndarray          # uint32[n]
+    order: np.ndarray         # uint32[n]: visiting order; rank[order[j]] = n-1-j
+
+
+def random_list(n: int, seed: int = 1, stream: int = 0) -> ListInput:
+    """One list over [0, n) in pseudorandom order (the paper's List(n, 1.0))."""
+    order = perm(n, seed, stream)
+    return ListInput(link_order(order), order)
+
+
+def block_list(n: int, block: int = 4096, seed: int = 2, stream: int = 1) -> ListInput:
+    """One list with block locality (blocks of `block` ids, chained in random order)."""
+    order = block_order(n, block, seed, stream)
+    return ListInput(link_order(order), order)
+
+
+def identity_list(n: int) -> ListInput:
+    """succ[i] = i + 1: the paper's List(n, 0.0) on one PE."""
+    order = np.arange(n, dtype=np.uint32)
+    return ListInput(link_order(order), order)
+
+
+@dataclass
+class ForestInput:
+    succ: np.ndarray          # uint32[n]
+    weight: np.ndarray        # int64[n] or int32[n]
+    order: np.ndarray         # uint32[n]; list i visits order[starts[i]:starts[i+1]]
+    starts: np.ndarray        # int64[count+1]
+
+
+def forest_lengths(seed: int, short_total: int, mean: float, n_long: int, long_len: int) -> np.ndarray:
+    lib = _load()
+    cnt = int(lib.wl_forest_lengths(seed, short_total, mean, n_long, long_len, None, 0))
+    lens = np.empty(cnt, dtype=np.uint64)
+    lib.wl_forest_lengths(seed, short_total, mean, n_long, long_len, _ptr(lens), cnt)
+    return lens
+
+
+def forest(n: int, mean: float = 64.0, n_long: int = 16, long_len: int = 1 << 20, seed: int = 3,
+           wlo: int = -1000, whi: int = 1000, wdtype=np.int64) -> ForestInput:
+    """Forest of lists: geometric lengths (support {1, 2, ...}, given mean) filling
+    n - n_long*long_len elements, the last truncated, plus n_long long lists;
+    ids placed in pseudorandom order; per-element weights uniform in [wlo, whi]."""
+    short_total = n - n_long * long_len
+    if short_total < 0:
+        raise ValueError("long lists exceed n")
+    lens = forest_lengths(seed, short_total, mean, n_long, long_len)
+    starts = np.zeros(lens.size + 1, dtype=np.int64)
+    np.cumsum(lens.astype(np.int64), out=starts[1:])
+    order = perm(n, seed, 33)
+    succ = np.empty(n, dtype=np.uint32)
+    if n:
+        _load().wl_link_chunks(_ptr(order), _ptr(starts), lens.size, _ptr(succ))
+    w = weights(n, seed, 35, wlo, whi, wdtype)
+    return ForestInput(succ, w, order, starts)
+
+
+def weights(n: int, seed: int, stream: int, lo: int, hi: int, dtype=np.int64) -> np.ndarray:
+    w = np.empty(n, dtype=dtype)
+    if n:
+        if dtype == np.int64:
+            _load().wl_weights_i64(seed, stream, n, lo, hi, _ptr(w))
+        elif dtype == np.int32:
+            _load().wl_weights_i32(seed, stream, n, lo, hi, _ptr(w))
+        else:
+            raise TypeError(dtype)
+    return w
+
+
+@dataclass
+class EulerInput:
+    succ: np.ndarray          # uint32[2(V-1)]
+    weight: np.ndarray        # int32: +1 down arcs, -1 up arcs
+    parent: np.ndarray        # uint32[V]
+    down_arc: np.ndarray      # uint32[V]: arc id of parent(v) -> v (entry 0 unused)
+    depth: np.ndarray         # uint32[V]: depth from parent recurrence
+
+
+def euler_tour(V: int, seed: int = 4) -> EulerInput:
+    """Euler tour of a random recursive tree (parent[v] uniform in [0, v))."""
+    lib = _load()
+    parent = np.empty(V, dtype=np.uint32)
+    lib.wl_recursive_tree(seed, V, _ptr(parent))
+    m = 2 * (V - 1) if V >= 2 else 0
+    succ = np.empty(m, dtype=np.uint32)
+    w = np.empty(m, dtype=np.int32)
+    down = np.empty(V, dtype=np.uint32)
+    if V >= 2:
+        rc = lib.wl_euler_tour(seed, _ptr(parent), V, _ptr(succ), _ptr(w), _ptr(down))
+        if rc != 0:
+            raise MemoryError("wl_euler_tour")
+    depth = np.empty(V, dtype=np.uint32)
+    lib.wl_tree_depth(_ptr(parent), V, _ptr(depth))
+    return EulerInput(succ, w, parent, down, depth)
+
+
+# ------------------------------------------------------------ serving trace --
+
+@dataclass
+class Request:
+    idx: int
+    n: int
+    kind: str                 # "random" or "block"
+    seed: int
+    arrival_s: float
+
+
+def serving_trace(count: int = 4096, lo_log2: float = 10.0, hi_log2: float = 24.0, rate_per_s: float = 1000.0,
+                  seed: int = 5, block: int = 4096) -> list[Request]:
+    """Requests with sizes floor(2^U), U ~ U[lo_log2, hi_log2], alternating
+    random/block-local order, and Poisson arrivals (exponential gaps, mean 1/rate)."""
+    out = []
+    t = 0.0
+    for i in range(count):
+        u = (draw(seed, 51, i) >> 11) / float(1 << 53)
+        n = int(math.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u)))
+        g = ((draw(seed, 53, i) >> 11) + 1) / float(1 << 53)
+        t += -math.log(g) / rate_per_s
+        out.append(Request(i, n, "random" if i % 2 == 0 else "block", int(draw(seed, 55, i) & 0x7FFFFFFF), t))
+    return out
+
+
+def request_input(req: Request, block: int = 4096) -> ListInput:
+    if req.kind == "random":
+        return random_list(req.n, seed=req.seed, stream=0)
+    return block_list(req.n, block=block, seed=req.seed, stream=1)
+
+
+# ------------------------------------------------------ named workloads -----
+
+WORKLOADS = {
+    "random_2^20": dict(kind="random", n=1 << 20, seed=1),
+    "random_2^28": dict(kind="random", n=1 << 28, seed=2),
+    "block4096_2^28": dict(kind="block", n=1 << 28, seed=2),
+    "forest_2^27": dict(kind="forest", n=1 << 27, seed=3),
+    "euler_rrt_2^26": dict(kind="euler", V=1 << 26, seed=4),
+}
