@@ -1,0 +1,217 @@
+/*
+ * lr.h -- C ABI of the MI355X (gfx950) list-ranking library (liblr.so).
+ *
+ * Problem (Section 1.1 of "Engineering Scalable Distributed List Ranking"):
+ * a successor array succ[0..n) describes a forest of singly linked lists; a
+ * terminal element points to itself, an initial element has no predecessor.
+ * For every element i the library computes
+ *   root[i] = the terminal of i's list (the paper "identifies i with i_term"),
+ *   rank[i] = the number of links followed from i to reach root[i],
+ *   sum[i]  = the weighted rank: the sum of the link weights w[j] over the
+ *             elements j on the path from i to root[i], root excluded (the
+ *             terminal has no outgoing link, so its weight never counts).
+ * The paper's in-place convention (succ becomes the terminal, rank goes from
+ * weight to weighted rank) is replaced by const inputs and separate outputs.
+ *
+ * Method: sparse ruling set (Section 2.1, Fig. 1): rulers are sampled, every
+ * ruler and every initial element walks the list to the next ruler or to a
+ * terminal, the rulers form a smaller weighted instance that is solved
+ * recursively down to a pointer-doubling base case (Wyllie), and every element
+ * then takes its rank from the walk that reached it.
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller. Inputs are
+ *     never written; requested outputs are fully overwritten.
+ *   - `ws` is caller-owned device workspace of at least the size the matching
+ *     *_workspace_bytes call reports. The library allocates no device memory
+ *     in these calls. A workspace must not be used by two calls that may run
+ *     at the same time.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Calls only
+ *     enqueue work and return; results are valid once the stream reaches that
+ *     point (event or stream synchronisation). Without LR_VALIDATE no call
+ *     synchronises, so a call can be captured into a HIP graph.
+ *   - Indices and ranks are uint32; n must be below 2^31.
+ *   - Without LR_VALIDATE, input that is not a forest of lists (an index out
+ *     of range, two predecessors, a cycle) gives unspecified outputs but never
+ *     an out-of-bounds access or a non-terminating kernel. With LR_VALIDATE
+ *     the call checks the input and the result on the device, synchronises the
+ *     stream, and returns LR_ERR_BAD_LIST for such input.
+ *   - Errors are returned as lr_status; nothing is thrown across the ABI.
+ */
+#ifndef LR_H
+#define LR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lr_status {
+    LR_OK = 0,
+    LR_ERR_INVALID_ARG = 1,   /* null required pointer, bad enum, bad option */
+    LR_ERR_UNSUPPORTED = 2,   /* n >= 2^31, or an option the device cannot run */
+    LR_ERR_WORKSPACE = 3,     /* ws NULL or smaller than required */
+    LR_ERR_OUT_OF_MEMORY = 4, /* server creation could not allocate its pool */
+    LR_ERR_BAD_LIST = 5,      /* LR_VALIDATE found input that is not a forest of lists */
+    LR_ERR_HIP = 6            /* a HIP runtime call failed */
+} lr_status;
+
+/* Element type of the weight array of lr_prefix_sum. */
+typedef enum lr_wtype {
+    LR_W_NONE = 0,  /* no weight array: every link weighs 1 (sum == rank) */
+    LR_W_I32 = 1,   /* int32 weights, widened to int64 */
+    LR_W_I64 = 2    /* int64 weights */
+} lr_wtype;
+
+enum {
+    LR_VALIDATE = 1u,  /* check input and result; synchronises the stream */
+    LR_PROFILE = 2u    /* record per-phase times, read with lr_profile_last */
+};
+
+#define LR_MAX_LEVELS 8
+
+/* Options; a NULL lr_opts* means all defaults. */
+typedef struct lr_opts {
+    uint64_t seed;                     /* seed of the ruler sampling hash */
+    uint32_t flags;                    /* LR_VALIDATE | LR_PROFILE */
+    uint32_t base_max;                 /* largest level solved by the one-workgroup
+                                          base case; 0 = default (8192 unweighted,
+                                          4096 weighted) */
+    uint32_t spacing[LR_MAX_LEVELS];   /* ruler spacing k per recursion level: one
+                                          ruler per k consecutive ids; powers of
+                                          two in [2, 4096]; the list ends at the
+                                          first 0. spacing[0] == 0 = planner
+                                          default. Levels are added with the
+                                          default spacing until the last level
+                                          fits base_max. */
+    uint32_t refill;                   /* chase: idle lanes of a wavefront that
+                                          trigger fetching new walks (1..64);
+                                          0 = default */
+} lr_opts;
+
+/* The plan a call will follow (host-only query, no device needed). */
+typedef struct lr_plan {
+    uint32_t levels;                   /* ruling-set levels before the base case */
+    uint32_t base_max;
+    uint64_t m[LR_MAX_LEVELS + 1];     /* elements per level; m[0] = n,
+                                          m[l+1] = ceil(m[l] / spacing[l]) */
+    uint32_t spacing[LR_MAX_LEVELS];
+    uint64_t workspace_bytes;
+} lr_plan;
+
+/* Fill *out with the plan for n elements (LR_W_NONE = lr_rank). Host only. */
+lr_status lr_plan_query(uint64_t n, lr_wtype w, const lr_opts* opts, lr_plan* out);
+
+/* Workspace bytes for n elements with these options: w == LR_W_NONE sizes an
+ * lr_rank call, LR_W_I32 / LR_W_I64 an lr_prefix_sum call (the same size for
+ * both, and also for lr_prefix_sum without weights). Host only; returns 0
+ * for invalid arguments. */
+size_t lr_workspace_bytes(uint64_t n, lr_wtype w, const lr_opts* opts);
+
+/* Unweighted list ranking (Section 1.1).
+ *   succ  [n] uint32, input: successor array (succ[t] == t marks a terminal).
+ *   rank  [n] uint32, output: links from i to its terminal. Required.
+ *   root  [n] uint32, output: terminal of i's list. May be NULL.
+ * n == 0 returns LR_OK and does nothing. */
+lr_status lr_rank(const uint32_t* succ, uint32_t* rank, uint32_t* root, uint64_t n,
+                  void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
+
+/* Weighted list ranking = list prefix sums (Section 1.1, weighted problem).
+ *   weight [n] int32 or int64 as `w` says (NULL iff w == LR_W_NONE); w[t] of a
+ *          terminal t is ignored.
+ *   sum    [n] int64, output: weighted rank (the suffix sum toward the
+ *          terminal, terminal excluded). Required. The caller guarantees
+ *          |sum| < 2^63.
+ *   rank, root: as lr_rank, both may be NULL.
+ * Head-anchored prefix sums follow: exclusive = sum[head] - sum[i]. */
+lr_status lr_prefix_sum(const uint32_t* succ, const void* weight, lr_wtype w, int64_t* sum,
+                        uint32_t* rank, uint32_t* root, uint64_t n,
+                        void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
+
+/* One unweighted ranking request of a batch. All pointers are device
+ * pointers; rank is required, root may be NULL; root ids are local to the
+ * request (in [0, n)). */
+typedef struct lr_request {
+    const uint32_t* succ;
+    uint32_t* rank;
+    uint32_t* root;
+    uint64_t n;
+} lr_request;
+
+/* Workspace bytes for lr_rank_batch over these requests (host only). */
+size_t lr_batch_workspace_bytes(const lr_request* reqs, uint32_t count, const lr_opts* opts);
+
+/* Rank many independent requests in one pass: the requests are treated as one
+ * forest over the concatenation of their index ranges (lists never cross
+ * requests), so every kernel of the method runs once for the whole batch.
+ * `reqs` is a HOST array of `count` descriptors; it is copied into the
+ * workspace before the call returns. The sum of the n must be below 2^31.
+ * Results are identical to ranking each request alone. */
+lr_status lr_rank_batch(const lr_request* reqs, uint32_t count,
+                        void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
+
+/* GPU baseline: Wyllie pointer doubling over the whole input (Section 1,
+ * Section 2.6: pointer doubling, ceil(log2 n) rounds of
+ * rank[i] += rank[succ[i]], succ[i] = succ[succ[i]]). Same outputs as
+ * lr_rank / lr_prefix_sum. Workspace from lr_wyllie_workspace_bytes. */
+size_t lr_wyllie_workspace_bytes(uint64_t n, lr_wtype w);
+lr_status lr_rank_wyllie(const uint32_t* succ, uint32_t* rank, uint32_t* root, uint64_t n,
+                         void* ws, size_t ws_bytes, void* stream);
+lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtype w, int64_t* sum,
+                               uint32_t* rank, uint32_t* root, uint64_t n,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Per-phase device times (milliseconds) of the last call made with
+ * LR_PROFILE on this thread: [0] detect, [1] head compaction, [2] chase,
+ * [3] upper levels and base case, [4] expand (all levels), [5] total.
+ * Synchronises on the recorded events. Returns the number of values written. */
+int lr_profile_last(double* ms, int cap);
+
+/* Human-readable name of a status code (static storage). */
+const char* lr_status_string(lr_status s);
+
+/* ------------------------------------------------------------- serving ----
+ * Continuous batching (project-defined; the paper has no serving layer).
+ * A server owns `hbm_budget` bytes of device workspace split across
+ * `max_inflight` batch slots, each with its own stream. Submitted requests
+ * wait in FIFO order; whenever a slot is free, the waiting requests whose
+ * workspace fits in the slot are launched together as one lr_rank_batch, so
+ * requests arriving while other batches run join the next batch and their
+ * work overlaps on the device. A request whose workspace can never fit a slot
+ * is rejected with LR_ERR_WORKSPACE; a batch that fails fails only its own
+ * requests. */
+typedef struct lr_server lr_server;
+
+typedef struct lr_server_config {
+    uint64_t hbm_budget;      /* device workspace bytes the server allocates */
+    uint32_t max_inflight;    /* concurrent batches (streams), >= 1 */
+    uint32_t max_batch;       /* most requests per batch (1 = one launch per request) */
+    lr_opts opts;             /* options for every batch */
+} lr_server_config;
+
+lr_status lr_server_create(const lr_server_config* cfg, lr_server** out);
+/* Enqueue a request (device buffers stay owned by the caller and must stay
+ * valid until the ticket completes). */
+lr_status lr_server_submit(lr_server* s, const lr_request* req, uint64_t* ticket);
+/* 0 = pending, 1 = done (*status and *latency_s, seconds from submit to the
+ * server observing completion, are filled), -1 = unknown ticket. */
+int lr_server_poll(lr_server* s, uint64_t ticket, lr_status* status, double* latency_s);
+/* Block until every submitted request has completed. */
+lr_status lr_server_drain(lr_server* s);
+void lr_server_destroy(lr_server* s);
+
+/* Replay a request trace through a server created from cfg: request i is
+ * submitted at arrival_s[i] seconds after the start (host clock). Writes
+ * each request's latency (submit -> completion) to latency_s[i] and the time
+ * from the start to the last completion to *makespan_s; status[i] (may be
+ * NULL) receives each request's status. */
+lr_status lr_server_replay(const lr_server_config* cfg, const lr_request* reqs, const double* arrival_s,
+                           uint32_t count, double* latency_s, lr_status* status, double* makespan_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LR_H */

@@ -1,0 +1,389 @@
+// C ABI of liblr.so: argument checks, planning, workspace carving, dispatch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "device.hpp"
+#include "lr.h"
+#include "plan.hpp"
+#include "runner.hpp"
+
+namespace lr {
+
+static inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+static uint64_t mix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+static bool pow2_in(uint32_t k, uint32_t lo, uint32_t hi) { return k >= lo && k <= hi && (k & (k - 1)) == 0; }
+
+static uint32_t ilog2(uint32_t k) {
+    uint32_t r = 0;
+    while ((1u << r) < k) ++r;
+    return r;
+}
+
+// Default spacing: long first-level walks amortise the per-ruler work on big
+// inputs; upper levels are cache resident and use short walks to keep the
+// longest walk (about k ln(m/k) steps) short. The last level takes the
+// smallest spacing that brings it under base_max.
+static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max) {
+    uint32_t k;
+    if (l == 0) k = (m >= (1ull << 24)) ? 64 : (m >= (1ull << 20) ? 32 : 16);
+    else k = 16;
+    uint32_t kmin = 2;
+    while ((m + kmin - 1) / kmin > base_max && kmin < 4096) kmin <<= 1;
+    return (kmin <= k) ? kmin : k;
+}
+
+lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, Plan* p) {
+    *p = Plan{};
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    p->weighted = weighted;
+    p->rec_bytes = weighted ? 16 : 8;
+    uint32_t bm = (o && o->base_max) ? o->base_max : (weighted ? 4096u : 8192u);
+    if (bm < 1 || bm > BASE_MAX_LIMIT) return LR_ERR_INVALID_ARG;
+    p->base_max = bm;
+    uint32_t rf = (o && o->refill) ? o->refill : 16u;
+    if (rf > 64) return LR_ERR_INVALID_ARG;
+    p->refill = rf;
+    const uint64_t seed = o ? o->seed : 0;
+    if (o) {
+        for (int l = 0; l < LR_MAX_LEVELS && o->spacing[l]; ++l)
+            if (!pow2_in(o->spacing[l], 2, 4096)) return LR_ERR_INVALID_ARG;
+    }
+    uint64_t m = n;
+    uint32_t L = 0;
+    bool user = o && o->spacing[0];
+    p->m[0] = n;
+    while (m > bm) {
+        if (L >= (uint32_t)LR_MAX_LEVELS) return LR_ERR_UNSUPPORTED;
+        uint32_t k;
+        if (user && o->spacing[L]) k = o->spacing[L];
+        else { user = false; k = default_spacing(L, m, bm); }
+        p->log2k[L] = ilog2(k);
+        p->lseed[L] = (uint32_t)mix64(seed * 0x2545f4914f6cdd1dULL + 0x1000 + L);
+        m = (m + k - 1) / k;
+        ++L;
+        p->m[L] = m;
+    }
+    p->levels = L;
+    // layout
+    size_t off = 0;
+    p->off_ctrl = off;
+    off += align_up(sizeof(Ctrl));
+    for (uint32_t l = 0; l < std::max(L, 1u); ++l) {
+        const uint64_t ml = p->m[l];
+        const uint64_t S = (l < L) ? p->m[l + 1] : 0;
+        p->off_slot[l] = off;
+        off += align_up(std::max<size_t>((size_t)ml * p->rec_bytes, 16));
+        if (l < L) {
+            p->ntiles[l] = (uint32_t)((ml + TILE - 1) / TILE);
+            p->off_eb[l] = off;
+            off += align_up((size_t)(S + ml) * p->rec_bytes);
+            p->off_tile[l] = off;
+            off += align_up((size_t)(p->ntiles[l] + 1) * 4);
+        }
+    }
+    if (batch_count) {
+        p->batch_count = batch_count;
+        p->off_batch_succ = off;
+        off += align_up((size_t)n * 4 + 16);
+        p->off_batch_desc = off;
+        off += align_up((size_t)batch_count * sizeof(BatchDesc));
+        p->off_batch_bases = off;
+        off += align_up((size_t)(batch_count + 1) * 4);
+    }
+    p->total = off + ALIGN;  // room to align the caller's base pointer
+    return LR_OK;
+}
+
+// ------------------------------------------------------------- profiling --
+struct ProfState {
+    hipEvent_t ev[EV_COUNT] = {};
+    bool made = false, valid = false;
+};
+static thread_local ProfState g_prof;
+
+static hipEvent_t* prof_events(bool on) {
+    if (!on) return nullptr;
+    if (!g_prof.made) {
+        for (auto& e : g_prof.ev)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_prof.made = true;
+    }
+    g_prof.valid = true;
+    return g_prof.ev;
+}
+
+static char* carve(void* ws) { return reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws))); }
+
+static lr_status finish(hipError_t e, const RunArgs& a, const Plan& p) {
+    if (e != hipSuccess) return LR_ERR_HIP;
+    if (a.validate) {
+        uint32_t err = 0;
+        const Ctrl* c = reinterpret_cast<const Ctrl*>(a.ws + p.off_ctrl);
+        if (hipMemcpyAsync(&err, &c->err, 4, hipMemcpyDeviceToHost, a.stream) != hipSuccess) return LR_ERR_HIP;
+        if (hipStreamSynchronize(a.stream) != hipSuccess) return LR_ERR_HIP;
+        if (err) return LR_ERR_BAD_LIST;
+    }
+    return LR_OK;
+}
+
+static lr_status check_base_lds(const Plan& p) {
+    const uint64_t mL = p.m[p.levels];
+    if (base_lds_bytes(mL, p.weighted) > device_max_lds()) return LR_ERR_UNSUPPORTED;
+    return LR_OK;
+}
+
+static lr_status rank_common(const uint32_t* succ, const void* weight, int wt, bool weighted, int64_t* sum,
+                             uint32_t* rank, uint32_t* root, uint64_t n, void* ws, size_t ws_bytes,
+                             const lr_opts* opts, void* stream) {
+    Plan p;
+    lr_status s = make_plan(n, weighted, opts, 0, &p);
+    if (s != LR_OK) return s;
+    if (!ws || ws_bytes < p.total) return LR_ERR_WORKSPACE;
+    if ((s = check_base_lds(p)) != LR_OK) return s;
+    RunArgs a;
+    a.plan = &p;
+    a.succ = succ;
+    a.weight = weight;
+    a.wt = wt;
+    a.rank = rank;
+    a.root = root;
+    a.sum = sum;
+    a.ws = carve(ws);
+    a.stream = static_cast<hipStream_t>(stream);
+    a.validate = opts && (opts->flags & LR_VALIDATE);
+    a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
+    return finish(run_srs(a), a, p);
+}
+
+}  // namespace lr
+
+using namespace lr;
+
+extern "C" {
+
+const char* lr_status_string(lr_status s) {
+    switch (s) {
+        case LR_OK: return "LR_OK";
+        case LR_ERR_INVALID_ARG: return "LR_ERR_INVALID_ARG: null required pointer, bad enum or bad option";
+        case LR_ERR_UNSUPPORTED: return "LR_ERR_UNSUPPORTED: size or option beyond what the library or device supports";
+        case LR_ERR_WORKSPACE: return "LR_ERR_WORKSPACE: workspace missing or smaller than required";
+        case LR_ERR_OUT_OF_MEMORY: return "LR_ERR_OUT_OF_MEMORY: device allocation failed";
+        case LR_ERR_BAD_LIST: return "LR_ERR_BAD_LIST: input is not a forest of lists";
+        case LR_ERR_HIP: return "LR_ERR_HIP: a HIP runtime call failed";
+    }
+    return "unknown lr_status";
+}
+
+lr_status lr_plan_query(uint64_t n, lr_wtype w, const lr_opts* opts, lr_plan* out) {
+    if (!out) return LR_ERR_INVALID_ARG;
+    if (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64) return LR_ERR_INVALID_ARG;
+    Plan p;
+    lr_status s = make_plan(n, w != LR_W_NONE, opts, 0, &p);
+    if (s != LR_OK) return s;
+    memset(out, 0, sizeof(*out));
+    out->levels = p.levels;
+    out->base_max = p.base_max;
+    for (uint32_t l = 0; l <= p.levels; ++l) out->m[l] = p.m[l];
+    for (uint32_t l = 0; l < p.levels; ++l) out->spacing[l] = 1u << p.log2k[l];
+    out->workspace_bytes = p.total;
+    return LR_OK;
+}
+
+size_t lr_workspace_bytes(uint64_t n, lr_wtype w, const lr_opts* opts) {
+    if (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64) return 0;
+    Plan p;
+    if (make_plan(n, w != LR_W_NONE, opts, 0, &p) != LR_OK) return 0;
+    return p.total;
+}
+
+lr_status lr_rank(const uint32_t* succ, uint32_t* rank, uint32_t* root, uint64_t n, void* ws, size_t ws_bytes,
+                  const lr_opts* opts, void* stream) {
+    if (n == 0) return LR_OK;
+    if (!succ || !rank) return LR_ERR_INVALID_ARG;
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    return rank_common(succ, nullptr, 0, false, nullptr, rank, root, n, ws, ws_bytes, opts, stream);
+}
+
+lr_status lr_prefix_sum(const uint32_t* succ, const void* weight, lr_wtype w, int64_t* sum, uint32_t* rank,
+                        uint32_t* root, uint64_t n, void* ws, size_t ws_bytes, const lr_opts* opts, void* stream) {
+    if (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64) return LR_ERR_INVALID_ARG;
+    if (n == 0) return LR_OK;
+    if (!succ || !sum) return LR_ERR_INVALID_ARG;
+    if ((w == LR_W_NONE) != (weight == nullptr)) return LR_ERR_INVALID_ARG;
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    return rank_common(succ, weight, (int)w, true, sum, rank, root, n, ws, ws_bytes, opts, stream);
+}
+
+size_t lr_wyllie_workspace_bytes(uint64_t n, lr_wtype w) {
+    if (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64) return 0;
+    if (n >= (1ull << 31)) return 0;
+    const size_t rec = (w == LR_W_NONE) ? 8 : 16;
+    return 2 * align_up((size_t)n * rec + 16) + ALIGN;
+}
+
+static lr_status wyllie_common(const uint32_t* succ, const void* weight, lr_wtype w, bool weighted, int64_t* sum,
+                               uint32_t* rank, uint32_t* root, uint64_t n, void* ws, size_t ws_bytes, void* stream) {
+    const size_t need = lr_wyllie_workspace_bytes(n, weighted ? (w == LR_W_NONE ? LR_W_I64 : w) : LR_W_NONE);
+    if (!ws || ws_bytes < need) return LR_ERR_WORKSPACE;
+    RunArgs a;
+    a.succ = succ;
+    a.weight = weight;
+    a.wt = (int)w;
+    a.rank = rank;
+    a.root = root;
+    a.sum = sum;
+    a.ws = carve(ws);
+    a.stream = static_cast<hipStream_t>(stream);
+    return run_wyllie(a, n, weighted) == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
+lr_status lr_rank_wyllie(const uint32_t* succ, uint32_t* rank, uint32_t* root, uint64_t n, void* ws,
+                         size_t ws_bytes, void* stream) {
+    if (n == 0) return LR_OK;
+    if (!succ || !rank) return LR_ERR_INVALID_ARG;
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    return wyllie_common(succ, nullptr, LR_W_NONE, false, nullptr, rank, root, n, ws, ws_bytes, stream);
+}
+
+lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtype w, int64_t* sum, uint32_t* rank,
+                               uint32_t* root, uint64_t n, void* ws, size_t ws_bytes, void* stream) {
+    if (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64) return LR_ERR_INVALID_ARG;
+    if (n == 0) return LR_OK;
+    if (!succ || !sum) return LR_ERR_INVALID_ARG;
+    if ((w == LR_W_NONE) != (weight == nullptr)) return LR_ERR_INVALID_ARG;
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    return wyllie_common(succ, weight, w, true, sum, rank, root, n, ws, ws_bytes, stream);
+}
+
+size_t lr_batch_workspace_bytes(const lr_request* reqs, uint32_t count, const lr_opts* opts) {
+    if (!reqs && count) return 0;
+    uint64_t N = 0;
+    for (uint32_t i = 0; i < count; ++i) N += reqs[i].n;
+    Plan p;
+    if (make_plan(N, false, opts, std::max(count, 1u), &p) != LR_OK) return 0;
+    return p.total;
+}
+
+}  // extern "C"
+
+namespace lr {
+
+// Staging of the request table: a per-thread pinned host buffer; before it is
+// rewritten, the copy that last read it must have completed.
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    ~Staging() {
+        if (pending && done) (void)hipEventSynchronize(done);
+        if (host) (void)hipHostFree(host);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+static thread_local Staging g_stage;
+
+// Enqueue a batch whose request table is already built on the host.
+lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t ws_bytes, const lr_opts* opts,
+                        hipStream_t st, void* host_stage, size_t host_cap, hipEvent_t* copy_done);
+
+lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t ws_bytes, const lr_opts* opts,
+                        hipStream_t st, void* host_stage, size_t host_cap, hipEvent_t* copy_done) {
+    uint64_t N = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) return LR_ERR_INVALID_ARG;
+        N += reqs[i].n;
+    }
+    if (N >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    if (N == 0) return LR_OK;
+    Plan p;
+    lr_status s = make_plan(N, false, opts, count, &p);
+    if (s != LR_OK) return s;
+    if (!ws || ws_bytes < p.total) return LR_ERR_WORKSPACE;
+    if ((s = check_base_lds(p)) != LR_OK) return s;
+    const size_t desc_bytes = (size_t)count * sizeof(BatchDesc);
+    const size_t base_bytes = (size_t)(count + 1) * 4;
+    if (host_cap < desc_bytes + base_bytes) return LR_ERR_INVALID_ARG;
+    BatchDesc* hd = static_cast<BatchDesc*>(host_stage);
+    uint32_t* hb = reinterpret_cast<uint32_t*>(static_cast<char*>(host_stage) + desc_bytes);
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        hd[i] = BatchDesc{reqs[i].succ, reqs[i].rank, reqs[i].root, reqs[i].n};
+        hb[i] = acc;
+        acc += (uint32_t)reqs[i].n;
+    }
+    hb[count] = acc;
+    char* w = carve(ws);
+    BatchDesc* dd = reinterpret_cast<BatchDesc*>(w + p.off_batch_desc);
+    uint32_t* db = reinterpret_cast<uint32_t*>(w + p.off_batch_bases);
+    uint32_t* concat = reinterpret_cast<uint32_t*>(w + p.off_batch_succ);
+    if (hipMemcpyAsync(dd, hd, desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LR_ERR_HIP;
+    if (hipMemcpyAsync(db, hb, base_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LR_ERR_HIP;
+    if (copy_done && hipEventRecord(*copy_done, st) != hipSuccess) return LR_ERR_HIP;
+    if (run_batch_gather(dd, db, count, (uint32_t)N, concat, st) != hipSuccess) return LR_ERR_HIP;
+    RunArgs a;
+    a.plan = &p;
+    a.succ = concat;
+    a.desc = dd;
+    a.bases = db;
+    a.count = count;
+    a.ws = w;
+    a.stream = st;
+    a.validate = opts && (opts->flags & LR_VALIDATE);
+    a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
+    return finish(run_srs(a), a, p);
+}
+
+}  // namespace lr
+
+extern "C" lr_status lr_rank_batch(const lr_request* reqs, uint32_t count, void* ws, size_t ws_bytes,
+                                   const lr_opts* opts, void* stream) {
+    if (count == 0) return LR_OK;
+    if (!reqs) return LR_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < count; ++i)
+        if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) return LR_ERR_INVALID_ARG;
+    const size_t need = (size_t)count * sizeof(BatchDesc) + (size_t)(count + 1) * 4;
+    Staging& g = g_stage;
+    if (g.pending) {
+        if (hipEventSynchronize(g.done) != hipSuccess) return LR_ERR_HIP;
+        g.pending = false;
+    }
+    if (g.cap < need) {
+        if (g.host) (void)hipHostFree(g.host);
+        g.host = nullptr;
+        g.cap = 0;
+        if (hipHostMalloc(&g.host, need, hipHostMallocDefault) != hipSuccess) return LR_ERR_HIP;
+        g.cap = need;
+    }
+    if (!g.done && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return LR_ERR_HIP;
+    lr_status s = batch_enqueue(reqs, count, ws, ws_bytes, opts, static_cast<hipStream_t>(stream), g.host, g.cap,
+                                &g.done);
+    if (s == LR_OK) g.pending = true;
+    return s;
+}
+
+extern "C" int lr_profile_last(double* ms, int cap) {
+    if (!ms || cap <= 0 || !g_prof.valid) return 0;
+    for (auto& e : g_prof.ev)
+        if (hipEventSynchronize(e) != hipSuccess) return 0;
+    float v[EV_COUNT] = {};
+    for (int i = 1; i < EV_COUNT; ++i) (void)hipEventElapsedTime(&v[i], g_prof.ev[i - 1], g_prof.ev[i]);
+    float total = 0;
+    (void)hipEventElapsedTime(&total, g_prof.ev[0], g_prof.ev[EV_COUNT - 1]);
+    double out[6] = {v[EV_DETECT], v[EV_HEADS], v[EV_CHASE0], v[EV_UPPER], v[EV_EXPAND], total};
+    int k = std::min(cap, 6);
+    for (int i = 0; i < k; ++i) ms[i] = out[i];
+    return k;
+}

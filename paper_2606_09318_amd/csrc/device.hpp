@@ -1,0 +1,219 @@
+// Device-side building blocks of the sparse ruling-set list ranker (gfx950).
+//
+// Data layout per recursion level l (m_l elements, S_l = m_{l+1} rulers):
+//   slot_l[m_l]         walk id and offset of every element, written by the
+//                       chase (the element's position inside its walk)
+//   eb_l[S_l + m_l]     one record per walk. Entries [0, S_l) are the walks of
+//                       the sampled rulers; after the chase they hold the
+//                       elements of level l+1 (successor ruler + segment
+//                       weight), after level l+1 is solved they hold its
+//                       results (rank + root). Entries [S_l, ...) are the walks
+//                       of initial elements that are not rulers; the compaction
+//                       pass parks each such walk's start element in the entry's
+//                       first word, the chase replaces it by the walk's end and
+//                       weight, and the resolve pass by the walk's result.
+//   hp_l[m_l] (bytes)   "has a predecessor" marks, aliased onto slot_l: they
+//                       are read by the compaction pass before the chase of the
+//                       same level overwrites slot_l.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lr {
+
+constexpr uint32_t TERM = 0x80000000u;      // record flag: element is a terminal
+constexpr uint32_t IDX = 0x7fffffffu;       // payload bits (ids are < 2^31)
+constexpr uint32_t NONE = 0xffffffffu;
+constexpr int MAXL = 8;
+
+struct Ctrl {
+    struct Lv { uint32_t H, q; } lv[MAXL];  // per level: #initial-element walks, chase queue head
+    uint32_t err;                           // validation error bits
+    uint32_t pad[15];
+};
+
+// ---------------------------------------------------------------- values --
+// Unweighted levels carry a link count; weighted levels carry (count, sum).
+template <bool W> struct Lay;
+
+template <> struct Lay<false> {
+    struct Val { uint32_t c; };
+    struct alignas(8) Slot { uint32_t w, c; };
+    struct alignas(8) Rec { uint32_t nxt, c; };       // level element / walk end
+    struct alignas(8) Res { uint32_t c, root; };      // solved rank + terminal id
+    static __device__ __forceinline__ Val zero() { return {0u}; }
+    static __device__ __forceinline__ Val one_link(int64_t) { return {1u}; }
+    static __device__ __forceinline__ Val add(Val a, Val b) { return {a.c + b.c}; }
+    static __device__ __forceinline__ Val sub(Val a, Val b) { return {a.c - b.c}; }
+    static __device__ __forceinline__ Slot slot(uint32_t w, Val v) { return {w, v.c}; }
+    static __device__ __forceinline__ Val val(Slot s) { return {s.c}; }
+    static __device__ __forceinline__ Rec rec(uint32_t nxt, Val v) { return {nxt, v.c}; }
+    static __device__ __forceinline__ Val val(Rec r) { return {r.c}; }
+    static __device__ __forceinline__ Res res(Val v, uint32_t root) { return {v.c, root}; }
+    static __device__ __forceinline__ Val val(Res r) { return {r.c}; }
+    static __device__ __forceinline__ Val junk() { return {NONE}; }
+};
+
+template <> struct Lay<true> {
+    struct Val { uint32_t c; int64_t s; };
+    struct alignas(16) Slot { uint32_t w, c; int64_t s; };
+    struct alignas(16) Rec { uint32_t nxt, c; int64_t s; };
+    struct alignas(16) Res { uint32_t c, root; int64_t s; };
+    static __device__ __forceinline__ Val zero() { return {0u, 0}; }
+    static __device__ __forceinline__ Val one_link(int64_t w) { return {1u, w}; }
+    static __device__ __forceinline__ Val add(Val a, Val b) { return {a.c + b.c, a.s + b.s}; }
+    static __device__ __forceinline__ Val sub(Val a, Val b) { return {a.c - b.c, a.s - b.s}; }
+    static __device__ __forceinline__ Slot slot(uint32_t w, Val v) { return {w, v.c, v.s}; }
+    static __device__ __forceinline__ Val val(Slot s) { return {s.c, s.s}; }
+    static __device__ __forceinline__ Rec rec(uint32_t nxt, Val v) { return {nxt, v.c, v.s}; }
+    static __device__ __forceinline__ Val val(Rec r) { return {r.c, r.s}; }
+    static __device__ __forceinline__ Res res(Val v, uint32_t root) { return {v.c, root, v.s}; }
+    static __device__ __forceinline__ Val val(Res r) { return {r.c, r.s}; }
+    static __device__ __forceinline__ Val junk() { return {NONE, INT64_MIN}; }
+};
+
+// ------------------------------------------------------------ sampling --
+// Ruler sampling by strata: level l cuts its index range into blocks of
+// k = 2^log2k consecutive ids and makes exactly one element of every block a
+// ruler, at a position drawn by a hash of (level seed, block). This is the
+// per-PE quota of Section 2.1 (r/p rulers drawn locally) taken down to blocks
+// of k ids, so the ruler count of every level is exactly ceil(m / k), known
+// before the data is read, and the ruler of block c has compact id c.
+// Hash: "lowbias32" integer finaliser (C. Wellons, hash-prospector).
+__device__ __forceinline__ uint32_t hash32(uint32_t seed, uint32_t x) {
+    uint32_t h = (x * 0x9e3779b9u) ^ seed;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+
+struct Sampler {
+    uint32_t m, log2k, seed;
+    __device__ __forceinline__ uint32_t pos(uint32_t blk) const {
+        const uint32_t base = blk << log2k;
+        const uint32_t k = 1u << log2k;
+        const uint32_t len = (m - base < k) ? (m - base) : k;
+        const uint32_t h = hash32(seed, blk);
+        return (len == k) ? (h & (k - 1u)) : (h % len);
+    }
+    __device__ __forceinline__ bool sampled(uint32_t y) const {
+        const uint32_t blk = y >> log2k;
+        return (y - (blk << log2k)) == pos(blk);
+    }
+    __device__ __forceinline__ uint32_t start(uint32_t c) const { return (c << log2k) + pos(c); }
+};
+
+// --------------------------------------------------------------- sources --
+// A source yields, for element x of a level, its successor (TERM | terminal
+// id when x is a terminal) and its value: the link weight for a non-terminal,
+// the terminal's own weight for a terminal (0 on the input level).
+// Out-of-range successors are read as terminals, so no walk leaves the array.
+template <bool W, int WT>  // WT: 0 = every link weighs 1, 1 = int32 weights, 2 = int64 weights
+struct SrcIn {
+    const uint32_t* succ;
+    const void* weight;
+    uint32_t m;
+    using L = Lay<W>;
+    __device__ __forceinline__ void load(uint32_t x, uint32_t& nxt, typename L::Val& v) const {
+        const uint32_t s = succ[x];
+        int64_t w = 1;
+        if constexpr (WT == 1) w = static_cast<const int32_t*>(weight)[x];
+        if constexpr (WT == 2) w = static_cast<const int64_t*>(weight)[x];
+        const bool t = (s == x) | (s >= m);
+        nxt = t ? (TERM | x) : s;
+        v = t ? L::zero() : L::one_link(w);
+    }
+};
+
+template <bool W>
+struct SrcLvl {
+    const typename Lay<W>::Rec* e;
+    uint32_t m;
+    using L = Lay<W>;
+    __device__ __forceinline__ void load(uint32_t x, uint32_t& nxt, typename L::Val& v) const {
+        const typename L::Rec r = e[x];
+        nxt = r.nxt;
+        v = L::val(r);
+        if (!(nxt & TERM) && nxt >= m) { nxt = TERM | IDX; v = L::zero(); }
+    }
+};
+
+// --------------------------------------------------------------- outputs --
+// Outputs take (element, value, root). A cursor lets an output keep state
+// between consecutive elements of one lane (the batch output walks its
+// request table forward instead of searching it per element).
+template <bool W>
+struct OutUser {
+    uint32_t* rank;
+    uint32_t* root;
+    int64_t* sum;
+    using L = Lay<W>;
+    struct Cur {};
+    __device__ __forceinline__ Cur begin(uint32_t) const { return {}; }
+    __device__ __forceinline__ void store(Cur&, uint32_t i, typename L::Val v, uint32_t r) const {
+        if (rank) rank[i] = v.c;
+        if (root) root[i] = r;
+        if constexpr (W) { if (sum) sum[i] = v.s; }
+    }
+};
+
+template <bool W>
+struct OutLvl {
+    typename Lay<W>::Res* e;
+    using L = Lay<W>;
+    struct Cur {};
+    __device__ __forceinline__ Cur begin(uint32_t) const { return {}; }
+    __device__ __forceinline__ void store(Cur&, uint32_t i, typename L::Val v, uint32_t r) const {
+        e[i] = L::res(v, r);
+    }
+};
+
+// Batch request table in device memory: bases[q] is the first global id of
+// request q, bases[count] the total.
+struct BatchDesc {
+    const uint32_t* succ;
+    uint32_t* rank;
+    uint32_t* root;
+    uint64_t n;
+};
+
+__device__ __forceinline__ uint32_t batch_find(const uint32_t* bases, uint32_t count, uint32_t g) {
+    uint32_t lo = 0, hi = count;  // invariant: bases[lo] <= g < bases[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (bases[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+struct OutBatch {
+    const BatchDesc* d;
+    const uint32_t* bases;
+    uint32_t count;
+    using L = Lay<false>;
+    struct Cur { uint32_t q, lo, hi; };
+    __device__ __forceinline__ Cur begin(uint32_t g) const {
+        const uint32_t q = batch_find(bases, count, g);
+        return {q, bases[q], bases[q + 1]};
+    }
+    __device__ __forceinline__ void store(Cur& c, uint32_t g, L::Val v, uint32_t r) const {
+        while (g >= c.hi && c.q + 1 < count) { c.q++; c.lo = c.hi; c.hi = bases[c.q + 1]; }
+        const BatchDesc& q = d[c.q];
+        const uint32_t l = g - c.lo;
+        q.rank[l] = v.c;
+        if (q.root) q.root[l] = r - c.lo;
+    }
+};
+
+// ------------------------------------------------------------ wave utils --
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+}  // namespace lr

@@ -1,0 +1,748 @@
+// HIP kernels for gfx950 (wave64) and the launch sequences that chain them.
+//
+// Sparse ruling set (Section 2.1, Fig. 1), per level l of the recursion:
+//   detect   (level 0 only) mark every element that has a predecessor;
+//            unmarked elements are the initial elements (findInit).
+//   heads    compact the initial elements that are not sampled rulers into a
+//            walk list (tile count -> one-workgroup scan -> tile write).
+//   chase    one lane per walk: from its start, follow succ and record in
+//            slot[x] the walk id and the weight from the start to x, until the
+//            next sampled ruler or a terminal (the ruler chasing loop). The
+//            walk's end and total weight form the next level's element (for a
+//            sampled ruler) or a parked record (for an initial element).
+//   base     the last level (<= base_max elements) is ranked by pointer
+//            doubling in LDS by one workgroup (the base case).
+//   resolve  walks of initial elements take the result of the ruler (or
+//            terminal) they ended on.
+//   expand   every element takes rank = rank(walk) - offset and the walk's
+//            root (ruler propagation).
+// Walks run forward along succ, so ranks toward the terminal come out
+// directly and no list reversal is needed.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "device.hpp"
+#include "runner.hpp"
+
+namespace lr {
+
+constexpr int TPB = 256;
+constexpr int CHASE_TPB = 256;
+constexpr int BASE_TPB = 1024;
+constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
+constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
+
+// ------------------------------------------------------------------ fill --
+__global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n4 = words / 4;
+    uint4 v = make_uint4(val, val, val, val);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        reinterpret_cast<uint4*>(p)[i] = v;
+    for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = val;
+}
+
+// ---------------------------------------------------------------- detect --
+// hp[succ[i]] = 1 for every non-terminal i. In a forest each element has at
+// most one predecessor, so every byte has at most one writer and plain byte
+// stores suffice (no atomics, no cross-XCD coherence traffic).
+template <bool VEC>
+__global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ succ, uint32_t m,
+                                                uint8_t* __restrict__ hp) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t done = 0;
+    if constexpr (VEC) {
+        const uint32_t m4 = m / 4;
+        for (uint32_t i = g; i < m4; i += stride) {
+            const uint4 s = reinterpret_cast<const uint4*>(succ)[i];
+            const uint32_t x = 4 * i;
+            if (s.x != x && s.x < m) hp[s.x] = 1;
+            if (s.y != x + 1 && s.y < m) hp[s.y] = 1;
+            if (s.z != x + 2 && s.z < m) hp[s.z] = 1;
+            if (s.w != x + 3 && s.w < m) hp[s.w] = 1;
+        }
+        done = m4 * 4;
+    }
+    for (uint32_t i = done + g; i < m; i += stride) {
+        const uint32_t s = succ[i];
+        if (s != i && s < m) hp[s] = 1;
+    }
+}
+
+// Validation: counts[s]++ per link (counts zeroed before); any element with
+// two predecessors or an out-of-range successor sets an error bit.
+__global__ __launch_bounds__(TPB) void k_validate_in(const uint32_t* __restrict__ succ, uint32_t m,
+                                                     uint32_t* __restrict__ counts, uint32_t* err) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const uint32_t s = succ[i];
+        if (s >= m) { atomicOr(err, 1u); continue; }
+        if (s != i && atomicAdd(&counts[s], 1u) != 0) atomicOr(err, 2u);
+    }
+}
+
+// ----------------------------------------------------------------- heads --
+// A tile of TILE elements per block: each lane owns 16 consecutive bytes of
+// the hp bytemap. An element starts a walk of its own when it has no
+// predecessor and is not the sampled ruler of its block.
+__device__ __forceinline__ uint32_t tile_heads(const uint8_t* __restrict__ hp, const Sampler& smp, uint32_t x0,
+                                               uint32_t& bits) {
+    bits = 0;
+    const uint32_t m = smp.m;
+    if (x0 >= m) return 0;
+    uint8_t b[16];
+    if (x0 + 16 <= m) {
+        const uint4 v = *reinterpret_cast<const uint4*>(hp + x0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 16; ++j) b[j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) b[j] = (x0 + j < m) ? hp[x0 + j] : 1;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t x = x0 + j;
+        if (b[j] == 0 && x < m && !smp.sampled(x)) bits |= 1u << j;
+    }
+    return __popc(bits);
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const uint32_t wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[wv] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (uint32_t i = 0; i < blockDim.x / 64; ++i) t += sh[i];
+    return t;
+}
+
+// Exclusive block scan (all lanes get their prefix; *total = block sum).
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* sh, uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= (uint32_t)o) inc += y;
+    }
+    if (lane == 63) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    const uint32_t nw = blockDim.x / 64;
+    for (uint32_t i = 0; i < nw; ++i) {
+        const uint32_t s = sh[i];
+        if (i < wv) before += s;
+        all += s;
+    }
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__ hp, Sampler smp,
+                                                     uint32_t* __restrict__ tilecnt, uint32_t* zero_p,
+                                                     uint32_t zero_words) {
+    __shared__ uint32_t sh[TPB / 64];
+    const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
+    uint32_t bits;
+    const uint32_t c = tile_heads(hp, smp, x0, bits);
+    const uint32_t t = block_sum(c, sh);
+    if (threadIdx.x == 0) tilecnt[blockIdx.x] = t;
+    // clear the next level's predecessor marks (free memory at this point)
+    if (zero_p) {
+        const uint32_t stride = gridDim.x * blockDim.x;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < zero_words; i += stride) zero_p[i] = 0;
+    }
+}
+
+// One workgroup: exclusive scan of the tile counts in place; publishes the
+// walk count and resets the chase queue of this level.
+__global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles,
+                                                     Ctrl* ctrl, int lvl) {
+    __shared__ uint32_t sh[1024 / 64];
+    const uint32_t per = (ntiles + blockDim.x - 1) / blockDim.x;
+    const uint32_t a = threadIdx.x * per;
+    const uint32_t b = min(a + per, ntiles);
+    uint32_t s = 0;
+    for (uint32_t i = a; i < b; ++i) s += tilecnt[i];
+    uint32_t total;
+    uint32_t run = block_exscan(s, sh, &total);
+    for (uint32_t i = a; i < b; ++i) {
+        const uint32_t v = tilecnt[i];
+        tilecnt[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        ctrl->lv[lvl].H = total;
+        ctrl->lv[lvl].q = 0;
+    }
+}
+
+// Writes walk start j into the first word of walk record S + j.
+__global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__ hp, Sampler smp,
+                                                     const uint32_t* __restrict__ tileoff, char* __restrict__ eb,
+                                                     uint32_t S, uint32_t rec_bytes) {
+    __shared__ uint32_t sh[TPB / 64];
+    const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
+    uint32_t bits;
+    const uint32_t c = tile_heads(hp, smp, x0, bits);
+    uint32_t total;
+    uint32_t pos = tileoff[blockIdx.x] + block_exscan(c, sh, &total);
+    while (bits) {
+        const int j = __ffs(bits) - 1;
+        bits &= bits - 1;
+        *reinterpret_cast<uint32_t*>(eb + (size_t)(S + pos) * rec_bytes) = x0 + j;
+        ++pos;
+    }
+}
+
+// ----------------------------------------------------------------- chase --
+// Persistent kernel: each lane holds one walk; a wavefront refills its idle
+// lanes from the level's walk queue with a single atomic (ballot + mbcnt
+// hand out consecutive walk ids) once `refill` lanes are idle. Each step is
+// one dependent gather (the record of x), one store (slot[x]) and a few ALU
+// operations for the ruler test, so the loop is bound by memory latency and
+// the lanes resident on the chip keep that many gathers in flight.
+template <bool W, class Src>
+__global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint32_t S, Ctrl* ctrl, int lvl,
+                                                     typename Lay<W>::Slot* __restrict__ slot,
+                                                     typename Lay<W>::Rec* __restrict__ eb,
+                                                     uint8_t* __restrict__ hp_next, uint32_t refill) {
+    using L = Lay<W>;
+    using Val = typename L::Val;
+    const uint32_t lane = lane_id();
+    const uint32_t total = S + ctrl->lv[lvl].H;
+    const uint32_t m = smp.m;
+    uint32_t w = NONE, x = 0, steps = 0;
+    Val off = L::zero();
+    bool exhausted = false;
+    for (;;) {
+        const uint64_t idle = __ballot(w == NONE);
+        if (idle == ~0ull && exhausted) break;
+        const uint32_t nidle = __popcll(idle);
+        if (!exhausted && (nidle >= refill || idle == ~0ull)) {
+            const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&ctrl->lv[lvl].q, nidle);
+            base = __shfl(base, leader);
+            if (base + nidle >= total) exhausted = true;
+            if (w == NONE) {
+                const uint32_t my = base + mbcnt(idle);
+                if (my < total) {
+                    w = my;
+                    off = L::zero();
+                    steps = 0;
+                    x = (my < S) ? smp.start(my) : reinterpret_cast<const uint32_t*>(eb + my)[0];
+                    if (x >= m) {  // corrupt start (cannot happen for valid input)
+                        eb[w] = L::rec(TERM | IDX, L::zero());
+                        atomicOr(&ctrl->err, 8u);
+                        w = NONE;
+                    }
+                }
+            }
+        }
+        if (w != NONE) {
+            uint32_t nxt;
+            Val v;
+            src.load(x, nxt, v);
+            slot[x] = L::slot(w, off);
+            if (nxt & TERM) {                       // x is a terminal: the walk ends on it
+                eb[w] = L::rec(nxt, L::add(off, v));
+                w = NONE;
+            } else {
+                off = L::add(off, v);
+                if (++steps >= m) {                 // longer than the level: input has a cycle
+                    eb[w] = L::rec(TERM | IDX, off);
+                    atomicOr(&ctrl->err, 8u);
+                    w = NONE;
+                } else if (smp.sampled(nxt)) {      // reached the next ruler
+                    const uint32_t c = nxt >> smp.log2k;
+                    eb[w] = L::rec(c, off);
+                    if (hp_next && w < S) hp_next[c] = 1;
+                    w = NONE;
+                } else {
+                    x = nxt;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ base --
+// Pointer doubling (Wyllie) on <= 16384 elements in LDS by one workgroup.
+// d[i] is the weight from i up to (not including) f[i]; terminals point to
+// themselves with d = 0, so a round d[i] += d[f[i]], f[i] = f[f[i]] leaves
+// them fixed, and after ceil(log2 len) rounds f[i] is i's terminal. The
+// result adds the terminal's own value (its weight at this level).
+template <bool W, class Src, class Out>
+__global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m, Ctrl* ctrl) {
+    using L = Lay<W>;
+    using Val = typename L::Val;
+    extern __shared__ __align__(16) unsigned char lds[];
+    int64_t* ds = reinterpret_cast<int64_t*>(lds);
+    uint32_t* dc = reinterpret_cast<uint32_t*>(lds + (W ? 8 * (size_t)m : 0));
+    uint16_t* f = reinterpret_cast<uint16_t*>(lds + (W ? 8 * (size_t)m : 0) + 4 * (size_t)m);
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < m; i += BASE_TPB) {
+        uint32_t nxt;
+        Val v;
+        src.load(i, nxt, v);
+        const bool term = (nxt & TERM) || nxt >= m;
+        f[i] = (uint16_t)(term ? i : nxt);
+        dc[i] = term ? 0u : v.c;
+        if constexpr (W) ds[i] = term ? 0 : v.s;
+    }
+    __syncthreads();
+    for (int round = 0; round < 40; ++round) {
+        uint16_t ff[BASE_PER];
+        uint32_t fc[BASE_PER];
+        int64_t fs[BASE_PER];
+        int changed = 0;
+#pragma unroll
+        for (int j = 0; j < BASE_PER; ++j) {
+            const uint32_t i = t + j * BASE_TPB;
+            if (i < m) {
+                const uint32_t fi = f[i];
+                ff[j] = f[fi];
+                fc[j] = dc[fi];
+                if constexpr (W) fs[j] = ds[fi];
+                changed |= (ff[j] != fi);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < BASE_PER; ++j) {
+            const uint32_t i = t + j * BASE_TPB;
+            if (i < m) {
+                f[i] = ff[j];
+                dc[i] += fc[j];
+                if constexpr (W) ds[i] += fs[j];
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    Val rv[BASE_PER];
+    uint32_t rr[BASE_PER];
+#pragma unroll
+    for (int j = 0; j < BASE_PER; ++j) {
+        const uint32_t i = t + j * BASE_TPB;
+        if (i < m) {
+            const uint32_t ti = f[i];
+            uint32_t nxt;
+            Val v;
+            src.load(ti, nxt, v);
+            Val d;
+            d.c = dc[i];
+            if constexpr (W) d.s = ds[i];
+            if (nxt & TERM) {
+                rv[j] = L::add(d, v);
+                rr[j] = nxt & IDX;
+            } else {  // never reached a terminal: the input has a cycle
+                rv[j] = L::junk();
+                rr[j] = NONE;
+                atomicOr(&ctrl->err, 16u);
+            }
+        }
+    }
+    __syncthreads();  // every read of the level's records happens before any in-place write
+#pragma unroll
+    for (int j = 0; j < BASE_PER; ++j) {
+        const uint32_t i = t + j * BASE_TPB;
+        if (i < m) {
+            auto cur = out.begin(i);
+            out.store(cur, i, rv[j], rr[j]);
+        }
+    }
+}
+
+// --------------------------------------------------------------- resolve --
+// Walk S + j of an initial element: its result is its own weight plus the
+// result of the ruler it ended on, or plus nothing when it ended on a
+// terminal (whose weight the chase already added).
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_resolve(char* __restrict__ eb_raw, uint32_t S, const Ctrl* ctrl, int lvl) {
+    using L = Lay<W>;
+    auto* rec = reinterpret_cast<typename L::Rec*>(eb_raw);
+    auto* res = reinterpret_cast<typename L::Res*>(eb_raw);
+    const uint32_t H = ctrl->lv[lvl].H;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < H; j += stride) {
+        const typename L::Rec r = rec[S + j];
+        typename L::Res o;
+        if (r.nxt & TERM) {
+            o = L::res(L::val(r), r.nxt & IDX);
+        } else if (r.nxt < S) {
+            const typename L::Res b = res[r.nxt];
+            o = L::res(L::add(L::val(r), L::val(b)), b.root);
+        } else {
+            o = L::res(L::junk(), NONE);
+        }
+        res[S + j] = o;
+    }
+}
+
+// ---------------------------------------------------------------- expand --
+// rank(x) = result(walk(x)) - offset(x); root(x) = root(walk(x)).
+// Wave tiles of 64 * EXPAND_CH elements, lane-strided (coalesced slot reads
+// and output writes); the result gather hits the small per-walk table.
+template <bool W, class Out>
+__global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __restrict__ slot, uint32_t m,
+                                                const typename Lay<W>::Res* __restrict__ res, uint32_t S,
+                                                Ctrl* ctrl, int lvl, Out out) {
+    using L = Lay<W>;
+    const uint32_t nw = S + ctrl->lv[lvl].H;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t ntile = (m + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
+    for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
+        const uint32_t base = tile * 64 * EXPAND_CH;
+        if (base + lane >= m) continue;
+        auto cur = out.begin(base + lane);
+        typename L::Slot sv[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            if (i < m) sv[j] = slot[i];
+        }
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            if (i < m) {
+                const typename L::Slot s = sv[j];
+                if (s.w < nw) {
+                    const typename L::Res b = res[s.w];
+                    out.store(cur, i, L::sub(L::val(b), L::val(s)), b.root);
+                } else {
+                    atomicOr(&ctrl->err, 4u);
+                    out.store(cur, i, L::junk(), NONE);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Wyllie --
+template <bool W, class Src>
+__global__ __launch_bounds__(TPB) void k_wy_init(Src src, typename Lay<W>::Rec* __restrict__ a, uint32_t m) {
+    using L = Lay<W>;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        uint32_t nxt;
+        typename L::Val v;
+        src.load(i, nxt, v);
+        a[i] = (nxt & TERM) ? L::rec(i, L::zero()) : L::rec(nxt, v);
+    }
+}
+
+// One doubling round: d[i] += d[f[i]]; f[i] = f[f[i]] (ping-pong buffers).
+// The last round writes the outputs instead (terminal weight is 0 here).
+template <bool W, bool LAST>
+__global__ __launch_bounds__(TPB) void k_wy_round(const typename Lay<W>::Rec* __restrict__ a,
+                                                  typename Lay<W>::Rec* __restrict__ b, uint32_t m,
+                                                  OutUser<W> out) {
+    using L = Lay<W>;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const typename L::Rec r = a[i];
+        const typename L::Rec q = a[r.nxt];
+        const typename L::Val d = L::add(L::val(r), L::val(q));
+        if constexpr (LAST) {
+            typename OutUser<W>::Cur c;
+            out.store(c, i, d, q.nxt);
+        } else {
+            b[i] = L::rec(q.nxt, d);
+        }
+    }
+}
+
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_wy_copy(const typename Lay<W>::Rec* __restrict__ a, uint32_t m,
+                                                 OutUser<W> out) {
+    using L = Lay<W>;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const typename L::Rec r = a[i];
+        typename OutUser<W>::Cur c;
+        out.store(c, i, L::val(r), r.nxt);
+    }
+}
+
+// ----------------------------------------------------------------- batch --
+// concat[g] = base(q) + succ_q[g - base(q)] for the request q owning g;
+// out-of-range successors become terminals (no list leaves its request).
+__global__ __launch_bounds__(TPB) void k_batch_gather(const BatchDesc* __restrict__ d,
+                                                      const uint32_t* __restrict__ bases, uint32_t count,
+                                                      uint32_t total, uint32_t* __restrict__ concat) {
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t ntile = (total + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
+    for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
+        const uint32_t base = tile * 64 * EXPAND_CH;
+        if (base + lane >= total) continue;
+        uint32_t q = batch_find(bases, count, base + lane);
+        uint32_t lo = bases[q], hi = bases[q + 1];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t g = base + j * 64 + lane;
+            if (g < total) {
+                while (g >= hi && q + 1 < count) { ++q; lo = hi; hi = bases[q + 1]; }
+                const uint32_t l = g - lo;
+                const uint32_t s = d[q].succ[l];
+                concat[g] = (s < hi - lo) ? lo + s : g;
+            }
+        }
+    }
+}
+
+// ============================================================== host side ==
+
+static int g_cus = 0;
+static size_t g_lds = 0;
+
+int device_cus() {
+    if (!g_cus) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            g_cus = v;
+        else
+            g_cus = 256;
+    }
+    return g_cus;
+}
+
+size_t device_max_lds() {
+    if (!g_lds) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            g_lds = (size_t)v;
+        else
+            g_lds = 65536;
+    }
+    return g_lds;
+}
+
+static inline uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap_per_cu = 8) {
+    uint64_t g = (work + per_block - 1) / per_block;
+    const uint64_t cap = (uint64_t)device_cus() * cap_per_cu;
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return (uint32_t)g;
+}
+
+template <class K>
+static uint32_t persistent_grid(K kernel, int tpb) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, tpb, 0) != hipSuccess || nb <= 0) nb = 4;
+    return (uint32_t)nb * (uint32_t)device_cus();
+}
+
+static hipError_t fill(void* p, uint64_t bytes, uint32_t val, hipStream_t st) {
+    const uint64_t words = (bytes + 3) / 4;
+    if (!words) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(words, TPB * 4)), dim3(TPB), 0, st, (uint32_t*)p, words, val);
+    return hipGetLastError();
+}
+
+static inline void rec_ev(const RunArgs& a, int i) {
+    if (a.ev) (void)hipEventRecord(a.ev[i], a.stream);
+}
+
+template <bool W, class Src, class Out>
+static hipError_t launch_base(Src src, Out out, uint32_t m, Ctrl* ctrl, hipStream_t st) {
+    const size_t lds = base_lds_bytes(m, W);
+    auto kern = k_base<W, Src, Out>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(1), dim3(BASE_TPB), lds, st, src, out, m, ctrl);
+    return hipGetLastError();
+}
+
+template <bool W, class Src>
+static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st) {
+    using L = Lay<W>;
+    auto kern = k_chase<W, Src>;
+    static uint32_t grid = 0;  // one per template instance
+    if (!grid) grid = persistent_grid(kern, CHASE_TPB);
+    const uint32_t S = (uint32_t)p.m[l + 1];
+    auto* slot = reinterpret_cast<typename L::Slot*>(ws + p.off_slot[l]);
+    auto* eb = reinterpret_cast<typename L::Rec*>(ws + p.off_eb[l]);
+    uint8_t* hp_next = (l + 1 < (int)p.levels) ? reinterpret_cast<uint8_t*>(ws + p.off_slot[l + 1]) : nullptr;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(CHASE_TPB), 0, st, src, smp, S, ctrl, l, slot, eb, hp_next,
+                       p.refill);
+    return hipGetLastError();
+}
+
+#define LR_TRY(x)                              \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+
+template <bool W, int WT, class Out0>
+static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
+    using L = Lay<W>;
+    const Plan& p = *a.plan;
+    char* ws = a.ws;
+    hipStream_t st = a.stream;
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
+    const uint32_t n = (uint32_t)p.m[0];
+    SrcIn<W, WT> src0{a.succ, a.weight, n};
+    rec_ev(a, EV_START);
+    if (a.validate) {
+        LR_TRY(fill(ctrl, sizeof(Ctrl), 0u, st));
+        uint32_t* counts = reinterpret_cast<uint32_t*>(ws + p.off_slot[0]);
+        LR_TRY(fill(counts, (uint64_t)n * 4, 0u, st));
+        LR_TRY(run_validate_input(a.succ, n, counts, &ctrl->err, st));
+    }
+    if (p.levels == 0) {
+        LR_TRY((launch_base<W>(src0, out0, n, ctrl, st)));
+        for (int i = EV_DETECT; i < EV_COUNT; ++i) rec_ev(a, i);
+        return hipSuccess;
+    }
+    // level 0: predecessor marks
+    uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
+    LR_TRY(fill(hp0, n, 0u, st));
+    {
+        const bool vec = ((uintptr_t)a.succ % 16) == 0;
+        const uint32_t g = grid_for(n, TPB * 4 * 4);
+        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0);
+        else hipLaunchKernelGGL(k_detect<false>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0);
+        LR_TRY(hipGetLastError());
+    }
+    rec_ev(a, EV_DETECT);
+    for (uint32_t l = 0; l < p.levels; ++l) {
+        const uint32_t m = (uint32_t)p.m[l];
+        const uint32_t S = (uint32_t)p.m[l + 1];
+        const Sampler smp{m, p.log2k[l], p.lseed[l]};
+        const uint8_t* hp = reinterpret_cast<const uint8_t*>(ws + p.off_slot[l]);
+        uint32_t* tile = reinterpret_cast<uint32_t*>(ws + p.off_tile[l]);
+        const bool more = l + 1 < p.levels;
+        uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
+        const uint32_t zw = more ? (S + 3) / 4 : 0;
+        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
+                           (uint32_t)p.rec_bytes);
+        LR_TRY(hipGetLastError());
+        if (a.validate) LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st));
+        if (l == 0) rec_ev(a, EV_HEADS);
+        if (l == 0) {
+            LR_TRY((launch_chase<W>(p, 0, src0, smp, ctrl, ws, st)));
+            rec_ev(a, EV_CHASE0);
+        } else {
+            SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]), m};
+            LR_TRY((launch_chase<W>(p, (int)l, src, smp, ctrl, ws, st)));
+        }
+    }
+    {
+        const uint32_t L_ = p.levels;
+        const uint32_t mL = (uint32_t)p.m[L_];
+        SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[L_ - 1]), mL};
+        OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[L_ - 1])};
+        LR_TRY((launch_base<W>(src, out, mL, ctrl, st)));
+    }
+    rec_ev(a, EV_UPPER);
+    for (int l = (int)p.levels - 1; l >= 0; --l) {
+        const uint32_t m = (uint32_t)p.m[l];
+        const uint32_t S = (uint32_t)p.m[l + 1];
+        hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
+                           ctrl, l);
+        LR_TRY(hipGetLastError());
+        const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
+        const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
+        const uint32_t g = grid_for(m, TPB * EXPAND_CH);
+        if (l == 0) {
+            hipLaunchKernelGGL((k_expand<W, Out0>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0);
+        } else {
+            OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1])};
+            hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, l,
+                               out);
+        }
+        LR_TRY(hipGetLastError());
+    }
+    rec_ev(a, EV_EXPAND);
+    return hipSuccess;
+}
+
+hipError_t run_srs(const RunArgs& a) {
+    const Plan& p = *a.plan;
+    if (a.desc) {
+        OutBatch out{a.desc, a.bases, a.count};
+        return run_srs_t<false, 0>(a, out);
+    }
+    if (!p.weighted) return run_srs_t<false, 0>(a, OutUser<false>{a.rank, a.root, nullptr});
+    OutUser<true> out{a.rank, a.root, a.sum};
+    switch (a.wt) {
+        case 1: return run_srs_t<true, 1>(a, out);
+        case 2: return run_srs_t<true, 2>(a, out);
+        default: return run_srs_t<true, 0>(a, out);
+    }
+}
+
+template <bool W, int WT>
+static hipError_t run_wyllie_t(const RunArgs& a, uint64_t n64) {
+    using L = Lay<W>;
+    const uint32_t n = (uint32_t)n64;
+    auto* A = reinterpret_cast<typename L::Rec*>(a.ws);
+    auto* B = reinterpret_cast<typename L::Rec*>(a.ws + ((n64 * sizeof(typename L::Rec) + ALIGN - 1) / ALIGN) * ALIGN);
+    OutUser<W> out{a.rank, a.root, W ? a.sum : nullptr};
+    const uint32_t g = grid_for(n, TPB * 4);
+    SrcIn<W, WT> src{a.succ, a.weight, n};
+    rec_ev(a, EV_START);
+    hipLaunchKernelGGL((k_wy_init<W, SrcIn<W, WT>>), dim3(g), dim3(TPB), 0, a.stream, src, A, n);
+    LR_TRY(hipGetLastError());
+    uint32_t rounds = 0;
+    while ((1ull << rounds) < n64) ++rounds;
+    if (rounds == 0) {
+        hipLaunchKernelGGL(k_wy_copy<W>, dim3(g), dim3(TPB), 0, a.stream, A, n, out);
+        LR_TRY(hipGetLastError());
+    }
+    for (uint32_t r = 0; r < rounds; ++r) {
+        if (r + 1 == rounds)
+            hipLaunchKernelGGL((k_wy_round<W, true>), dim3(g), dim3(TPB), 0, a.stream, A, B, n, out);
+        else
+            hipLaunchKernelGGL((k_wy_round<W, false>), dim3(g), dim3(TPB), 0, a.stream, A, B, n, out);
+        LR_TRY(hipGetLastError());
+        std::swap(A, B);
+    }
+    for (int i = EV_DETECT; i < EV_COUNT; ++i) rec_ev(a, i);
+    return hipSuccess;
+}
+
+hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted) {
+    if (!weighted) return run_wyllie_t<false, 0>(a, n);
+    switch (a.wt) {
+        case 1: return run_wyllie_t<true, 1>(a, n);
+        case 2: return run_wyllie_t<true, 2>(a, n);
+        default: return run_wyllie_t<true, 0>(a, n);
+    }
+}
+
+hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, uint32_t count, uint32_t total,
+                            uint32_t* concat, hipStream_t st) {
+    if (!total) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(total, TPB * EXPAND_CH)), dim3(TPB), 0, st, desc, bases, count,
+                       total, concat);
+    return hipGetLastError();
+}
+
+hipError_t run_validate_input(const uint32_t* succ, uint32_t n, uint32_t* counts, uint32_t* err, hipStream_t st) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_validate_in, dim3(grid_for(n, TPB * 4)), dim3(TPB), 0, st, succ, n, counts, err);
+    return hipGetLastError();
+}
+
+}  // namespace lr

@@ -1,0 +1,50 @@
+// Host entry points into the kernel sequences (defined in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.hpp"
+
+namespace lr {
+
+struct BatchDesc;
+
+enum { EV_START, EV_DETECT, EV_HEADS, EV_CHASE0, EV_UPPER, EV_EXPAND, EV_COUNT };
+
+struct RunArgs {
+    const Plan* plan = nullptr;
+    const uint32_t* succ = nullptr;   // level-0 successor array (user's, or the batch concatenation)
+    const void* weight = nullptr;
+    int wt = 0;                       // 0: unit links, 1: int32, 2: int64
+    uint32_t* rank = nullptr;
+    uint32_t* root = nullptr;
+    int64_t* sum = nullptr;
+    // batch outputs (rank/root per request) instead of rank/root above
+    const BatchDesc* desc = nullptr;
+    const uint32_t* bases = nullptr;
+    uint32_t count = 0;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool validate = false;
+    hipEvent_t* ev = nullptr;         // EV_COUNT events to record, or null
+};
+
+// Sparse ruling-set ranking over the whole plan. Enqueues only.
+hipError_t run_srs(const RunArgs& a);
+
+// Wyllie pointer doubling baseline; ws holds two ping-pong record arrays.
+hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted);
+
+// Batch staging: copy the requests' successor arrays into one forest over the
+// concatenated id range (ids shifted by the request's base).
+hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, uint32_t count, uint32_t total,
+                            uint32_t* concat, hipStream_t st);
+
+// Validation pass before ranking: range and in-degree check on the input.
+hipError_t run_validate_input(const uint32_t* succ, uint32_t n, uint32_t* counts, uint32_t* err,
+                              hipStream_t st);
+
+int device_cus();
+size_t device_max_lds();
+
+}  // namespace lr

@@ -1,0 +1,105 @@
+"""The C ABI library loads on a machine without a GPU, exports every function
+include/lr.h declares, and answers its host-only queries and argument checks
+(no call here reaches a kernel)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2606_09318_amd as lr
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "lr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lr_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = lr.load()
+    names = declared_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for s in range(7):
+        assert lr.status_string(s).startswith("LR_")
+
+
+def test_plan_levels_and_sizes():
+    p = lr.lr_plan_query(1 << 28)
+    assert p.levels >= 2
+    assert p.m[0] == 1 << 28
+    for l in range(p.levels):
+        k = p.spacing[l]
+        assert k & (k - 1) == 0 and 2 <= k <= 4096
+        assert p.m[l + 1] == -(-p.m[l] // k)
+    assert p.m[p.levels] <= p.base_max
+    small = lr.lr_plan_query(5000)
+    assert small.levels == 0
+
+
+def test_plan_honours_spacing_and_base():
+    o = lr.make_opts(spacing=(4, 2), base_max=16)
+    p = lr.lr_plan_query(1000, lr.LR_W_NONE, o)
+    assert [p.spacing[i] for i in range(p.levels)][:2] == [4, 2]
+    assert p.m[1] == 250 and p.m[2] == 125
+    assert p.m[p.levels] <= 16
+    with pytest.raises(lr.LrError):
+        lr.lr_plan_query(1000, lr.LR_W_NONE, lr.make_opts(spacing=(3,)))
+    with pytest.raises(lr.LrError):
+        lr.lr_plan_query(1000, lr.LR_W_NONE, lr.make_opts(base_max=1 << 20))
+
+
+def test_workspace_monotone_and_weighted_larger():
+    prev = 0
+    for e in range(0, 31):
+        b = lr.lr_workspace_bytes((1 << e) + 3 if e < 30 else (1 << 31) - 1)
+        assert b >= prev
+        prev = b
+    assert lr.lr_workspace_bytes(1 << 31) == 0
+    assert lr.lr_workspace_bytes(1 << 20, lr.LR_W_I64) > lr.lr_workspace_bytes(1 << 20)
+    assert lr.lr_workspace_bytes(1 << 20, lr.LR_W_I32) == lr.lr_workspace_bytes(1 << 20, lr.LR_W_I64)
+    assert lr.lr_workspace_bytes(10, 7) == 0
+    assert lr.lr_wyllie_workspace_bytes(1 << 20) >= 2 * 8 * (1 << 20)
+
+
+def test_argument_errors_before_any_device_work():
+    L = lr.load()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    assert L.lr_rank(None, fake, None, 0, None, 0, None, None) == lr.LR_OK          # n == 0: no-op
+    assert L.lr_rank(None, fake, None, 10, fake, 1 << 20, None, None) == lr.LR_ERR_INVALID_ARG
+    assert L.lr_rank(fake, None, None, 10, fake, 1 << 20, None, None) == lr.LR_ERR_INVALID_ARG
+    assert L.lr_rank(fake, fake, None, 1 << 31, fake, 1 << 20, None, None) == lr.LR_ERR_UNSUPPORTED
+    assert L.lr_rank(fake, fake, None, 100000, fake, 16, None, None) == lr.LR_ERR_WORKSPACE
+    assert L.lr_rank(fake, fake, None, 100000, None, 1 << 30, None, None) == lr.LR_ERR_WORKSPACE
+    assert L.lr_prefix_sum(fake, None, 1, fake, None, None, 10, fake, 1 << 20, None, None) == lr.LR_ERR_INVALID_ARG
+    assert L.lr_prefix_sum(fake, fake, 9, fake, None, None, 10, fake, 1 << 20, None, None) == lr.LR_ERR_INVALID_ARG
+    assert L.lr_prefix_sum(fake, fake, 2, None, None, None, 10, fake, 1 << 20, None, None) == lr.LR_ERR_INVALID_ARG
+    bad = lr.make_opts(spacing=(5,))
+    assert L.lr_rank(fake, fake, None, 100000, fake, 1 << 30, ctypes.byref(bad), None) == lr.LR_ERR_INVALID_ARG
+    assert L.lr_rank_wyllie(fake, fake, None, 1000, fake, 8, None) == lr.LR_ERR_WORKSPACE
+    reqs = (lr.lr_request * 2)()
+    reqs[0].succ, reqs[0].rank, reqs[0].n = 0x1000, None, 5
+    assert L.lr_rank_batch(reqs, 2, fake, 1 << 20, None, None) == lr.LR_ERR_INVALID_ARG
+    assert L.lr_rank_batch(None, 0, None, 0, None, None) == lr.LR_OK
+    cfg = lr.lr_server_config()
+    out = ctypes.c_void_p()
+    assert L.lr_server_create(ctypes.byref(cfg), ctypes.byref(out)) == lr.LR_ERR_INVALID_ARG
+
+
+def test_batch_workspace_counts_all_requests():
+    reqs = (lr.lr_request * 3)()
+    for i, n in enumerate((1000, 20000, 300000)):
+        reqs[i].succ, reqs[i].rank, reqs[i].n = 0x1000, 0x2000, n
+    b3 = lr.lr_batch_workspace_bytes(reqs, 3)
+    b1 = lr.lr_batch_workspace_bytes(reqs, 1)
+    assert b3 > b1 > 0
+    assert b3 >= lr.lr_workspace_bytes(321000)

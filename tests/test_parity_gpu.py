@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element
+by element, bit-exact (all outputs are integers, tolerance 0)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2606_09318_amd as lr
+import workloads
+from gpu_util import gpu_prefix, gpu_rank, gpu_wyllie
+
+pytestmark = pytest.mark.gpu
+
+
+def check_rank(succ, opts=None):
+    st, r, t = gpu_rank(succ, opts)
+    assert st == lr.LR_OK, lr.status_string(st)
+    ost, er, et, _ = oracle.rank(succ)
+    assert ost == oracle.OK
+    assert np.array_equal(r, er), f"rank mismatch at {np.nonzero(r != er)[0][:10]}"
+    assert np.array_equal(t, et), f"root mismatch at {np.nonzero(t != et)[0][:10]}"
+
+
+def test_random_list_2p20():
+    """Single random list of 2^20 elements (the small configuration)."""
+    print("case: random list n=2^20 seed=1", flush=True)
+    check_rank(workloads.random_list(1 << 20, seed=1).succ)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 17, 63, 64, 65, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
+                               12345, 65537, 100003, 1 << 18])
+def test_random_list_sizes(n):
+    print(f"case: random list n={n}", flush=True)
+    check_rank(workloads.random_list(n, seed=100 + n).succ)
+
+
+@pytest.mark.parametrize("k0", [2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096])
+def test_spacing_invariance(k0):
+    """Outputs do not depend on the ruler spacing (several levels forced)."""
+    print(f"case: spacing k0={k0}", flush=True)
+    L = workloads.random_list(200003, seed=7)
+    check_rank(L.succ, lr.make_opts(spacing=(k0,), base_max=64, seed=k0))
+
+
+@pytest.mark.parametrize("spacing,base", [((2, 2, 2, 2, 2), 8), ((4, 8, 2), 16), ((64, 2), 1), ((16,), 16384)])
+def test_deep_recursion(spacing, base):
+    print(f"case: spacing={spacing} base={base}", flush=True)
+    L = workloads.random_list(30011, seed=9)
+    check_rank(L.succ, lr.make_opts(spacing=spacing, base_max=base))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 12345678901])
+def test_seed_invariance_and_determinism(seed):
+    print(f"case: seed={seed}", flush=True)
+    L = workloads.random_list(150000, seed=3)
+    o = lr.make_opts(seed=seed, base_max=256)
+    st1, r1, t1 = gpu_rank(L.succ, o)
+    st2, r2, t2 = gpu_rank(L.succ, o)
+    assert st1 == st2 == lr.LR_OK
+    assert np.array_equal(r1, r2) and np.array_equal(t1, t2)
+    check_rank(L.succ, o)
+
+
+def test_structured_lists():
+    n = 100000
+    print("case: identity / reversed / singletons / pairs / block-local", flush=True)
+    check_rank(np.minimum(np.arange(n) + 1, n - 1).astype(np.uint32), lr.make_opts(base_max=512))
+    check_rank(np.maximum(np.arange(n) - 1, 0).astype(np.uint32), lr.make_opts(base_max=512))
+    check_rank(np.arange(n, dtype=np.uint32), lr.make_opts(base_max=512))
+    pairs = np.arange(n, dtype=np.uint32)
+    pairs[0::2] = np.arange(1, n, 2, dtype=np.uint32)
+    check_rank(pairs, lr.make_opts(base_max=512))
+    check_rank(workloads.block_list(n, block=4096, seed=5).succ, lr.make_opts(base_max=512))
+    check_rank(workloads.block_list(n, block=64, seed=6).succ, lr.make_opts(base_max=512))
+
+
+@pytest.mark.parametrize("mean,base", [(2.0, 128), (8.0, 1024), (64.0, 0)])
+def test_forest_ranks(mean, base):
+    print(f"case: forest mean={mean} base={base}", flush=True)
+    F = workloads.forest(300000, mean=mean, n_long=3, long_len=20000, seed=int(mean))
+    check_rank(F.succ, lr.make_opts(base_max=base))
+
+
+@pytest.mark.parametrize("wdtype", [np.int64, np.int32, None])
+@pytest.mark.parametrize("base", [0, 64])
+def test_prefix_sum_forest(wdtype, base):
+    print(f"case: prefix sum forest wdtype={wdtype} base={base}", flush=True)
+    F = workloads.forest(250000, mean=64, n_long=4, long_len=10000, seed=31,
+                         wdtype=wdtype if wdtype is not None else np.int64)
+    w = F.weight if wdtype is not None else None
+    st, s, r, t = gpu_prefix(F.succ, w, lr.make_opts(base_max=base))
+    assert st == lr.LR_OK, lr.status_string(st)
+    ost, er, et, es = oracle.rank(F.succ, w)
+    assert ost == 0
+    assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+
+
+def test_prefix_sum_optional_outputs():
+    F = workloads.forest(50000, mean=16, n_long=1, long_len=5000, seed=32)
+    st, s, r, t = gpu_prefix(F.succ, F.weight, lr.make_opts(base_max=128), want_rank=False, want_root=False)
+    assert st == lr.LR_OK
+    assert np.array_equal(s, oracle.rank(F.succ, F.weight)[3])
+
+
+@pytest.mark.parametrize("V", [2, 3, 1000, 1 << 16])
+def test_euler_tour_depths(V):
+    print(f"case: euler V={V}", flush=True)
+    E = workloads.euler_tour(V, seed=14)
+    st, s, r, t = gpu_prefix(E.succ, E.weight, lr.make_opts(base_max=256))
+    assert st == lr.LR_OK
+    ost, er, et, es = oracle.rank(E.succ, E.weight)
+    assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+    m = E.succ.size
+    h = int(np.setdiff1d(np.arange(m), E.succ[E.succ != np.arange(m)])[0])
+    v = np.arange(1, V)
+    assert np.array_equal(s[h] - s[E.down_arc[v]] + 1, E.depth[1:].astype(np.int64))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 1000, 70001])
+def test_wyllie_baseline(n):
+    print(f"case: wyllie n={n}", flush=True)
+    F = workloads.forest(n, mean=16, n_long=0, long_len=0, seed=n)
+    st, r, t, _ = gpu_wyllie(F.succ)
+    assert st == lr.LR_OK
+    ost, er, et, es = oracle.rank(F.succ, F.weight)
+    assert np.array_equal(r, er) and np.array_equal(t, et)
+    st, r, t, s = gpu_wyllie(F.succ, F.weight, weighted=True)
+    assert st == lr.LR_OK
+    assert np.array_equal(r, er) and np.array_equal(t, et) and np.array_equal(s, es)
+
+
+def test_all_tiny_forests():
+    """Every valid successor array with n <= 5, each ranked alone."""
+    import itertools
+    for n in range(1, 6):
+        print(f"case: all forests n={n}", flush=True)
+        for succ in itertools.product(range(n), repeat=n):
+            a = np.array(succ, np.uint32)
+            if oracle.rank(a)[0] != oracle.OK:
+                continue
+            st, r, t = gpu_rank(a)
+            assert st == 0
+            _, er, et, _ = oracle.rank(a)
+            assert np.array_equal(r, er) and np.array_equal(t, et), a
+
+
+def test_relabelled_input_gives_relabelled_output():
+    F = workloads.forest(123457, mean=32, n_long=2, long_len=9000, seed=41)
+    n = F.succ.size
+    sigma = workloads.perm(n, seed=77)
+    succ2 = np.empty(n, np.uint32)
+    succ2[sigma] = sigma[F.succ]
+    o = lr.make_opts(base_max=300)
+    _, r, t = gpu_rank(F.succ, o)
+    _, r2, t2 = gpu_rank(succ2, o)
+    assert np.array_equal(r2[sigma], r) and np.array_equal(t2[sigma], sigma[t])
+
+
+def test_validate_accepts_valid_and_flags_invalid():
+    o = lr.make_opts(flags=lr.LR_VALIDATE, base_max=64)
+    L = workloads.random_list(100000, seed=2)
+    st, r, _ = gpu_rank(L.succ, o)
+    assert st == lr.LR_OK
+    F = workloads.forest(50000, mean=8, n_long=1, long_len=1000, seed=3)
+    assert gpu_rank(F.succ, o)[0] == lr.LR_OK
+    assert gpu_prefix(F.succ, F.weight, o)[0] == lr.LR_OK
+    # a pure cycle beside a list
+    cyc = L.succ.copy()
+    a, c = int(L.order[10]), int(L.order[12])
+    cyc[L.order[9]] = L.order[9]          # cut the list after position 9
+    cyc[c] = a                            # close positions 10..12 into a cycle; 13.. stays a list
+    assert gpu_rank(cyc, o)[0] == lr.LR_ERR_BAD_LIST
+    dbl = L.succ.copy()
+    dbl[L.order[5]] = L.order[7]          # two predecessors for order[7]
+    assert gpu_rank(dbl, o)[0] == lr.LR_ERR_BAD_LIST
+    oob = L.succ.copy()
+    oob[123] = 100000 + 5
+    assert gpu_rank(oob, o)[0] == lr.LR_ERR_BAD_LIST
+    small = np.array([1, 2, 0, 3], np.uint32)  # cycle in a case small enough for the base case alone
+    assert gpu_rank(small, o)[0] == lr.LR_ERR_BAD_LIST
+
+
+def test_invalid_input_without_validation_is_memory_safe():
+    """Without LR_VALIDATE, malformed input returns (garbage) without faults."""
+    n = 50000
+    rng = np.random.default_rng(5)
+    bad = rng.integers(0, n, size=n).astype(np.uint32)  # many double predecessors and cycles
+    st, _, _ = gpu_rank(bad, lr.make_opts(base_max=64))
+    assert st == lr.LR_OK
+    bad2 = bad.copy()
+    bad2[::7] = 0xfffffff0
+    st, _, _ = gpu_rank(bad2, lr.make_opts(base_max=64))
+    assert st == lr.LR_OK
+
+
+def test_profile_phases():
+    L = workloads.random_list(1 << 20, seed=1)
+    st, _, _ = gpu_rank(L.succ, lr.make_opts(flags=lr.LR_PROFILE))
+    assert st == 0
+    ms = lr.lr_profile_last()
+    assert len(ms) == 6 and all(x >= 0 for x in ms) and ms[5] > 0
+    torch.cuda.synchronize()
