@@ -1,0 +1,279 @@
+"""Benchmark: sparse ruling-set list ranking of one random 2^28-element list on
+one MI355X, plus the context numbers the metric asks for.
+
+A step is one lr_rank call (every kernel of the method: predecessor marks,
+head compaction, chase, upper levels, base case, expand) on a list already
+resident in HBM. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G elements ranked/s and achieved HBM GB/s, 2^28 random list; batched p50/p99"
+HBM_PEAK_GBS = 8000.0
+N_MAIN = 1 << 28
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
+    ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=4096)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2606_09318_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build ranks one GPU's share and has no multi-GPU path; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4, "reps": 5}))
+        return
+
+    n = args.n
+    t0 = time.time()
+    L = workloads.random_list(n, seed=2, stream=0)
+    gen_s = time.time() - t0
+    succ = torch.from_numpy(L.succ.view(np.int32)).to(dev)
+    rank = torch.empty(n, dtype=torch.int32, device=dev)
+    root = torch.empty(n, dtype=torch.int32, device=dev)
+    plan = lr.lr_plan_query(n)
+    ws = lr.workspace(lr.lr_workspace_bytes(n), dev)
+
+    def step():
+        s = lr.lr_rank(succ, rank, root, ws, None, stream)
+        if s:
+            raise lr.LrError(s, "lr_rank")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = n / (ms * 1e-3) / 1e9
+
+    # correctness of what was timed: closed form of the generated order
+    order = torch.from_numpy(L.order.view(np.int32)).to(dev)
+    expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device=dev)
+    ok = bool(torch.equal(rank.index_select(0, order), expect)) and bool((root == int(L.order[-1])).all())
+    del order, expect
+    if not ok:
+        raise SystemExit("bench: ranks do not match the closed form of the generated list")
+    if args.only_main:
+        print(json.dumps({"metric": METRIC, "value": round(value, 4), "unit": "G elements/s",
+                          "ms_per_step": round(ms, 4), "n": n}))
+        return
+
+    # per-phase times with HIP events on the launch stream (LR_PROFILE), and
+    # the level-0 chase (the dominant kernel) for the roofline
+    popt = lr.make_opts(flags=lr.LR_PROFILE)
+    phases = []
+    for _ in range(5):
+        lr.lr_rank(succ, rank, root, ws, popt, stream)
+        phases.append(lr.lr_profile_last())
+    ph = np.median(np.array(phases), axis=0)
+    chase_ms = float(ph[2])
+    S = int(plan.m[1])
+    chase_bytes = n * (4 + 8) + S * (8 + 1)      # succ gather + slot store per element; record + mark per walk
+    achieved = chase_bytes / (chase_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "chase_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel_hash") == kernel_source_hash() and tj.get("n") == n:
+            traffic = tj.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "k_chase (level 0)", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "chase_ms": round(chase_ms, 4),
+                "algorithmic_bytes": chase_bytes}
+    whole_bytes = n * (1 + 4 + 1 + 2 + 4 + 8 + 8 + 8 + 4 + 4)  # 44 B per element over the level-0 passes
+    extra = {"phases_ms": {"detect": round(float(ph[0]), 4), "heads": round(float(ph[1]), 4),
+                           "chase_level0": round(chase_ms, 4), "upper_levels_and_base": round(float(ph[3]), 4),
+                           "resolve_and_group": round(float(ph[4]), 4),
+                           "expand": round(float(ph[5]), 4), "total": round(float(ph[6]), 4)},
+             "useful_bytes_gbs_whole_step": round(whole_bytes / (ms * 1e-3) / 1e9, 1),
+             "plan": {"levels": plan.levels, "m": [int(plan.m[i]) for i in range(plan.levels + 1)],
+                      "spacing": [int(plan.spacing[i]) for i in range(plan.levels)]},
+             "generation_s": round(gen_s, 2)}
+
+    # GPU baseline: Wyllie pointer doubling on the same list
+    del ws
+    torch.cuda.empty_cache()
+    wsw = lr.workspace(lr.lr_wyllie_workspace_bytes(n), dev)
+    lr.lr_rank_wyllie(succ, rank, root, wsw, stream)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(3):
+        lr.lr_rank_wyllie(succ, rank, root, wsw, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wy_ms = ev0.elapsed_time(ev1) / 3
+    extra["wyllie"] = {"ms": round(wy_ms, 3), "srs_speedup": round(wy_ms / ms, 2)}
+    del wsw
+    torch.cuda.empty_cache()
+
+    # locality-preserving variant of the same size (blocks of 4096 ids)
+    B = workloads.block_list(n, block=4096, seed=2, stream=1)
+    succ.copy_(torch.from_numpy(B.succ.view(np.int32)))
+    ws = lr.workspace(lr.lr_workspace_bytes(n), dev)
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(5):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    bms = ev0.elapsed_time(ev1) / 5
+    order = torch.from_numpy(B.order.view(np.int32)).to(dev)
+    bok = bool(torch.equal(rank.index_select(0, order), torch.arange(n - 1, -1, -1, dtype=torch.int32, device=dev)))
+    extra["block_local_4096"] = {"ms": round(bms, 3), "g_elements_per_s": round(n / (bms * 1e-3) / 1e9, 3),
+                                 "closed_form_ok": bok}
+    del ws, order, succ, rank, root, B, L
+    torch.cuda.empty_cache()
+
+    if not args.no_serve:
+        extra["serving"] = serve_bench(args.serve_count)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+
+    out = {"metric": METRIC, "value": round(value, 4), "unit": "G elements/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "single random list, n=2^28, uint32 succ (seed 2), rank + root",
+                      "n": n, "parallelism": "single GPU"},
+           "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out))
+
+
+def serve_bench(count: int) -> dict:
+    """Continuous batching vs one launch sequence per request on the serving
+    trace (Poisson arrivals, sizes log-uniform over 2^10..2^24)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    tr = workloads.serving_trace(count=count, lo_log2=10, hi_log2=24, rate_per_s=1.0, seed=5)
+    items = []
+    total = 0
+    t0 = time.time()
+    for q in tr:
+        Lq = workloads.request_input(q)
+        s = torch.from_numpy(Lq.succ.view(np.int32)).to("cuda:0", non_blocking=False)
+        items.append((s, torch.empty(q.n, dtype=torch.int32, device="cuda:0"), None))
+        total += q.n
+    gen_s = time.time() - t0
+    reqs = lr.requests(items)
+    budget = 32 << 30
+
+    def cfg(inflight, max_batch):
+        c = lr.lr_server_config()
+        c.hbm_budget, c.max_inflight, c.max_batch = budget, inflight, max_batch
+        return c
+
+    torch.cuda.synchronize()
+    # saturation throughput: every request present at t = 0
+    st, lat, sts, mk = lr.lr_server_replay(cfg(2, count), reqs, [0.0] * count, count)
+    sat = total / mk
+    rate = 0.8 * sat / (total / count)
+    arr = [0.0] * count
+    t = 0.0
+    for i, q in enumerate(workloads.serving_trace(count=count, lo_log2=10, hi_log2=24, rate_per_s=rate, seed=5)):
+        arr[i] = q.arrival_s
+    res = {"requests": count, "total_elements": total, "offered_rate_req_per_s": round(rate, 1),
+           "hbm_budget_gib": budget >> 30, "saturation_g_elements_per_s": round(sat / 1e9, 3),
+           "input_generation_s": round(gen_s, 1)}
+    for name, c in (("batched", cfg(2, count)), ("per_request", cfg(1, 1))):
+        st, lat, sts, mk = lr.lr_server_replay(c, reqs, arr, count)
+        lat = np.array(lat) * 1e3
+        res[name] = {"status_ok": bool(st == 0 and all(s == 0 for s in sts)),
+                     "throughput_g_elements_per_s": round(total / mk / 1e9, 3), "makespan_s": round(mk, 3),
+                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    # spot check: a few requests against their closed form
+    for i in range(0, count, max(1, count // 16)):
+        Lq = workloads.request_input(tr[i])
+        r = items[i][1].cpu().numpy().view(np.uint32)
+        expect = np.empty(tr[i].n, np.uint32)
+        expect[Lq.order] = np.arange(tr[i].n - 1, -1, -1, dtype=np.uint32)
+        if not np.array_equal(r, expect):
+            res["closed_form_ok"] = False
+            break
+    else:
+        res["closed_form_ok"] = True
+    del items
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline() -> dict:
+    """The oracle as it stands (sequential pointer chasing, one thread) on a
+    bounded sample of the same workload: one random list of 2^25 elements."""
+    import oracle
+    import workloads
+
+    n = 1 << 25
+    L = workloads.random_list(n, seed=2, stream=0)
+    t0 = time.perf_counter()
+    st, r, t, _ = oracle.rank(L.succ, want=("rank", "root"))
+    dt = time.perf_counter() - t0
+    assert st == 0
+    return {"value": round(n / dt / 1e9, 5), "unit": "G elements/s", "cores": 1, "kind": "oracle",
+            "sample": "one random list of 2^25 elements from the same generator, one run, rank + root",
+            "seconds": round(dt, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -164,9 +164,12 @@ lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtyp
                                void* ws, size_t ws_bytes, void* stream);
 
 /* Per-phase device times (milliseconds) of the last call made with
- * LR_PROFILE on this thread: [0] detect, [1] head compaction, [2] chase,
- * [3] upper levels and base case, [4] expand (all levels), [5] total.
- * Synchronises on the recorded events. Returns the number of values written. */
+ * LR_PROFILE on this thread: [0] predecessor marks, [1] head compaction,
+ * [2] level-0 chase, [3] upper levels, base case and their propagation,
+ * [4] level-0 record resolution and first grouping pass (0 for inputs
+ * below 2^22), [5] level-0 propagation to the outputs, [6] total.
+ * Synchronises on the recorded events. Returns the number of values
+ * written. */
 int lr_profile_last(double* ms, int cap);
 
 /* Human-readable name of a status code (static storage). */

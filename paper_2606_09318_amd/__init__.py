@@ -188,8 +188,8 @@ def lr_rank_batch(reqs: ctypes.Array, count: int, ws, opts=None, stream=None) ->
 
 
 def lr_profile_last() -> list[float]:
-    buf = (ctypes.c_double * 6)()
-    k = load().lr_profile_last(buf, 6)
+    buf = (ctypes.c_double * 7)()
+    k = load().lr_profile_last(buf, 7)
     return list(buf[:k])
 
 

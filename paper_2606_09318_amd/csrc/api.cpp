@@ -76,15 +76,42 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         p->m[L] = m;
     }
     p->levels = L;
+    p->log0 = L >= 1 && n >= LOG_MIN_N;
     // layout
     size_t off = 0;
     p->off_ctrl = off;
     off += align_up(sizeof(Ctrl));
+    if (p->log0) {
+        p->chunk = LOG_CHUNK;
+        p->max_chunks = (uint32_t)((n + LOG_CHUNK - 64) / (LOG_CHUNK - 63)) + LOG_MAX_WAVES + 1;
+        const size_t cap = (size_t)p->max_chunks * LOG_CHUNK;
+        uint32_t lg = 0;
+        while ((1ull << lg) < n) ++lg;
+        p->s2 = (weighted ? 11u : 12u) + (lg > 28 ? 1u : 0u);  // fine range fits the LDS of one workgroup
+        p->s1 = p->s2 + std::max(1u, (lg - p->s2 + 1) / 2);     // split the fan-out evenly over two passes
+        p->nb1 = (uint32_t)((n + (1ull << p->s1) - 1) >> p->s1);
+        p->nb2 = (uint32_t)((n + (1ull << p->s2) - 1) >> p->s2);
+        const int arrays = weighted ? 4 : 3;
+        for (int i = 0; i < arrays; ++i) {
+            p->off_log[i] = off;
+            off += align_up(cap * (i == 3 ? 8 : 4));
+        }
+        for (int i = 0; i < arrays; ++i) {
+            p->off_p[i] = off;
+            off += align_up((size_t)n * (i == 3 ? 8 : 4));
+        }
+        p->off_fill = off;
+        off += align_up((size_t)(p->nb1 + p->nb2) * 4);
+    }
     for (uint32_t l = 0; l < std::max(L, 1u); ++l) {
         const uint64_t ml = p->m[l];
         const uint64_t S = (l < L) ? p->m[l + 1] : 0;
-        p->off_slot[l] = off;
-        off += align_up(std::max<size_t>((size_t)ml * p->rec_bytes, 16));
+        if (l == 0 && p->log0) {
+            p->off_slot[0] = p->off_p[0];  // no slot array: marks and counts live in the grouping area
+        } else {
+            p->off_slot[l] = off;
+            off += align_up(std::max<size_t>((size_t)ml * p->rec_bytes, 16));
+        }
         if (l < L) {
             p->ntiles[l] = (uint32_t)((ml + TILE - 1) / TILE);
             p->off_eb[l] = off;
@@ -382,8 +409,8 @@ extern "C" int lr_profile_last(double* ms, int cap) {
     for (int i = 1; i < EV_COUNT; ++i) (void)hipEventElapsedTime(&v[i], g_prof.ev[i - 1], g_prof.ev[i]);
     float total = 0;
     (void)hipEventElapsedTime(&total, g_prof.ev[0], g_prof.ev[EV_COUNT - 1]);
-    double out[6] = {v[EV_DETECT], v[EV_HEADS], v[EV_CHASE0], v[EV_UPPER], v[EV_EXPAND], total};
-    int k = std::min(cap, 6);
+    double out[7] = {v[EV_DETECT], v[EV_HEADS], v[EV_CHASE0], v[EV_UPPER], v[EV_PART], v[EV_EXPAND], total};
+    int k = std::min(cap, 7);
     for (int i = 0; i < k; ++i) ms[i] = out[i];
     return k;
 }

@@ -29,7 +29,19 @@ constexpr int MAXL = 8;
 struct Ctrl {
     struct Lv { uint32_t H, q; } lv[MAXL];  // per level: #initial-element walks, chase queue head
     uint32_t err;                           // validation error bits
-    uint32_t pad[15];
+    uint32_t chunks;                        // visit-log chunks handed out (level 0, log mode)
+    uint32_t pad[14];
+};
+
+// Visit log of the level-0 chase (log mode), structure of arrays: one record
+// (element, walk, offset) per visited element. The same layout holds the
+// records after they are partitioned by element range.
+template <bool W>
+struct LogArrays {
+    uint32_t* x;
+    uint32_t* w;
+    uint32_t* c;
+    int64_t* s;  // weighted levels only
 };
 
 // ---------------------------------------------------------------- values --

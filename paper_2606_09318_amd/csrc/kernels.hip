@@ -163,8 +163,9 @@ __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__
 // One workgroup: exclusive scan of the tile counts in place; publishes the
 // walk count and resets the chase queue of this level.
 __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles,
-                                                     Ctrl* ctrl, int lvl) {
+                                                     Ctrl* ctrl, int lvl, uint32_t* clr, uint32_t nclr) {
     __shared__ uint32_t sh[1024 / 64];
+    for (uint32_t i = threadIdx.x; i < nclr; i += blockDim.x) clr[i] = 0;
     const uint32_t per = (ntiles + blockDim.x - 1) / blockDim.x;
     const uint32_t a = threadIdx.x * per;
     const uint32_t b = min(a + per, ntiles);
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tile
     if (threadIdx.x == 0) {
         ctrl->lv[lvl].H = total;
         ctrl->lv[lvl].q = 0;
+        if (lvl == 0) ctrl->chunks = 0;
     }
 }
 
@@ -208,11 +210,19 @@ __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__
 // one dependent gather (the record of x), one store (slot[x]) and a few ALU
 // operations for the ruler test, so the loop is bound by memory latency and
 // the lanes resident on the chip keep that many gathers in flight.
-template <bool W, class Src>
+//
+// LOG mode (level 0 of large inputs): instead of storing slot[x] at a random
+// address, the active lanes of a wavefront append their (x, walk, offset)
+// records to a chunk of the visit log that the wavefront owns, at consecutive
+// positions (mbcnt over the active lanes), so every step writes whole lines.
+// A chunk that cannot take another step's records is padded with NONE and a
+// new one is taken with one atomic.
+template <bool W, class Src, bool LOG>
 __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint32_t S, Ctrl* ctrl, int lvl,
                                                      typename Lay<W>::Slot* __restrict__ slot,
                                                      typename Lay<W>::Rec* __restrict__ eb,
-                                                     uint8_t* __restrict__ hp_next, uint32_t refill) {
+                                                     uint8_t* __restrict__ hp_next, uint32_t refill,
+                                                     LogArrays<W> lg, uint32_t max_chunks) {
     using L = Lay<W>;
     using Val = typename L::Val;
     const uint32_t lane = lane_id();
@@ -221,6 +231,8 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
     uint32_t w = NONE, x = 0, steps = 0;
     Val off = L::zero();
     bool exhausted = false;
+    uint32_t cbase = 0, cfill = LOG_CHUNK;  // visit-log chunk held by this wavefront (LOG mode)
+    bool have = false, dead = false;
     for (;;) {
         const uint64_t idle = __ballot(w == NONE);
         if (idle == ~0ull && exhausted) break;
@@ -246,11 +258,45 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                 }
             }
         }
+        uint32_t pos = 0;
+        if constexpr (LOG) {
+            const uint64_t act = __ballot(w != NONE);
+            const uint32_t na = __popcll(act);
+            if (na && !dead) {
+                if (cfill + na > LOG_CHUNK) {
+                    if (have)
+                        for (uint32_t q = cfill + lane; q < LOG_CHUNK; q += 64) lg.x[cbase + q] = NONE;
+                    uint32_t c = 0;
+                    if (lane == 0) c = atomicAdd(&ctrl->chunks, 1u);
+                    c = __shfl(c, 0);
+                    if (c >= max_chunks) {  // more visits than elements: the input is not a forest
+                        dead = true;
+                        have = false;
+                        if (lane == 0) atomicOr(&ctrl->err, 32u);
+                    } else {
+                        cbase = c * LOG_CHUNK;
+                        cfill = 0;
+                        have = true;
+                    }
+                }
+                pos = cbase + cfill + mbcnt(act);
+                cfill += na;
+            }
+        }
         if (w != NONE) {
             uint32_t nxt;
             Val v;
             src.load(x, nxt, v);
-            slot[x] = L::slot(w, off);
+            if constexpr (LOG) {
+                if (!dead) {
+                    lg.x[pos] = x;
+                    lg.w[pos] = w;
+                    lg.c[pos] = off.c;
+                    if constexpr (W) lg.s[pos] = off.s;
+                }
+            } else {
+                slot[x] = L::slot(w, off);
+            }
             if (nxt & TERM) {                       // x is a terminal: the walk ends on it
                 eb[w] = L::rec(nxt, L::add(off, v));
                 w = NONE;
@@ -270,6 +316,10 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                 }
             }
         }
+    }
+    if constexpr (LOG) {
+        if (have)
+            for (uint32_t q = cfill + lane; q < LOG_CHUNK; q += 64) lg.x[cbase + q] = NONE;
     }
 }
 
@@ -427,6 +477,240 @@ __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __r
     }
 }
 
+// ---------------------------------------------------------- placement ----
+// Log mode, after the recursion: every visit-log record (x, walk, offset)
+// becomes (x, rank, root[, sum]) and must land at x. Records are grouped by
+// element range in two passes and a final pass writes each range of 2^s2
+// elements from LDS, so every output line is written whole:
+//   place1  resolve each record against its walk's result (records of one
+//           walk sit close together in the log, so these gathers mostly hit
+//           the caches) and partition by x >> s1 (coarse ranges);
+//   place2  within each coarse range, partition by x >> s2 (fine ranges);
+//   place3  one workgroup per fine range: scatter into LDS by x, then write
+//           the outputs in order.
+// Every element is visited exactly once, so range r has exactly as many
+// records as ids; its region in the output array starts at r << shift and a
+// per-range fill counter hands out positions inside it.
+template <bool W>
+struct PlaceArrays {
+    uint32_t* x;
+    uint32_t* r;   // rank (link count)
+    uint32_t* t;   // root
+    int64_t* s;    // weighted rank (weighted levels only)
+};
+
+template <bool W>
+constexpr int place_per() { return W ? 8 : 16; }
+
+// LDS bytes of one placement tile over nb buckets (device and host agree).
+__host__ __device__ constexpr size_t place_lds_bytes(bool weighted, uint32_t nb) {
+    const size_t T = (size_t)(weighted ? 8 : 16) * TPB;
+    size_t o = 8 * (size_t)nb + 12 * T;
+    if (weighted) o = ((o + 7) & ~(size_t)7) + 8 * T;
+    return o + 2 * T;
+}
+
+// LDS counting sort of one tile by bucket, then coalesced writes of each
+// bucket's run to [region(b) + reserved(b), ...). Records with x >= n are
+// skipped. lo_bucket: global id of the tile's bucket 0 (place2).
+template <bool W, int PER>
+__device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER], const uint32_t (&ts)[PER],
+                           const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t region_shift,
+                           uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
+                           Ctrl* ctrl, unsigned char* lds) {
+    constexpr uint32_t T = (uint32_t)PER * TPB;
+    size_t o = 0;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + o);
+    o += 4 * (size_t)nb;
+    uint32_t* gbase = reinterpret_cast<uint32_t*>(lds + o);
+    o += 4 * (size_t)nb;
+    uint32_t* sx = reinterpret_cast<uint32_t*>(lds + o);
+    o += 4 * (size_t)T;
+    uint32_t* sr = reinterpret_cast<uint32_t*>(lds + o);
+    o += 4 * (size_t)T;
+    uint32_t* st = reinterpret_cast<uint32_t*>(lds + o);
+    o += 4 * (size_t)T;
+    int64_t* sw = nullptr;
+    if constexpr (W) {
+        o = (o + 7) & ~(size_t)7;
+        sw = reinterpret_cast<int64_t*>(lds + o);
+        o += 8 * (size_t)T;
+    }
+    uint16_t* sb = reinterpret_cast<uint16_t*>(lds + o);
+    __shared__ uint32_t scan_sh[TPB / 64];
+    __shared__ uint32_t tile_total;
+    const uint32_t t = threadIdx.x;
+    uint32_t lr[PER];
+    for (uint32_t b = t; b < nb; b += TPB) hist[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+        if (xs[j] < n) lr[j] = atomicAdd(&hist[bs[j]], 1u);
+    __syncthreads();
+    // exclusive scan of hist (each lane owns a run of consecutive buckets) and reservations
+    const uint32_t chunk = (nb + TPB - 1) / TPB;
+    const uint32_t a = min(t * chunk, nb), e = min(a + chunk, nb);
+    uint32_t sum = 0;
+    for (uint32_t b = a; b < e; ++b) sum += hist[b];
+    uint32_t total;
+    uint32_t run = block_exscan(sum, scan_sh, &total);
+    for (uint32_t b = a; b < e; ++b) {
+        const uint32_t h = hist[b];
+        gbase[b] = h ? atomicAdd(&fill[lo_bucket + b], h) : 0u;
+        hist[b] = run;
+        run += h;
+    }
+    if (t == 0) tile_total = total;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (xs[j] < n) {
+            const uint32_t p = hist[bs[j]] + lr[j];
+            sx[p] = xs[j];
+            sr[p] = rs[j];
+            st[p] = ts[j];
+            if constexpr (W) sw[p] = ss[j];
+            sb[p] = (uint16_t)bs[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = tile_total;
+    for (uint32_t i = t; i < cnt; i += TPB) {
+        const uint32_t b = sb[i];
+        const uint64_t lo = (uint64_t)(lo_bucket + b) << region_shift;
+        const uint64_t hi = min(lo + (1ull << region_shift), (uint64_t)n);
+        const uint64_t p = lo + gbase[b] + (i - hist[b]);
+        if (p < hi) {
+            out.x[p] = sx[i];
+            out.r[p] = sr[i];
+            out.t[p] = st[i];
+            if constexpr (W) out.s[p] = sw[i];
+        } else {
+            atomicOr(&ctrl->err, 64u);  // a range overflowed: some element was visited twice
+        }
+    }
+    __syncthreads();
+}
+
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
+                                                const typename Lay<W>::Res* __restrict__ res, uint32_t S,
+                                                Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
+                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out) {
+    using L = Lay<W>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int PER = place_per<W>();
+    const uint32_t T = PER * TPB;
+    const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
+    const uint32_t nw = S + ctrl->lv[0].H;
+    const uint32_t tiles = (used + T - 1) / T;
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+        int64_t ss[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tile * T + j * TPB + threadIdx.x;
+            xs[j] = (i < used) ? lg.x[i] : NONE;
+            if (xs[j] < n) {
+                const uint32_t w = lg.w[i];
+                typename L::Val off;
+                off.c = lg.c[i];
+                if constexpr (W) off.s = lg.s[i];
+                if (w < nw) {
+                    const typename L::Res b = res[w];
+                    const typename L::Val v = L::sub(L::val(b), off);
+                    rs[j] = v.c;
+                    ts[j] = b.root;
+                    if constexpr (W) ss[j] = v.s;
+                } else {
+                    rs[j] = NONE;
+                    ts[j] = NONE;
+                    if constexpr (W) ss[j] = INT64_MIN;
+                    atomicOr(&ctrl->err, 4u);
+                }
+                bs[j] = xs[j] >> s1;
+            }
+        }
+        place_tile<W, PER>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
+    }
+}
+
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
+                                                uint32_t* __restrict__ fill2, PlaceArrays<W> out) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int PER = place_per<W>();
+    const uint32_t T = PER * TPB;
+    const uint32_t tiles = (n + T - 1) / T;
+    const uint32_t fan = 1u << (s1 - s2);
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint32_t c = (tile * T) >> s1;  // coarse range of this tile (T divides 2^s1)
+        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+        int64_t ss[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tile * T + j * TPB + threadIdx.x;
+            xs[j] = (i < n) ? in.x[i] : NONE;
+            if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
+                atomicOr(&ctrl->err, 64u);
+                xs[j] = NONE;
+            }
+            if (xs[j] < n) {
+                rs[j] = in.r[i];
+                ts[j] = in.t[i];
+                if constexpr (W) ss[j] = in.s[i];
+                bs[j] = (xs[j] >> s2) - c * fan;
+            }
+        }
+        place_tile<W, PER>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
+    }
+}
+
+// One workgroup per fine range of 2^s2 elements: place the records by x in
+// LDS, then write the outputs in element order.
+template <bool W, class Out>
+__global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
+                                                const uint32_t* __restrict__ fill2, int check, Out out) {
+    using L = Lay<W>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const uint32_t R = 1u << s2;
+    int64_t* ls = reinterpret_cast<int64_t*>(lds);
+    uint32_t* lr = reinterpret_cast<uint32_t*>(lds + (W ? 8 * (size_t)R : 0));
+    uint32_t* lt = lr + R;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
+        const uint32_t base = f << s2;
+        const uint32_t len = min(R, n - base);
+        for (uint32_t i = t; i < len; i += TPB) {
+            lr[i] = NONE;
+            lt[i] = NONE;
+            if constexpr (W) ls[i] = INT64_MIN;
+        }
+        if (check && t == 0 && fill2[f] != len) atomicOr(&ctrl->err, 128u);
+        __syncthreads();
+        for (uint32_t i = t; i < len; i += TPB) {
+            const uint32_t x = in.x[base + i];
+            const uint32_t k = x - base;
+            if (k < len) {
+                lr[k] = in.r[base + i];
+                lt[k] = in.t[base + i];
+                if constexpr (W) ls[k] = in.s[base + i];
+            }
+        }
+        __syncthreads();
+        if (t < len) {
+            auto cur = out.begin(base + t);
+            for (uint32_t i = t; i < len; i += TPB) {
+                typename L::Val v;
+                v.c = lr[i];
+                if constexpr (W) v.s = ls[i];
+                out.store(cur, base + i, v, lt[i]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- Wyllie --
 template <bool W, class Src>
 __global__ __launch_bounds__(TPB) void k_wy_init(Src src, typename Lay<W>::Rec* __restrict__ a, uint32_t m) {
@@ -568,18 +852,32 @@ static hipError_t launch_base(Src src, Out out, uint32_t m, Ctrl* ctrl, hipStrea
     return hipGetLastError();
 }
 
-template <bool W, class Src>
+template <bool W>
+static LogArrays<W> log_arrays(char* ws, const size_t* off) {
+    LogArrays<W> a;
+    a.x = reinterpret_cast<uint32_t*>(ws + off[0]);
+    a.w = reinterpret_cast<uint32_t*>(ws + off[1]);
+    a.c = reinterpret_cast<uint32_t*>(ws + off[2]);
+    a.s = W ? reinterpret_cast<int64_t*>(ws + off[3]) : nullptr;
+    return a;
+}
+
+template <bool W, bool LOG, class Src>
 static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st) {
     using L = Lay<W>;
-    auto kern = k_chase<W, Src>;
+    auto kern = k_chase<W, Src, LOG>;
     static uint32_t grid = 0;  // one per template instance
-    if (!grid) grid = persistent_grid(kern, CHASE_TPB);
+    if (!grid) {
+        grid = persistent_grid(kern, CHASE_TPB);
+        if (LOG) grid = std::min<uint32_t>(grid, LOG_MAX_WAVES / (CHASE_TPB / 64));  // bounds the log slack
+    }
     const uint32_t S = (uint32_t)p.m[l + 1];
     auto* slot = reinterpret_cast<typename L::Slot*>(ws + p.off_slot[l]);
     auto* eb = reinterpret_cast<typename L::Rec*>(ws + p.off_eb[l]);
     uint8_t* hp_next = (l + 1 < (int)p.levels) ? reinterpret_cast<uint8_t*>(ws + p.off_slot[l + 1]) : nullptr;
+    LogArrays<W> lg = LOG ? log_arrays<W>(ws, p.off_log) : LogArrays<W>{};
     hipLaunchKernelGGL(kern, dim3(grid), dim3(CHASE_TPB), 0, st, src, smp, S, ctrl, l, slot, eb, hp_next,
-                       p.refill);
+                       p.refill, lg, p.max_chunks);
     return hipGetLastError();
 }
 
@@ -588,6 +886,54 @@ static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl*
         hipError_t e_ = (x);                   \
         if (e_ != hipSuccess) return e_;       \
     } while (0)
+
+template <bool W>
+static PlaceArrays<W> place_arrays(char* ws, const size_t* off) {
+    PlaceArrays<W> a;
+    a.x = reinterpret_cast<uint32_t*>(ws + off[0]);
+    a.r = reinterpret_cast<uint32_t*>(ws + off[1]);
+    a.t = reinterpret_cast<uint32_t*>(ws + off[2]);
+    a.s = W ? reinterpret_cast<int64_t*>(ws + off[3]) : nullptr;
+    return a;
+}
+
+template <class K>
+static hipError_t allow_lds(K kern, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Level-0 propagation in log mode: resolve + coarse grouping, fine grouping,
+// placement. The fine-grouped records reuse the visit-log arrays.
+template <bool W, class Out0>
+static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S, Ctrl* ctrl,
+                            Out0 out0) {
+    char* ws = a.ws;
+    hipStream_t st = a.stream;
+    const uint32_t n = (uint32_t)p.m[0];
+    uint32_t* fill1 = reinterpret_cast<uint32_t*>(ws + p.off_fill);
+    uint32_t* fill2 = fill1 + p.nb1;
+    const PlaceArrays<W> P = place_arrays<W>(ws, p.off_p);
+    const PlaceArrays<W> Q = place_arrays<W>(ws, p.off_log);
+    constexpr uint32_t T = (uint32_t)place_per<W>() * TPB;
+    const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
+    const size_t l1 = place_lds_bytes(W, p.nb1);
+    LR_TRY(allow_lds(k_place1<W>, l1));
+    hipLaunchKernelGGL(k_place1<W>, dim3(grid_for(cap, T)), dim3(TPB), l1, st, log_arrays<W>(ws, p.off_log),
+                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P);
+    LR_TRY(hipGetLastError());
+    rec_ev(a, EV_PART);
+    const size_t l2 = place_lds_bytes(W, 1u << (p.s1 - p.s2));
+    LR_TRY(allow_lds(k_place2<W>, l2));
+    hipLaunchKernelGGL(k_place2<W>, dim3(grid_for(n, T)), dim3(TPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2, Q);
+    LR_TRY(hipGetLastError());
+    const size_t l3 = ((size_t)1 << p.s2) * (W ? 16 : 8);
+    LR_TRY(allow_lds(k_place3<W, Out0>, l3));
+    hipLaunchKernelGGL((k_place3<W, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), dim3(TPB),
+                       l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0);
+    return hipGetLastError();
+}
+
 
 template <bool W, int WT, class Out0>
 static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
@@ -632,19 +978,25 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const uint32_t zw = more ? (S + 3) / 4 : 0;
         hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, nullptr, 0u);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
                            (uint32_t)p.rec_bytes);
         LR_TRY(hipGetLastError());
-        if (a.validate) LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st));
+        if (a.validate && !(l == 0 && p.log0))
+            LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st));
         if (l == 0) rec_ev(a, EV_HEADS);
         if (l == 0) {
-            LR_TRY((launch_chase<W>(p, 0, src0, smp, ctrl, ws, st)));
+            if (p.log0) {
+                LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st));
+                LR_TRY((launch_chase<W, true>(p, 0, src0, smp, ctrl, ws, st)));
+            } else {
+                LR_TRY((launch_chase<W, false>(p, 0, src0, smp, ctrl, ws, st)));
+            }
             rec_ev(a, EV_CHASE0);
         } else {
             SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]), m};
-            LR_TRY((launch_chase<W>(p, (int)l, src, smp, ctrl, ws, st)));
+            LR_TRY((launch_chase<W, false>(p, (int)l, src, smp, ctrl, ws, st)));
         }
     }
     {
@@ -654,7 +1006,6 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[L_ - 1])};
         LR_TRY((launch_base<W>(src, out, mL, ctrl, st)));
     }
-    rec_ev(a, EV_UPPER);
     for (int l = (int)p.levels - 1; l >= 0; --l) {
         const uint32_t m = (uint32_t)p.m[l];
         const uint32_t S = (uint32_t)p.m[l + 1];
@@ -665,7 +1016,13 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
         const uint32_t g = grid_for(m, TPB * EXPAND_CH);
         if (l == 0) {
-            hipLaunchKernelGGL((k_expand<W, Out0>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0);
+            rec_ev(a, EV_UPPER);
+            if (p.log0) {
+                LR_TRY((run_place<W, Out0>(a, p, res, S, ctrl, out0)));
+            } else {
+                rec_ev(a, EV_PART);
+                hipLaunchKernelGGL((k_expand<W, Out0>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0);
+            }
         } else {
             OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1])};
             hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, l,

@@ -12,6 +12,9 @@ namespace lr {
 constexpr uint32_t TILE = 4096;            // elements per compaction tile
 constexpr uint32_t BASE_MAX_LIMIT = 16384; // one workgroup of 1024 lanes x 16 elements
 constexpr size_t ALIGN = 256;
+constexpr uint32_t LOG_CHUNK = 1024;         // records per visit-log chunk
+constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
+constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
 
 struct Plan {
     bool weighted = false;
@@ -29,6 +32,14 @@ struct Plan {
     size_t off_eb[LR_MAX_LEVELS] = {};
     size_t off_tile[LR_MAX_LEVELS] = {};
     size_t off_batch_succ = 0, off_batch_desc = 0, off_batch_bases = 0;
+    // level 0 in log mode: the chase appends (element, walk, offset) records to
+    // a chunked visit log instead of storing at random addresses; after the
+    // recursion the records are resolved and grouped by element range in two
+    // passes (ranges of 2^s1, then 2^s2 ids) and written range by range.
+    // The fine-grouped records reuse the log arrays.
+    bool log0 = false;
+    uint32_t chunk = 0, max_chunks = 0, s1 = 0, s2 = 0, nb1 = 0, nb2 = 0;
+    size_t off_log[4] = {}, off_p[4] = {}, off_fill = 0;  // fill: nb1 then nb2 counters
     uint32_t batch_count = 0;
     size_t total = 0;
 };

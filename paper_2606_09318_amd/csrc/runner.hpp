@@ -9,7 +9,7 @@ namespace lr {
 
 struct BatchDesc;
 
-enum { EV_START, EV_DETECT, EV_HEADS, EV_CHASE0, EV_UPPER, EV_EXPAND, EV_COUNT };
+enum { EV_START, EV_DETECT, EV_HEADS, EV_CHASE0, EV_UPPER, EV_PART, EV_EXPAND, EV_COUNT };
 
 struct RunArgs {
     const Plan* plan = nullptr;

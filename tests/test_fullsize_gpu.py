@@ -1,0 +1,83 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (default options). Every output element is checked: against
+the closed form of the generated order where one exists, otherwise against
+the local certificate (whose solution on a valid forest is unique) and the
+Euler-tour depth recurrence."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2606_09318_amd as lr
+import workloads
+from gpu_util import certificate_gpu, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def closed_form_ok(rank, root, order_np):
+    n = order_np.size
+    order = dev(order_np)
+    expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+    ok = bool(torch.equal(rank.index_select(0, order), expect))
+    return ok and bool((root == int(order_np[-1])).all())
+
+
+@pytest.mark.parametrize("kind", ["random", "block4096"])
+def test_single_list_2p28(kind):
+    n = 1 << 28
+    print(f"case: {kind} list n=2^28", flush=True)
+    L = workloads.random_list(n, seed=2, stream=0) if kind == "random" else \
+        workloads.block_list(n, block=4096, seed=2, stream=1)
+    succ = dev(L.succ)
+    r, t = lr.rank(succ)
+    torch.cuda.synchronize()
+    assert closed_form_ok(r, t, L.order)
+    assert certificate_gpu(succ, r, t)
+    if kind == "random":
+        # the GPU baseline agrees bit for bit
+        r2 = torch.empty_like(r)
+        t2 = torch.empty_like(t)
+        del L
+        ws = lr.workspace(lr.lr_wyllie_workspace_bytes(n))
+        assert lr.lr_rank_wyllie(succ, r2, t2, ws) == lr.LR_OK
+        torch.cuda.synchronize()
+        assert torch.equal(r, r2) and torch.equal(t, t2)
+    torch.cuda.empty_cache()
+
+
+def test_forest_2p27_int64_weights():
+    n = 1 << 27
+    print("case: forest n=2^27 geometric(64) + 16 x 2^20, int64 weights", flush=True)
+    F = workloads.forest(n, mean=64, n_long=16, long_len=1 << 20, seed=3)
+    succ, w = dev(F.succ), dev(F.weight)
+    s, r, t = lr.prefix_sum(succ, w)
+    torch.cuda.synchronize()
+    assert certificate_gpu(succ, r, t, s, w)
+    # each list's ranks are a permutation of 0..len-1 and |S| stays in int64
+    lens = torch.bincount(t.to(torch.int64), minlength=n)
+    assert bool((r.to(torch.int64) < lens.index_select(0, t.to(torch.int64))).all())
+    assert int(lens.max()) == 1 << 20
+    # spot check whole lists against the generator's order
+    for i in list(range(0, F.starts.size - 1, (F.starts.size - 1) // 64)) + [F.starts.size - 2]:
+        a, b = int(F.starts[i]), int(F.starts[i + 1])
+        ids = torch.from_numpy(F.order[a:b].astype(np.int64)).cuda()
+        assert torch.equal(r.index_select(0, ids).cpu(), torch.arange(b - a - 1, -1, -1, dtype=torch.int32))
+    torch.cuda.empty_cache()
+
+
+def test_euler_tour_2p26_depths():
+    V = 1 << 26
+    print("case: Euler tour of a random recursive tree, V=2^26", flush=True)
+    E = workloads.euler_tour(V, seed=4)
+    succ, w = dev(E.succ), dev(E.weight)
+    s, r, t = lr.prefix_sum(succ, w)
+    torch.cuda.synchronize()
+    assert certificate_gpu(succ, r, t, s, w)
+    m = E.succ.size
+    idx = torch.arange(m, dtype=torch.int32, device="cuda")
+    head = int(torch.nonzero(r == m - 1)[0])
+    down = dev(E.down_arc[1:].view(np.int32) if E.down_arc.dtype == np.uint32 else E.down_arc[1:])
+    depth = s[head] - s.index_select(0, down) + 1
+    assert torch.equal(depth.cpu(), torch.from_numpy(E.depth[1:].astype(np.int64)))
+    del idx
+    torch.cuda.empty_cache()

@@ -198,5 +198,62 @@ def test_profile_phases():
     st, _, _ = gpu_rank(L.succ, lr.make_opts(flags=lr.LR_PROFILE))
     assert st == 0
     ms = lr.lr_profile_last()
-    assert len(ms) == 6 and all(x >= 0 for x in ms) and ms[5] > 0
+    assert len(ms) == 7 and all(x >= 0 for x in ms) and ms[6] > 0
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------------
+# Inputs of 2^22 elements and more take the visit-log path at level 0.
+
+@pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 12345, 5000011])
+def test_log_mode_random_lists(n):
+    print(f"case: log mode random list n={n}", flush=True)
+    p = lr.lr_plan_query(n)
+    assert p.levels >= 1
+    check_rank(workloads.random_list(n, seed=n % 1000).succ)
+
+
+def test_log_mode_block_list_and_forest():
+    n = (1 << 22) + 77
+    print("case: log mode block list / forest", flush=True)
+    check_rank(workloads.block_list(n, block=4096, seed=8).succ)
+    F = workloads.forest(n, mean=64, n_long=4, long_len=100000, seed=9)
+    check_rank(F.succ)
+    st, s, r, t = gpu_prefix(F.succ, F.weight)
+    assert st == lr.LR_OK
+    ost, er, et, es = oracle.rank(F.succ, F.weight)
+    assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+    F32 = workloads.forest(n, mean=8, n_long=1, long_len=300000, seed=10, wdtype=np.int32)
+    st, s, r, t = gpu_prefix(F32.succ, F32.weight)
+    ost, er, et, es = oracle.rank(F32.succ, F32.weight)
+    assert st == lr.LR_OK and np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+
+
+def test_log_mode_all_singletons_and_pairs():
+    n = (1 << 22) + 3
+    print("case: log mode singletons / pairs", flush=True)
+    check_rank(np.arange(n, dtype=np.uint32))
+    pairs = np.arange(n, dtype=np.uint32)
+    pairs[0:n - 1:2] = np.arange(1, n, 2, dtype=np.uint32)
+    check_rank(pairs)
+
+
+def test_log_mode_validate():
+    n = 1 << 22
+    o = lr.make_opts(flags=lr.LR_VALIDATE)
+    L = workloads.random_list(n, seed=4)
+    assert gpu_rank(L.succ, o)[0] == lr.LR_OK
+    cyc = L.succ.copy()
+    cyc[L.order[999]] = L.order[999]
+    cyc[L.order[2000]] = L.order[1000]
+    assert gpu_rank(cyc, o)[0] == lr.LR_ERR_BAD_LIST
+    dbl = L.succ.copy()
+    dbl[L.order[5]] = L.order[7]
+    assert gpu_rank(dbl, o)[0] == lr.LR_ERR_BAD_LIST
+
+
+def test_log_mode_invalid_input_is_memory_safe():
+    n = 1 << 22
+    rng = np.random.default_rng(11)
+    bad = rng.integers(0, n, size=n).astype(np.uint32)
+    assert gpu_rank(bad)[0] == lr.LR_OK
