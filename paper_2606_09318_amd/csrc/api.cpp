@@ -81,6 +81,8 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
     size_t off = 0;
     p->off_ctrl = off;
     off += align_up(sizeof(Ctrl));
+    p->off_hsum = off;
+    off += align_up((size_t)HEADSUM_BLOCKS * 16);
     if (p->log0) {
         p->chunk = LOG_CHUNK;
         p->max_chunks = (uint32_t)((n + LOG_CHUNK - 64) / (LOG_CHUNK - 63)) + LOG_MAX_WAVES + 1;
@@ -102,6 +104,9 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         }
         p->off_fill = off;
         off += align_up((size_t)(p->nb1 + p->nb2) * 4);
+        const size_t seg_records = (size_t)SEG_TILES * place_tile_records(weighted);
+        p->off_segh = off;
+        off += align_up(((cap + seg_records - 1) / seg_records) * p->nb1 * 4);
     }
     for (uint32_t l = 0; l < std::max(L, 1u); ++l) {
         const uint64_t ml = p->m[l];

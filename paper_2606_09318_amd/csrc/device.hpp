@@ -30,7 +30,10 @@ struct Ctrl {
     struct Lv { uint32_t H, q; } lv[MAXL];  // per level: #initial-element walks, chase queue head
     uint32_t err;                           // validation error bits
     uint32_t chunks;                        // visit-log chunks handed out (level 0, log mode)
-    uint32_t pad[14];
+    uint32_t nterm;                         // level 0: number of terminals (= number of lists)
+    uint32_t single;                        // level 0: one list, whose head is known from hsum
+    uint64_t hsum;                          // level 0: sum of ids minus sum of successors of non-terminals
+    uint32_t pad[10];
 };
 
 // Visit log of the level-0 chase (log mode), structure of arrays: one record

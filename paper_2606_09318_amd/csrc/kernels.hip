@@ -35,7 +35,9 @@ constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
 constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
 
 // ------------------------------------------------------------------ fill --
-__global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val) {
+__global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,
+                                              const Ctrl* skip_if_single) {
+    if (skip_if_single && skip_if_single->single) return;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n4 = words / 4;
     uint4 v = make_uint4(val, val, val, val);
@@ -50,7 +52,8 @@ __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t
 // stores suffice (no atomics, no cross-XCD coherence traffic).
 template <bool VEC>
 __global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ succ, uint32_t m,
-                                                uint8_t* __restrict__ hp) {
+                                                uint8_t* __restrict__ hp, const Ctrl* ctrl) {
+    if (ctrl->single) return;
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t done = 0;
@@ -69,6 +72,93 @@ __global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ suc
     for (uint32_t i = done + g; i < m; i += stride) {
         const uint32_t s = succ[i];
         if (s != i && s < m) hp[s] = 1;
+    }
+}
+
+// One list shortcut for finding the initial elements. Every non-head element
+// has exactly one predecessor, so over a forest
+//   sum(all ids) - sum(succ[x] over non-terminals x) = sum of the heads,
+// and the number of terminals is the number of lists. With one list this
+// sum IS the head, found by one streaming reduction instead of a random
+// store per element; the marking passes then do nothing.
+template <bool VEC>
+__global__ __launch_bounds__(TPB) void k_headsum(const uint32_t* __restrict__ succ, uint32_t m,
+                                                 uint32_t* __restrict__ partial) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t hs = 0;
+    uint32_t nt = 0;
+    auto one = [&](uint32_t x, uint32_t s) {
+        if (s == x || s >= m) { ++nt; hs += x; }
+        else hs += (uint64_t)x - s;
+    };
+    uint32_t done = 0;
+    if constexpr (VEC) {
+        const uint32_t m4 = m / 4;
+        for (uint32_t i = g; i < m4; i += stride) {
+            const uint4 s = reinterpret_cast<const uint4*>(succ)[i];
+            one(4 * i, s.x);
+            one(4 * i + 1, s.y);
+            one(4 * i + 2, s.z);
+            one(4 * i + 3, s.w);
+        }
+        done = m4 * 4;
+    }
+    for (uint32_t i = done + g; i < m; i += stride) one(i, succ[i]);
+    __shared__ uint64_t shs[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        hs += __shfl_xor(hs, o);
+        nt += __shfl_xor(nt, o);
+    }
+    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
+        partial[4 * blockIdx.x] = nt;
+        partial[4 * blockIdx.x + 1] = 0;
+        reinterpret_cast<uint64_t*>(partial)[2 * blockIdx.x + 1] = hs;
+    }
+}
+
+// Sums the partials; with exactly one terminal (and a head inside the range)
+// it publishes the head as the level's only initial-element walk.
+__global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restrict__ partial, uint32_t nparts,
+                                                       Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
+                                                       uint32_t rec_bytes) {
+    uint64_t hs = 0;
+    uint32_t nt = 0;
+    for (uint32_t i = threadIdx.x; i < nparts; i += TPB) {
+        nt += partial[4 * i];
+        hs += reinterpret_cast<const uint64_t*>(partial)[2 * i + 1];
+    }
+    __shared__ uint64_t shs[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        hs += __shfl_xor(hs, o);
+        nt += __shfl_xor(nt, o);
+    }
+    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
+        ctrl->nterm = nt;
+        ctrl->hsum = hs;
+        const bool single = nt == 1 && hs < smp.m;
+        ctrl->single = single ? 1u : 0u;
+        if (single) {
+            const uint32_t h = (uint32_t)hs;
+            uint32_t H = 0;
+            if (!smp.sampled(h)) {
+                *reinterpret_cast<uint32_t*>(eb + (size_t)S * rec_bytes) = h;
+                H = 1;
+            }
+            ctrl->lv[0].H = H;
+            ctrl->lv[0].q = 0;
+            ctrl->chunks = 0;
+        }
     }
 }
 
@@ -146,26 +236,27 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* sh, uint3
 
 __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__ hp, Sampler smp,
                                                      uint32_t* __restrict__ tilecnt, uint32_t* zero_p,
-                                                     uint32_t zero_words) {
+                                                     uint32_t zero_words, const Ctrl* skip_if_single) {
     __shared__ uint32_t sh[TPB / 64];
-    const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
-    uint32_t bits;
-    const uint32_t c = tile_heads(hp, smp, x0, bits);
-    const uint32_t t = block_sum(c, sh);
-    if (threadIdx.x == 0) tilecnt[blockIdx.x] = t;
     // clear the next level's predecessor marks (free memory at this point)
     if (zero_p) {
         const uint32_t stride = gridDim.x * blockDim.x;
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < zero_words; i += stride) zero_p[i] = 0;
     }
+    if (skip_if_single && skip_if_single->single) return;
+    const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
+    uint32_t bits;
+    const uint32_t c = tile_heads(hp, smp, x0, bits);
+    const uint32_t t = block_sum(c, sh);
+    if (threadIdx.x == 0) tilecnt[blockIdx.x] = t;
 }
 
 // One workgroup: exclusive scan of the tile counts in place; publishes the
 // walk count and resets the chase queue of this level.
 __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles,
-                                                     Ctrl* ctrl, int lvl, uint32_t* clr, uint32_t nclr) {
+                                                     Ctrl* ctrl, int lvl) {
     __shared__ uint32_t sh[1024 / 64];
-    for (uint32_t i = threadIdx.x; i < nclr; i += blockDim.x) clr[i] = 0;
+    if (lvl == 0 && ctrl->single) return;
     const uint32_t per = (ntiles + blockDim.x - 1) / blockDim.x;
     const uint32_t a = threadIdx.x * per;
     const uint32_t b = min(a + per, ntiles);
@@ -188,8 +279,9 @@ __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tile
 // Writes walk start j into the first word of walk record S + j.
 __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__ hp, Sampler smp,
                                                      const uint32_t* __restrict__ tileoff, char* __restrict__ eb,
-                                                     uint32_t S, uint32_t rec_bytes) {
+                                                     uint32_t S, uint32_t rec_bytes, const Ctrl* skip_if_single) {
     __shared__ uint32_t sh[TPB / 64];
+    if (skip_if_single && skip_if_single->single) return;
     const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
     uint32_t bits;
     const uint32_t c = tile_heads(hp, smp, x0, bits);
@@ -500,7 +592,7 @@ struct PlaceArrays {
 };
 
 template <bool W>
-constexpr int place_per() { return W ? 8 : 16; }
+constexpr int place_per() { return (int)place_tile_records(W) / TPB; }
 
 // LDS bytes of one placement tile over nb buckets (device and host agree).
 __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, uint32_t nb) {
@@ -513,11 +605,14 @@ __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, uint32_t nb)
 // LDS counting sort of one tile by bucket, then coalesced writes of each
 // bucket's run to [region(b) + reserved(b), ...). Records with x >= n are
 // skipped. lo_bucket: global id of the tile's bucket 0 (place2).
+// Space in a bucket's region comes either from a global fill counter (one
+// atomic per bucket and tile) or, when `run` is given, from running offsets in
+// LDS that a prefix over segment histograms initialised (no atomics).
 template <bool W, int PER>
 __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER], const uint32_t (&ts)[PER],
                            const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t region_shift,
-                           uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
-                           Ctrl* ctrl, unsigned char* lds) {
+                           uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, uint32_t* run_lds,
+                           PlaceArrays<W> out, Ctrl* ctrl, unsigned char* lds) {
     constexpr uint32_t T = (uint32_t)PER * TPB;
     size_t o = 0;
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + o);
@@ -556,7 +651,12 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     uint32_t run = block_exscan(sum, scan_sh, &total);
     for (uint32_t b = a; b < e; ++b) {
         const uint32_t h = hist[b];
-        gbase[b] = h ? atomicAdd(&fill[lo_bucket + b], h) : 0u;
+        if (run_lds) {
+            gbase[b] = run_lds[b];
+            run_lds[b] += h;
+        } else {
+            gbase[b] = h ? atomicAdd(&fill[lo_bucket + b], h) : 0u;
+        }
         hist[b] = run;
         run += h;
     }
@@ -592,46 +692,101 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     __syncthreads();
 }
 
+// place1 works on segments of SEG_TILES tiles of the visit log. k_p1_hist
+// counts each segment's records per coarse range, k_p1_scan turns the counts
+// into each segment's starting offset inside every range, and k_place1 then
+// writes a segment's runs at those offsets without atomics.
+
+__global__ __launch_bounds__(TPB) void k_p1_hist(const uint32_t* __restrict__ lx, const Ctrl* ctrl,
+                                                 uint32_t max_chunks, uint32_t n, uint32_t s1, uint32_t nb1,
+                                                 uint32_t seg_records, uint32_t nseg, uint32_t* __restrict__ segh) {
+    extern __shared__ uint32_t hh[];
+    const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
+    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        for (uint32_t b = threadIdx.x; b < nb1; b += TPB) hh[b] = 0;
+        __syncthreads();
+        const uint32_t lo = sg * seg_records;
+        const uint32_t hi = min(lo + seg_records, used);
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += TPB) {
+            const uint32_t x = lx[i];
+            if (x < n) atomicAdd(&hh[x >> s1], 1u);
+        }
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < nb1; b += TPB) segh[(size_t)sg * nb1 + b] = hh[b];
+        __syncthreads();
+    }
+}
+
+// One workgroup per coarse range: exclusive prefix of its column of segment
+// counts; the column total must equal the range's size.
+__global__ __launch_bounds__(1024) void k_p1_scan(uint32_t* __restrict__ segh, uint32_t nseg, uint32_t nb1,
+                                                  uint32_t n, uint32_t s1, Ctrl* ctrl, int check) {
+    __shared__ uint32_t sh[1024 / 64];
+    const uint32_t b = blockIdx.x;
+    const uint32_t per = (nseg + blockDim.x - 1) / blockDim.x;
+    const uint32_t a = min(threadIdx.x * per, nseg), e = min(a + per, nseg);
+    uint32_t sum = 0;
+    for (uint32_t i = a; i < e; ++i) sum += segh[(size_t)i * nb1 + b];
+    uint32_t total;
+    uint32_t run = block_exscan(sum, sh, &total);
+    for (uint32_t i = a; i < e; ++i) {
+        const uint32_t v = segh[(size_t)i * nb1 + b];
+        segh[(size_t)i * nb1 + b] = run;
+        run += v;
+    }
+    if (check && threadIdx.x == 0) {
+        const uint32_t lo = b << s1;
+        const uint32_t hi = min(lo + (1u << s1), n);
+        if (total != hi - lo) atomicOr(&ctrl->err, 128u);
+    }
+}
+
 template <bool W>
 __global__ __launch_bounds__(TPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
-                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out) {
+                                                const uint32_t* __restrict__ segh, uint32_t nseg,
+                                                PlaceArrays<W> out) {
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
-    const uint32_t T = PER * TPB;
+    constexpr uint32_t T = PER * TPB;
+    uint32_t* run_lds = reinterpret_cast<uint32_t*>(lds + place_lds_bytes(W, nb1));
     const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
     const uint32_t nw = S + ctrl->lv[0].H;
-    const uint32_t tiles = (used + T - 1) / T;
-    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
-        int64_t ss[PER];
+    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        for (uint32_t b = threadIdx.x; b < nb1; b += TPB) run_lds[b] = segh[(size_t)sg * nb1 + b];
+        __syncthreads();
+        const uint32_t t0 = sg * SEG_TILES;
+        for (uint32_t tile = t0; tile < t0 + SEG_TILES && tile * T < used; ++tile) {
+            uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+            int64_t ss[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const uint32_t i = tile * T + j * TPB + threadIdx.x;
-            xs[j] = (i < used) ? lg.x[i] : NONE;
-            if (xs[j] < n) {
-                const uint32_t w = lg.w[i];
-                typename L::Val off;
-                off.c = lg.c[i];
-                if constexpr (W) off.s = lg.s[i];
-                if (w < nw) {
-                    const typename L::Res b = res[w];
-                    const typename L::Val v = L::sub(L::val(b), off);
-                    rs[j] = v.c;
-                    ts[j] = b.root;
-                    if constexpr (W) ss[j] = v.s;
-                } else {
-                    rs[j] = NONE;
-                    ts[j] = NONE;
-                    if constexpr (W) ss[j] = INT64_MIN;
-                    atomicOr(&ctrl->err, 4u);
+            for (int j = 0; j < PER; ++j) {
+                const uint32_t i = tile * T + j * TPB + threadIdx.x;
+                xs[j] = (i < used) ? lg.x[i] : NONE;
+                if (xs[j] < n) {
+                    const uint32_t w = lg.w[i];
+                    typename L::Val off;
+                    off.c = lg.c[i];
+                    if constexpr (W) off.s = lg.s[i];
+                    if (w < nw) {
+                        const typename L::Res b = res[w];
+                        const typename L::Val v = L::sub(L::val(b), off);
+                        rs[j] = v.c;
+                        ts[j] = b.root;
+                        if constexpr (W) ss[j] = v.s;
+                    } else {
+                        rs[j] = NONE;
+                        ts[j] = NONE;
+                        if constexpr (W) ss[j] = INT64_MIN;
+                        atomicOr(&ctrl->err, 4u);
+                    }
+                    bs[j] = xs[j] >> s1;
                 }
-                bs[j] = xs[j] >> s1;
             }
+            place_tile<W, PER>(xs, rs, ts, ss, bs, nb1, s1, 0, n, nullptr, run_lds, out, ctrl, lds);
         }
-        place_tile<W, PER>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
     }
 }
 
@@ -662,7 +817,7 @@ __global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, u
                 bs[j] = (xs[j] >> s2) - c * fan;
             }
         }
-        place_tile<W, PER>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
+        place_tile<W, PER>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, nullptr, out, ctrl, lds);
     }
 }
 
@@ -829,10 +984,11 @@ static uint32_t persistent_grid(K kernel, int tpb) {
     return (uint32_t)nb * (uint32_t)device_cus();
 }
 
-static hipError_t fill(void* p, uint64_t bytes, uint32_t val, hipStream_t st) {
+static hipError_t fill(void* p, uint64_t bytes, uint32_t val, hipStream_t st, const Ctrl* skip_if_single = nullptr) {
     const uint64_t words = (bytes + 3) / 4;
     if (!words) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(words, TPB * 4)), dim3(TPB), 0, st, (uint32_t*)p, words, val);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(words, TPB * 4)), dim3(TPB), 0, st, (uint32_t*)p, words, val,
+                       skip_if_single);
     return hipGetLastError();
 }
 
@@ -911,16 +1067,25 @@ static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<
     char* ws = a.ws;
     hipStream_t st = a.stream;
     const uint32_t n = (uint32_t)p.m[0];
-    uint32_t* fill1 = reinterpret_cast<uint32_t*>(ws + p.off_fill);
-    uint32_t* fill2 = fill1 + p.nb1;
+    uint32_t* fill2 = reinterpret_cast<uint32_t*>(ws + p.off_fill) + p.nb1;
     const PlaceArrays<W> P = place_arrays<W>(ws, p.off_p);
     const PlaceArrays<W> Q = place_arrays<W>(ws, p.off_log);
     constexpr uint32_t T = (uint32_t)place_per<W>() * TPB;
     const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
-    const size_t l1 = place_lds_bytes(W, p.nb1);
+    const uint32_t seg_records = SEG_TILES * T;
+    const uint32_t nseg = (uint32_t)((cap + seg_records - 1) / seg_records);
+    uint32_t* segh = reinterpret_cast<uint32_t*>(ws + p.off_segh);
+    hipLaunchKernelGGL(k_p1_hist, dim3(std::min<uint32_t>(nseg, (uint32_t)device_cus() * 8)), dim3(TPB),
+                       p.nb1 * 4, st, reinterpret_cast<const uint32_t*>(ws + p.off_log[0]), ctrl, p.max_chunks, n,
+                       p.s1, p.nb1, seg_records, nseg, segh);
+    LR_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_p1_scan, dim3(p.nb1), dim3(1024), 0, st, segh, nseg, p.nb1, n, p.s1, ctrl,
+                       (int)a.validate);
+    LR_TRY(hipGetLastError());
+    const size_t l1 = place_lds_bytes(W, p.nb1) + 4 * (size_t)p.nb1;
     LR_TRY(allow_lds(k_place1<W>, l1));
-    hipLaunchKernelGGL(k_place1<W>, dim3(grid_for(cap, T)), dim3(TPB), l1, st, log_arrays<W>(ws, p.off_log),
-                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P);
+    hipLaunchKernelGGL(k_place1<W>, dim3(nseg), dim3(TPB), l1, st, log_arrays<W>(ws, p.off_log), p.max_chunks,
+                       res, S, ctrl, n, p.s1, p.nb1, segh, nseg, P);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
     const size_t l2 = place_lds_bytes(W, 1u << (p.s1 - p.s2));
@@ -956,14 +1121,24 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         for (int i = EV_DETECT; i < EV_COUNT; ++i) rec_ev(a, i);
         return hipSuccess;
     }
-    // level 0: predecessor marks
+    // level 0: initial elements. One list: its head from a streaming sum.
+    // Otherwise: predecessor marks (the one-list case skips these kernels).
     uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
-    LR_TRY(fill(hp0, n, 0u, st));
     {
         const bool vec = ((uintptr_t)a.succ % 16) == 0;
+        const uint32_t gs = std::min<uint32_t>(grid_for(n, TPB * 16), HEADSUM_BLOCKS);
+        uint32_t* part = reinterpret_cast<uint32_t*>(ws + p.off_hsum);
+        if (vec) hipLaunchKernelGGL(k_headsum<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
+        else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
+        LR_TRY(hipGetLastError());
+        const Sampler smp0{n, p.log2k[0], p.lseed[0]};
+        hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs, ctrl, smp0, ws + p.off_eb[0],
+                           (uint32_t)p.m[1], (uint32_t)p.rec_bytes);
+        LR_TRY(hipGetLastError());
+        LR_TRY(fill(hp0, n, 0u, st, ctrl));
         const uint32_t g = grid_for(n, TPB * 4 * 4);
-        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0);
-        else hipLaunchKernelGGL(k_detect<false>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0);
+        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0, ctrl);
+        else hipLaunchKernelGGL(k_detect<false>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0, ctrl);
         LR_TRY(hipGetLastError());
     }
     rec_ev(a, EV_DETECT);
@@ -976,12 +1151,13 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const bool more = l + 1 < p.levels;
         uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
         const uint32_t zw = more ? (S + 3) / 4 : 0;
-        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw);
+        const Ctrl* skip = (l == 0) ? ctrl : nullptr;
+        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw, skip);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, nullptr, 0u);
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
-                           (uint32_t)p.rec_bytes);
+                           (uint32_t)p.rec_bytes, skip);
         LR_TRY(hipGetLastError());
         if (a.validate && !(l == 0 && p.log0))
             LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st));

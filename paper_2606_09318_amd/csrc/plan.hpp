@@ -12,9 +12,13 @@ namespace lr {
 constexpr uint32_t TILE = 4096;            // elements per compaction tile
 constexpr uint32_t BASE_MAX_LIMIT = 16384; // one workgroup of 1024 lanes x 16 elements
 constexpr size_t ALIGN = 256;
+constexpr uint32_t HEADSUM_BLOCKS = 2048;      // partial sums of the one-list head search
 constexpr uint32_t LOG_CHUNK = 1024;         // records per visit-log chunk
 constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
 constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
+constexpr uint32_t SEG_TILES = 32;           // log tiles per segment of the first grouping pass
+// records per grouping tile (256 lanes x 16 unweighted / 8 weighted records)
+constexpr uint32_t place_tile_records(bool weighted) { return (weighted ? 8u : 16u) * 256u; }
 
 struct Plan {
     bool weighted = false;
@@ -28,6 +32,7 @@ struct Plan {
     size_t rec_bytes = 0;                  // slot / record / result size (8 or 16)
     // workspace layout (byte offsets)
     size_t off_ctrl = 0;
+    size_t off_hsum = 0;                   // HEADSUM_BLOCKS x 16 B partial sums
     size_t off_slot[LR_MAX_LEVELS] = {};
     size_t off_eb[LR_MAX_LEVELS] = {};
     size_t off_tile[LR_MAX_LEVELS] = {};
@@ -40,6 +45,7 @@ struct Plan {
     bool log0 = false;
     uint32_t chunk = 0, max_chunks = 0, s1 = 0, s2 = 0, nb1 = 0, nb2 = 0;
     size_t off_log[4] = {}, off_p[4] = {}, off_fill = 0;  // fill: nb1 then nb2 counters
+    size_t off_segh = 0;                                  // segment x coarse-range counts
     uint32_t batch_count = 0;
     size_t total = 0;
 };
