@@ -89,7 +89,7 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         const size_t cap = (size_t)p->max_chunks * LOG_CHUNK;
         uint32_t lg = 0;
         while ((1ull << lg) < n) ++lg;
-        p->s2 = (weighted ? 11u : 12u) + (lg > 28 ? 1u : 0u);  // fine range fits the LDS of one workgroup
+        p->s2 = PLACE_FINE_SHIFT;                               // a fine range's outputs fit one workgroup's LDS
         p->s1 = p->s2 + std::max(1u, (lg - p->s2 + 1) / 2);     // split the fan-out evenly over two passes
         p->nb1 = (uint32_t)((n + (1ull << p->s1) - 1) >> p->s1);
         p->nb2 = (uint32_t)((n + (1ull << p->s2) - 1) >> p->s2);
@@ -104,9 +104,6 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         }
         p->off_fill = off;
         off += align_up((size_t)(p->nb1 + p->nb2) * 4);
-        const size_t seg_records = (size_t)SEG_TILES * place_tile_records(weighted);
-        p->off_segh = off;
-        off += align_up(((cap + seg_records - 1) / seg_records) * p->nb1 * 4);
     }
     for (uint32_t l = 0; l < std::max(L, 1u); ++l) {
         const uint64_t ml = p->m[l];
@@ -173,6 +170,7 @@ static lr_status finish(hipError_t e, const RunArgs& a, const Plan& p) {
 static lr_status check_base_lds(const Plan& p) {
     const uint64_t mL = p.m[p.levels];
     if (base_lds_bytes(mL, p.weighted) > device_max_lds()) return LR_ERR_UNSUPPORTED;
+    if (p.log0 && ((size_t)1 << p.s2) * (p.weighted ? 16 : 8) > device_max_lds()) return LR_ERR_UNSUPPORTED;
     return LR_OK;
 }
 

@@ -571,18 +571,19 @@ __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __r
 
 // ---------------------------------------------------------- placement ----
 // Log mode, after the recursion: every visit-log record (x, walk, offset)
-// becomes (x, rank, root[, sum]) and must land at x. Records are grouped by
-// element range in two passes and a final pass writes each range of 2^s2
+// becomes (x, rank[, root][, sum]) and must land at x. Records are grouped by
+// element range in two passes and a third pass writes each range of 2^s2
 // elements from LDS, so every output line is written whole:
 //   place1  resolve each record against its walk's result (records of one
 //           walk sit close together in the log, so these gathers mostly hit
-//           the caches) and partition by x >> s1 (coarse ranges);
-//   place2  within each coarse range, partition by x >> s2 (fine ranges);
+//           the caches) and group by x >> s1 (coarse ranges);
+//   place2  within each coarse range, group by x >> s2 (fine ranges);
 //   place3  one workgroup per fine range: scatter into LDS by x, then write
 //           the outputs in order.
-// Every element is visited exactly once, so range r has exactly as many
-// records as ids; its region in the output array starts at r << shift and a
-// per-range fill counter hands out positions inside it.
+// Every element is visited exactly once, so range r receives exactly as many
+// records as it has ids; its group starts at r << shift and a fill counter per
+// range hands out positions inside it. All tiles append at the same few
+// frontiers, so the partially written lines there complete quickly.
 template <bool W>
 struct PlaceArrays {
     uint32_t* x;
@@ -594,25 +595,22 @@ struct PlaceArrays {
 template <bool W>
 constexpr int place_per() { return (int)place_tile_records(W) / TPB; }
 
-// LDS bytes of one placement tile over nb buckets (device and host agree).
-__host__ __device__ constexpr size_t place_lds_bytes(bool weighted, uint32_t nb) {
-    const size_t T = (size_t)(weighted ? 8 : 16) * TPB;
-    size_t o = 8 * (size_t)nb + 12 * T;
+// LDS bytes of one grouping tile over nb ranges (device and host agree).
+__host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, uint32_t nb) {
+    const size_t T = place_tile_records(weighted);
+    size_t o = 8 * (size_t)nb + (root ? 12 : 8) * T;
     if (weighted) o = ((o + 7) & ~(size_t)7) + 8 * T;
     return o + 2 * T;
 }
 
-// LDS counting sort of one tile by bucket, then coalesced writes of each
-// bucket's run to [region(b) + reserved(b), ...). Records with x >= n are
-// skipped. lo_bucket: global id of the tile's bucket 0 (place2).
-// Space in a bucket's region comes either from a global fill counter (one
-// atomic per bucket and tile) or, when `run` is given, from running offsets in
-// LDS that a prefix over segment histograms initialised (no atomics).
-template <bool W, int PER>
+// LDS counting sort of one tile by range, then coalesced writes of each
+// range's run at [group(lo_bucket + b) + reserved, ...), space reserved with
+// one atomic per range and tile.
+template <bool W, bool ROOT, int PER>
 __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER], const uint32_t (&ts)[PER],
-                           const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t region_shift,
-                           uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, uint32_t* run_lds,
-                           PlaceArrays<W> out, Ctrl* ctrl, unsigned char* lds) {
+                           const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t shift,
+                           uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
+                           Ctrl* ctrl, unsigned char* lds) {
     constexpr uint32_t T = (uint32_t)PER * TPB;
     size_t o = 0;
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + o);
@@ -623,8 +621,11 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     o += 4 * (size_t)T;
     uint32_t* sr = reinterpret_cast<uint32_t*>(lds + o);
     o += 4 * (size_t)T;
-    uint32_t* st = reinterpret_cast<uint32_t*>(lds + o);
-    o += 4 * (size_t)T;
+    uint32_t* st = nullptr;
+    if constexpr (ROOT) {
+        st = reinterpret_cast<uint32_t*>(lds + o);
+        o += 4 * (size_t)T;
+    }
     int64_t* sw = nullptr;
     if constexpr (W) {
         o = (o + 7) & ~(size_t)7;
@@ -642,7 +643,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     for (int j = 0; j < PER; ++j)
         if (xs[j] < n) lr[j] = atomicAdd(&hist[bs[j]], 1u);
     __syncthreads();
-    // exclusive scan of hist (each lane owns a run of consecutive buckets) and reservations
+    // exclusive scan of hist (each lane owns a run of consecutive ranges) and reservations
     const uint32_t chunk = (nb + TPB - 1) / TPB;
     const uint32_t a = min(t * chunk, nb), e = min(a + chunk, nb);
     uint32_t sum = 0;
@@ -651,12 +652,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     uint32_t run = block_exscan(sum, scan_sh, &total);
     for (uint32_t b = a; b < e; ++b) {
         const uint32_t h = hist[b];
-        if (run_lds) {
-            gbase[b] = run_lds[b];
-            run_lds[b] += h;
-        } else {
-            gbase[b] = h ? atomicAdd(&fill[lo_bucket + b], h) : 0u;
-        }
+        gbase[b] = h ? atomicAdd(&fill[lo_bucket + b], h) : 0u;
         hist[b] = run;
         run += h;
     }
@@ -668,7 +664,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
             const uint32_t p = hist[bs[j]] + lr[j];
             sx[p] = xs[j];
             sr[p] = rs[j];
-            st[p] = ts[j];
+            if constexpr (ROOT) st[p] = ts[j];
             if constexpr (W) sw[p] = ss[j];
             sb[p] = (uint16_t)bs[j];
         }
@@ -677,13 +673,13 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     const uint32_t cnt = tile_total;
     for (uint32_t i = t; i < cnt; i += TPB) {
         const uint32_t b = sb[i];
-        const uint64_t lo = (uint64_t)(lo_bucket + b) << region_shift;
-        const uint64_t hi = min(lo + (1ull << region_shift), (uint64_t)n);
+        const uint64_t lo = (uint64_t)(lo_bucket + b) << shift;
+        const uint64_t hi = min(lo + (1ull << shift), (uint64_t)n);
         const uint64_t p = lo + gbase[b] + (i - hist[b]);
         if (p < hi) {
             out.x[p] = sx[i];
             out.r[p] = sr[i];
-            out.t[p] = st[i];
+            if constexpr (ROOT) out.t[p] = st[i];
             if constexpr (W) out.s[p] = sw[i];
         } else {
             atomicOr(&ctrl->err, 64u);  // a range overflowed: some element was visited twice
@@ -692,110 +688,55 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     __syncthreads();
 }
 
-// place1 works on segments of SEG_TILES tiles of the visit log. k_p1_hist
-// counts each segment's records per coarse range, k_p1_scan turns the counts
-// into each segment's starting offset inside every range, and k_place1 then
-// writes a segment's runs at those offsets without atomics.
-
-__global__ __launch_bounds__(TPB) void k_p1_hist(const uint32_t* __restrict__ lx, const Ctrl* ctrl,
-                                                 uint32_t max_chunks, uint32_t n, uint32_t s1, uint32_t nb1,
-                                                 uint32_t seg_records, uint32_t nseg, uint32_t* __restrict__ segh) {
-    extern __shared__ uint32_t hh[];
-    const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
-    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        for (uint32_t b = threadIdx.x; b < nb1; b += TPB) hh[b] = 0;
-        __syncthreads();
-        const uint32_t lo = sg * seg_records;
-        const uint32_t hi = min(lo + seg_records, used);
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += TPB) {
-            const uint32_t x = lx[i];
-            if (x < n) atomicAdd(&hh[x >> s1], 1u);
-        }
-        __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nb1; b += TPB) segh[(size_t)sg * nb1 + b] = hh[b];
-        __syncthreads();
-    }
-}
-
-// One workgroup per coarse range: exclusive prefix of its column of segment
-// counts; the column total must equal the range's size.
-__global__ __launch_bounds__(1024) void k_p1_scan(uint32_t* __restrict__ segh, uint32_t nseg, uint32_t nb1,
-                                                  uint32_t n, uint32_t s1, Ctrl* ctrl, int check) {
-    __shared__ uint32_t sh[1024 / 64];
-    const uint32_t b = blockIdx.x;
-    const uint32_t per = (nseg + blockDim.x - 1) / blockDim.x;
-    const uint32_t a = min(threadIdx.x * per, nseg), e = min(a + per, nseg);
-    uint32_t sum = 0;
-    for (uint32_t i = a; i < e; ++i) sum += segh[(size_t)i * nb1 + b];
-    uint32_t total;
-    uint32_t run = block_exscan(sum, sh, &total);
-    for (uint32_t i = a; i < e; ++i) {
-        const uint32_t v = segh[(size_t)i * nb1 + b];
-        segh[(size_t)i * nb1 + b] = run;
-        run += v;
-    }
-    if (check && threadIdx.x == 0) {
-        const uint32_t lo = b << s1;
-        const uint32_t hi = min(lo + (1u << s1), n);
-        if (total != hi - lo) atomicOr(&ctrl->err, 128u);
-    }
-}
-
-template <bool W>
+template <bool W, bool ROOT>
 __global__ __launch_bounds__(TPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
-                                                const uint32_t* __restrict__ segh, uint32_t nseg,
-                                                PlaceArrays<W> out) {
+                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out) {
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
     constexpr uint32_t T = PER * TPB;
-    uint32_t* run_lds = reinterpret_cast<uint32_t*>(lds + place_lds_bytes(W, nb1));
     const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
     const uint32_t nw = S + ctrl->lv[0].H;
-    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        for (uint32_t b = threadIdx.x; b < nb1; b += TPB) run_lds[b] = segh[(size_t)sg * nb1 + b];
-        __syncthreads();
-        const uint32_t t0 = sg * SEG_TILES;
-        for (uint32_t tile = t0; tile < t0 + SEG_TILES && tile * T < used; ++tile) {
-            uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
-            int64_t ss[PER];
+    const uint32_t tiles = (used + T - 1) / T;
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+        int64_t ss[PER];
 #pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const uint32_t i = tile * T + j * TPB + threadIdx.x;
-                xs[j] = (i < used) ? lg.x[i] : NONE;
-                if (xs[j] < n) {
-                    const uint32_t w = lg.w[i];
-                    typename L::Val off;
-                    off.c = lg.c[i];
-                    if constexpr (W) off.s = lg.s[i];
-                    if (w < nw) {
-                        const typename L::Res b = res[w];
-                        const typename L::Val v = L::sub(L::val(b), off);
-                        rs[j] = v.c;
-                        ts[j] = b.root;
-                        if constexpr (W) ss[j] = v.s;
-                    } else {
-                        rs[j] = NONE;
-                        ts[j] = NONE;
-                        if constexpr (W) ss[j] = INT64_MIN;
-                        atomicOr(&ctrl->err, 4u);
-                    }
-                    bs[j] = xs[j] >> s1;
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tile * T + j * TPB + threadIdx.x;
+            xs[j] = (i < used) ? lg.x[i] : NONE;
+            if (xs[j] < n) {
+                const uint32_t w = lg.w[i];
+                typename L::Val off;
+                off.c = lg.c[i];
+                if constexpr (W) off.s = lg.s[i];
+                if (w < nw) {
+                    const typename L::Res b = res[w];
+                    const typename L::Val v = L::sub(L::val(b), off);
+                    rs[j] = v.c;
+                    ts[j] = b.root;
+                    if constexpr (W) ss[j] = v.s;
+                } else {
+                    rs[j] = NONE;
+                    ts[j] = NONE;
+                    if constexpr (W) ss[j] = INT64_MIN;
+                    atomicOr(&ctrl->err, 4u);
                 }
+                bs[j] = xs[j] >> s1;
             }
-            place_tile<W, PER>(xs, rs, ts, ss, bs, nb1, s1, 0, n, nullptr, run_lds, out, ctrl, lds);
         }
+        place_tile<W, ROOT, PER>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
     }
 }
 
-template <bool W>
+template <bool W, bool ROOT>
 __global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
                                                 uint32_t* __restrict__ fill2, PlaceArrays<W> out) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
-    const uint32_t T = PER * TPB;
+    constexpr uint32_t T = PER * TPB;
     const uint32_t tiles = (n + T - 1) / T;
     const uint32_t fan = 1u << (s1 - s2);
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -812,18 +753,18 @@ __global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, u
             }
             if (xs[j] < n) {
                 rs[j] = in.r[i];
-                ts[j] = in.t[i];
+                if constexpr (ROOT) ts[j] = in.t[i];
                 if constexpr (W) ss[j] = in.s[i];
                 bs[j] = (xs[j] >> s2) - c * fan;
             }
         }
-        place_tile<W, PER>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, nullptr, out, ctrl, lds);
+        place_tile<W, ROOT, PER>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
     }
 }
 
 // One workgroup per fine range of 2^s2 elements: place the records by x in
 // LDS, then write the outputs in element order.
-template <bool W, class Out>
+template <bool W, bool ROOT, class Out>
 __global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
                                                 const uint32_t* __restrict__ fill2, int check, Out out) {
     using L = Lay<W>;
@@ -838,17 +779,16 @@ __global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, u
         const uint32_t len = min(R, n - base);
         for (uint32_t i = t; i < len; i += TPB) {
             lr[i] = NONE;
-            lt[i] = NONE;
+            if constexpr (ROOT) lt[i] = NONE;
             if constexpr (W) ls[i] = INT64_MIN;
         }
         if (check && t == 0 && fill2[f] != len) atomicOr(&ctrl->err, 128u);
         __syncthreads();
         for (uint32_t i = t; i < len; i += TPB) {
-            const uint32_t x = in.x[base + i];
-            const uint32_t k = x - base;
+            const uint32_t k = in.x[base + i] - base;
             if (k < len) {
                 lr[k] = in.r[base + i];
-                lt[k] = in.t[base + i];
+                if constexpr (ROOT) lt[k] = in.t[base + i];
                 if constexpr (W) ls[k] = in.s[base + i];
             }
         }
@@ -859,7 +799,7 @@ __global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, u
                 typename L::Val v;
                 v.c = lr[i];
                 if constexpr (W) v.s = ls[i];
-                out.store(cur, base + i, v, lt[i]);
+                out.store(cur, base + i, v, ROOT ? lt[i] : NONE);
             }
         }
         __syncthreads();
@@ -1061,42 +1001,41 @@ static hipError_t allow_lds(K kern, size_t bytes) {
 
 // Level-0 propagation in log mode: resolve + coarse grouping, fine grouping,
 // placement. The fine-grouped records reuse the visit-log arrays.
-template <bool W, class Out0>
-static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S, Ctrl* ctrl,
-                            Out0 out0) {
+template <bool W, bool ROOT, class Out0>
+static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S,
+                              Ctrl* ctrl, Out0 out0) {
     char* ws = a.ws;
     hipStream_t st = a.stream;
     const uint32_t n = (uint32_t)p.m[0];
-    uint32_t* fill2 = reinterpret_cast<uint32_t*>(ws + p.off_fill) + p.nb1;
+    uint32_t* fill1 = reinterpret_cast<uint32_t*>(ws + p.off_fill);
+    uint32_t* fill2 = fill1 + p.nb1;
     const PlaceArrays<W> P = place_arrays<W>(ws, p.off_p);
     const PlaceArrays<W> Q = place_arrays<W>(ws, p.off_log);
-    constexpr uint32_t T = (uint32_t)place_per<W>() * TPB;
+    constexpr uint32_t T = place_tile_records(W);
     const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
-    const uint32_t seg_records = SEG_TILES * T;
-    const uint32_t nseg = (uint32_t)((cap + seg_records - 1) / seg_records);
-    uint32_t* segh = reinterpret_cast<uint32_t*>(ws + p.off_segh);
-    hipLaunchKernelGGL(k_p1_hist, dim3(std::min<uint32_t>(nseg, (uint32_t)device_cus() * 8)), dim3(TPB),
-                       p.nb1 * 4, st, reinterpret_cast<const uint32_t*>(ws + p.off_log[0]), ctrl, p.max_chunks, n,
-                       p.s1, p.nb1, seg_records, nseg, segh);
-    LR_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_p1_scan, dim3(p.nb1), dim3(1024), 0, st, segh, nseg, p.nb1, n, p.s1, ctrl,
-                       (int)a.validate);
-    LR_TRY(hipGetLastError());
-    const size_t l1 = place_lds_bytes(W, p.nb1) + 4 * (size_t)p.nb1;
-    LR_TRY(allow_lds(k_place1<W>, l1));
-    hipLaunchKernelGGL(k_place1<W>, dim3(nseg), dim3(TPB), l1, st, log_arrays<W>(ws, p.off_log), p.max_chunks,
-                       res, S, ctrl, n, p.s1, p.nb1, segh, nseg, P);
+    const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
+    LR_TRY(allow_lds(k_place1<W, ROOT>, l1));
+    hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), dim3(TPB), l1, st, log_arrays<W>(ws, p.off_log),
+                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
-    const size_t l2 = place_lds_bytes(W, 1u << (p.s1 - p.s2));
-    LR_TRY(allow_lds(k_place2<W>, l2));
-    hipLaunchKernelGGL(k_place2<W>, dim3(grid_for(n, T)), dim3(TPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2, Q);
+    const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
+    LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
+    hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), dim3(TPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2,
+                       Q);
     LR_TRY(hipGetLastError());
-    const size_t l3 = ((size_t)1 << p.s2) * (W ? 16 : 8);
-    LR_TRY(allow_lds(k_place3<W, Out0>, l3));
-    hipLaunchKernelGGL((k_place3<W, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), dim3(TPB),
-                       l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0);
+    const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
+    LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
+    hipLaunchKernelGGL((k_place3<W, ROOT, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)),
+                       dim3(TPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0);
     return hipGetLastError();
+}
+
+template <bool W, class Out0>
+static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S, Ctrl* ctrl,
+                            Out0 out0) {
+    if (a.desc || a.root) return run_place_t<W, true>(a, p, res, S, ctrl, out0);
+    return run_place_t<W, false>(a, p, res, S, ctrl, out0);
 }
 
 

@@ -16,7 +16,7 @@ constexpr uint32_t HEADSUM_BLOCKS = 2048;      // partial sums of the one-list h
 constexpr uint32_t LOG_CHUNK = 1024;         // records per visit-log chunk
 constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
 constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
-constexpr uint32_t SEG_TILES = 32;           // log tiles per segment of the first grouping pass
+constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
 // records per grouping tile (256 lanes x 16 unweighted / 8 weighted records)
 constexpr uint32_t place_tile_records(bool weighted) { return (weighted ? 8u : 16u) * 256u; }
 
@@ -40,12 +40,11 @@ struct Plan {
     // level 0 in log mode: the chase appends (element, walk, offset) records to
     // a chunked visit log instead of storing at random addresses; after the
     // recursion the records are resolved and grouped by element range in two
-    // passes (ranges of 2^s1, then 2^s2 ids) and written range by range.
-    // The fine-grouped records reuse the log arrays.
+    // passes (ranges of 2^s1, then 2^s2 ids) and written range by range from
+    // LDS. The fine-grouped records reuse the log arrays.
     bool log0 = false;
     uint32_t chunk = 0, max_chunks = 0, s1 = 0, s2 = 0, nb1 = 0, nb2 = 0;
     size_t off_log[4] = {}, off_p[4] = {}, off_fill = 0;  // fill: nb1 then nb2 counters
-    size_t off_segh = 0;                                  // segment x coarse-range counts
     uint32_t batch_count = 0;
     size_t total = 0;
 };
