@@ -81,8 +81,8 @@ def main():
     plan = lr.lr_plan_query(n)
     ws = lr.workspace(lr.lr_workspace_bytes(n), dev)
 
-    def step():
-        s = lr.lr_rank(succ, rank, root, ws, None, stream)
+    def step(want_root=False):
+        s = lr.lr_rank(succ, rank, root if want_root else None, ws, None, stream)
         if s:
             raise lr.LrError(s, "lr_rank")
 
@@ -101,10 +101,22 @@ def main():
     # correctness of what was timed: closed form of the generated order
     order = torch.from_numpy(L.order.view(np.int32)).to(dev)
     expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device=dev)
+    ok = bool(torch.equal(rank.index_select(0, order), expect))
+    if not ok:
+        raise SystemExit("bench: ranks do not match the closed form of the generated list")
+    # the same call with the root output as well (context; the configuration asks for ranks)
+    step(True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(5):
+        step(True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_root = ev0.elapsed_time(ev1) / 5
     ok = bool(torch.equal(rank.index_select(0, order), expect)) and bool((root == int(L.order[-1])).all())
     del order, expect
     if not ok:
-        raise SystemExit("bench: ranks do not match the closed form of the generated list")
+        raise SystemExit("bench: ranks/roots do not match the closed form of the generated list")
     if args.only_main:
         print(json.dumps({"metric": METRIC, "value": round(value, 4), "unit": "G elements/s",
                           "ms_per_step": round(ms, 4), "n": n}))
@@ -115,12 +127,14 @@ def main():
     popt = lr.make_opts(flags=lr.LR_PROFILE)
     phases = []
     for _ in range(5):
-        lr.lr_rank(succ, rank, root, ws, popt, stream)
+        lr.lr_rank(succ, rank, None, ws, popt, stream)
         phases.append(lr.lr_profile_last())
     ph = np.median(np.array(phases), axis=0)
     chase_ms = float(ph[2])
     S = int(plan.m[1])
-    chase_bytes = n * (4 + 8) + S * (8 + 1)      # succ gather + slot store per element; record + mark per walk
+    # per element: 4 B succ gather + 12 B visit-log record (element, walk, offset);
+    # per walk: 8 B walk record + 1 B predecessor mark
+    chase_bytes = n * (4 + 12) + S * (8 + 1)
     achieved = chase_bytes / (chase_ms * 1e-3) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "chase_traffic.json")
@@ -133,7 +147,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "chase_ms": round(chase_ms, 4),
                 "algorithmic_bytes": chase_bytes}
-    whole_bytes = n * (1 + 4 + 1 + 2 + 4 + 8 + 8 + 8 + 4 + 4)  # 44 B per element over the level-0 passes
+    # per element over the level-0 passes of the timed call (rank only): head sum 4 B read;
+    # chase 4 B gather + 12 B log write; place1 12 B read + 8 B write; place2 8 + 8;
+    # place3 8 B read + 4 B rank write  -> 68 B
+    whole_bytes = n * (4 + 4 + 12 + 12 + 8 + 8 + 8 + 8 + 4)
     extra = {"phases_ms": {"detect": round(float(ph[0]), 4), "heads": round(float(ph[1]), 4),
                            "chase_level0": round(chase_ms, 4), "upper_levels_and_base": round(float(ph[3]), 4),
                            "resolve_and_group": round(float(ph[4]), 4),
@@ -141,7 +158,8 @@ def main():
              "useful_bytes_gbs_whole_step": round(whole_bytes / (ms * 1e-3) / 1e9, 1),
              "plan": {"levels": plan.levels, "m": [int(plan.m[i]) for i in range(plan.levels + 1)],
                       "spacing": [int(plan.spacing[i]) for i in range(plan.levels)]},
-             "generation_s": round(gen_s, 2)}
+             "generation_s": round(gen_s, 2),
+             "rank_and_root": {"ms": round(ms_root, 4), "g_elements_per_s": round(n / (ms_root * 1e-3) / 1e9, 4)}}
 
     # GPU baseline: Wyllie pointer doubling on the same list
     del ws
@@ -189,7 +207,7 @@ def main():
     out = {"metric": METRIC, "value": round(value, 4), "unit": "G elements/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "single random list, n=2^28, uint32 succ (seed 2), rank + root",
+           "config": {"workload": "single random list, n=2^28, uint32 succ (seed 2), uint32 rank output",
                       "n": n, "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
