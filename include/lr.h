@@ -86,9 +86,11 @@ typedef struct lr_opts {
                                           default. Levels are added with the
                                           default spacing until the last level
                                           fits base_max. */
-    uint32_t refill;                   /* chase: idle lanes of a wavefront that
-                                          trigger fetching new walks (1..64);
-                                          0 = default */
+    uint32_t refill;                   /* chase: idle walk slots of a wavefront
+                                          that trigger taking new walks
+                                          (1 .. 64 x lane_walks); 0 = default (1) */
+    uint32_t lane_walks;               /* level-0 chase: walks each lane holds at
+                                          once (1 or 2); 0 = default (1) */
 } lr_opts;
 
 /* The plan a call will follow (host-only query, no device needed). */

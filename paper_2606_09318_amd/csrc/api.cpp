@@ -37,7 +37,7 @@ static uint32_t ilog2(uint32_t k) {
 // smallest spacing that brings it under base_max.
 static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max) {
     uint32_t k;
-    if (l == 0) k = (m >= (1ull << 24)) ? 64 : (m >= (1ull << 20) ? 32 : 16);
+    if (l == 0) k = (m >= (1ull << 26)) ? 64 : (m >= (1ull << 23) ? 32 : 16);
     else k = 16;
     uint32_t kmin = 2;
     while ((m + kmin - 1) / kmin > base_max && kmin < 4096) kmin <<= 1;
@@ -52,8 +52,11 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
     uint32_t bm = (o && o->base_max) ? o->base_max : (weighted ? 4096u : 8192u);
     if (bm < 1 || bm > BASE_MAX_LIMIT) return LR_ERR_INVALID_ARG;
     p->base_max = bm;
-    uint32_t rf = (o && o->refill) ? o->refill : 16u;
-    if (rf > 64) return LR_ERR_INVALID_ARG;
+    const uint32_t lw = (o && o->lane_walks) ? o->lane_walks : 1u;
+    if (lw > 2) return LR_ERR_INVALID_ARG;
+    p->lane_walks = lw;
+    uint32_t rf = (o && o->refill) ? o->refill : 1u;
+    if (rf > 64 * lw) return LR_ERR_INVALID_ARG;
     p->refill = rf;
     const uint64_t seed = o ? o->seed : 0;
     if (o) {
@@ -85,7 +88,8 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
     off += align_up((size_t)HEADSUM_BLOCKS * 16);
     if (p->log0) {
         p->chunk = LOG_CHUNK;
-        p->max_chunks = (uint32_t)((n + LOG_CHUNK - 64) / (LOG_CHUNK - 63)) + LOG_MAX_WAVES + 1;
+        // a chunk is given up only when a step's records (at most 64 per walk a lane holds) do not fit
+        p->max_chunks = (uint32_t)((n + LOG_CHUNK - 128) / (LOG_CHUNK - 127)) + LOG_MAX_WAVES + 1;
         const size_t cap = (size_t)p->max_chunks * LOG_CHUNK;
         uint32_t lg = 0;
         while ((1ull << lg) < n) ++lg;
@@ -369,6 +373,7 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     a.desc = dd;
     a.bases = db;
     a.count = count;
+    for (uint32_t i = 0; i < count; ++i) a.any_root |= reqs[i].root != nullptr;
     a.ws = w;
     a.stream = st;
     a.validate = opts && (opts->flags & LR_VALIDATE);

@@ -33,6 +33,7 @@ constexpr int CHASE_TPB = 256;
 constexpr int BASE_TPB = 1024;
 constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
 constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
+constexpr int PTPB = 512;                            // placement kernels: lanes per workgroup
 
 // ------------------------------------------------------------------ fill --
 __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,
@@ -297,8 +298,8 @@ __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__
 
 // ----------------------------------------------------------------- chase --
 // Persistent kernel: each lane holds one walk; a wavefront refills its idle
-// lanes from the level's walk queue with a single atomic (ballot + mbcnt
-// hand out consecutive walk ids) once `refill` lanes are idle. Each step is
+// lanes from its own range of walk ids (ballot + mbcnt hand out consecutive
+// ids) once `refill` lanes are idle. Each step is
 // one dependent gather (the record of x), one store (slot[x]) and a few ALU
 // operations for the ruler test, so the loop is bound by memory latency and
 // the lanes resident on the chip keep that many gathers in flight.
@@ -309,7 +310,10 @@ __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__
 // positions (mbcnt over the active lanes), so every step writes whole lines.
 // A chunk that cannot take another step's records is padded with NONE and a
 // new one is taken with one atomic.
-template <bool W, class Src, bool LOG>
+//
+// NW walks per lane: the lane issues the loads of all its walks before it
+// uses any of them, so NW independent gathers are in flight per lane.
+template <bool W, class Src, bool LOG, int NW>
 __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint32_t S, Ctrl* ctrl, int lvl,
                                                      typename Lay<W>::Slot* __restrict__ slot,
                                                      typename Lay<W>::Rec* __restrict__ eb,
@@ -320,40 +324,75 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
     const uint32_t lane = lane_id();
     const uint32_t total = S + ctrl->lv[lvl].H;
     const uint32_t m = smp.m;
-    uint32_t w = NONE, x = 0, steps = 0;
-    Val off = L::zero();
-    bool exhausted = false;
+    uint32_t w[NW], x[NW], steps[NW];
+    Val off[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        w[k] = NONE;
+        x[k] = 0;
+        steps[k] = 0;
+        off[k] = L::zero();
+    }
+    // Each wavefront owns a contiguous range of walk ids and refills its lanes
+    // from it: walk lengths are geometric with mean k, so a few hundred walks
+    // per wavefront already balance the work, and no queue is shared.
+    const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t per = total / nwave + 1;
+    const uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, total);
+    uint32_t cursor = (uint32_t)min<uint64_t>((uint64_t)gwave * per, total);
+    bool exhausted = cursor >= whi;
     uint32_t cbase = 0, cfill = LOG_CHUNK;  // visit-log chunk held by this wavefront (LOG mode)
     bool have = false, dead = false;
     for (;;) {
-        const uint64_t idle = __ballot(w == NONE);
-        if (idle == ~0ull && exhausted) break;
-        const uint32_t nidle = __popcll(idle);
-        if (!exhausted && (nidle >= refill || idle == ~0ull)) {
-            const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&ctrl->lv[lvl].q, nidle);
-            base = __shfl(base, leader);
-            if (base + nidle >= total) exhausted = true;
-            if (w == NONE) {
-                const uint32_t my = base + mbcnt(idle);
-                if (my < total) {
-                    w = my;
-                    off = L::zero();
-                    steps = 0;
-                    x = (my < S) ? smp.start(my) : reinterpret_cast<const uint32_t*>(eb + my)[0];
-                    if (x >= m) {  // corrupt start (cannot happen for valid input)
-                        eb[w] = L::rec(TERM | IDX, L::zero());
-                        atomicOr(&ctrl->err, 8u);
-                        w = NONE;
+        uint64_t idle[NW];
+        uint32_t nidle = 0;
+        bool all_idle = true;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            idle[k] = __ballot(w[k] == NONE);
+            nidle += __popcll(idle[k]);
+            all_idle &= idle[k] == ~0ull;
+        }
+        if (all_idle && exhausted) break;
+        if (!exhausted && (nidle >= refill || all_idle)) {
+            const uint32_t base = cursor;
+            cursor += nidle;
+            if (cursor >= whi) exhausted = true;
+            uint32_t acc = base;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                if (w[k] == NONE) {
+                    const uint32_t my = acc + mbcnt(idle[k]);
+                    if (my < whi) {
+                        w[k] = my;
+                        off[k] = L::zero();
+                        steps[k] = 0;
+                        x[k] = (my < S) ? smp.start(my) : reinterpret_cast<const uint32_t*>(eb + my)[0];
+                        if (x[k] >= m) {  // corrupt start (cannot happen for valid input)
+                            eb[w[k]] = L::rec(TERM | IDX, L::zero());
+                            atomicOr(&ctrl->err, 8u);
+                            w[k] = NONE;
+                        }
                     }
                 }
+                acc += __popcll(idle[k]);
             }
         }
-        uint32_t pos = 0;
+        uint32_t nxt[NW];
+        Val v[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            if (w[k] != NONE) src.load(x[k], nxt[k], v[k]);
+        uint32_t pos[NW];
         if constexpr (LOG) {
-            const uint64_t act = __ballot(w != NONE);
-            const uint32_t na = __popcll(act);
+            uint64_t act[NW];
+            uint32_t na = 0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                act[k] = __ballot(w[k] != NONE);
+                na += __popcll(act[k]);
+            }
             if (na && !dead) {
                 if (cfill + na > LOG_CHUNK) {
                     if (have)
@@ -371,40 +410,44 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                         have = true;
                     }
                 }
-                pos = cbase + cfill + mbcnt(act);
+                uint32_t acc = cbase + cfill;
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    pos[k] = acc + mbcnt(act[k]);
+                    acc += __popcll(act[k]);
+                }
                 cfill += na;
             }
         }
-        if (w != NONE) {
-            uint32_t nxt;
-            Val v;
-            src.load(x, nxt, v);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            if (w[k] == NONE) continue;
             if constexpr (LOG) {
                 if (!dead) {
-                    lg.x[pos] = x;
-                    lg.w[pos] = w;
-                    lg.c[pos] = off.c;
-                    if constexpr (W) lg.s[pos] = off.s;
+                    lg.x[pos[k]] = x[k];
+                    lg.w[pos[k]] = w[k];
+                    lg.c[pos[k]] = off[k].c;
+                    if constexpr (W) lg.s[pos[k]] = off[k].s;
                 }
             } else {
-                slot[x] = L::slot(w, off);
+                slot[x[k]] = L::slot(w[k], off[k]);
             }
-            if (nxt & TERM) {                       // x is a terminal: the walk ends on it
-                eb[w] = L::rec(nxt, L::add(off, v));
-                w = NONE;
+            if (nxt[k] & TERM) {                    // x is a terminal: the walk ends on it
+                eb[w[k]] = L::rec(nxt[k], L::add(off[k], v[k]));
+                w[k] = NONE;
             } else {
-                off = L::add(off, v);
-                if (++steps >= m) {                 // longer than the level: input has a cycle
-                    eb[w] = L::rec(TERM | IDX, off);
+                off[k] = L::add(off[k], v[k]);
+                if (++steps[k] >= m) {              // longer than the level: input has a cycle
+                    eb[w[k]] = L::rec(TERM | IDX, off[k]);
                     atomicOr(&ctrl->err, 8u);
-                    w = NONE;
-                } else if (smp.sampled(nxt)) {      // reached the next ruler
-                    const uint32_t c = nxt >> smp.log2k;
-                    eb[w] = L::rec(c, off);
-                    if (hp_next && w < S) hp_next[c] = 1;
-                    w = NONE;
+                    w[k] = NONE;
+                } else if (smp.sampled(nxt[k])) {   // reached the next ruler
+                    const uint32_t c = nxt[k] >> smp.log2k;
+                    eb[w[k]] = L::rec(c, off[k]);
+                    if (hp_next && w[k] < S) hp_next[c] = 1;
+                    w[k] = NONE;
                 } else {
-                    x = nxt;
+                    x[k] = nxt[k];
                 }
             }
         }
@@ -593,7 +636,7 @@ struct PlaceArrays {
 };
 
 template <bool W>
-constexpr int place_per() { return (int)place_tile_records(W) / TPB; }
+constexpr int place_per() { return (int)place_tile_records(W) / PTPB; }
 
 // LDS bytes of one grouping tile over nb ranges (device and host agree).
 __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, uint32_t nb) {
@@ -611,7 +654,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
                            const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t shift,
                            uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
                            Ctrl* ctrl, unsigned char* lds) {
-    constexpr uint32_t T = (uint32_t)PER * TPB;
+    constexpr uint32_t T = (uint32_t)PER * PTPB;
     size_t o = 0;
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + o);
     o += 4 * (size_t)nb;
@@ -633,18 +676,18 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
         o += 8 * (size_t)T;
     }
     uint16_t* sb = reinterpret_cast<uint16_t*>(lds + o);
-    __shared__ uint32_t scan_sh[TPB / 64];
+    __shared__ uint32_t scan_sh[PTPB / 64];
     __shared__ uint32_t tile_total;
     const uint32_t t = threadIdx.x;
     uint32_t lr[PER];
-    for (uint32_t b = t; b < nb; b += TPB) hist[b] = 0;
+    for (uint32_t b = t; b < nb; b += PTPB) hist[b] = 0;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; ++j)
         if (xs[j] < n) lr[j] = atomicAdd(&hist[bs[j]], 1u);
     __syncthreads();
     // exclusive scan of hist (each lane owns a run of consecutive ranges) and reservations
-    const uint32_t chunk = (nb + TPB - 1) / TPB;
+    const uint32_t chunk = (nb + PTPB - 1) / PTPB;
     const uint32_t a = min(t * chunk, nb), e = min(a + chunk, nb);
     uint32_t sum = 0;
     for (uint32_t b = a; b < e; ++b) sum += hist[b];
@@ -671,7 +714,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     }
     __syncthreads();
     const uint32_t cnt = tile_total;
-    for (uint32_t i = t; i < cnt; i += TPB) {
+    for (uint32_t i = t; i < cnt; i += PTPB) {
         const uint32_t b = sb[i];
         const uint64_t lo = (uint64_t)(lo_bucket + b) << shift;
         const uint64_t hi = min(lo + (1ull << shift), (uint64_t)n);
@@ -689,14 +732,14 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
 }
 
 template <bool W, bool ROOT>
-__global__ __launch_bounds__(TPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
+__global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
                                                 uint32_t* __restrict__ fill1, PlaceArrays<W> out) {
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
-    constexpr uint32_t T = PER * TPB;
+    constexpr uint32_t T = PER * PTPB;
     const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
     const uint32_t nw = S + ctrl->lv[0].H;
     const uint32_t tiles = (used + T - 1) / T;
@@ -705,7 +748,7 @@ __global__ __launch_bounds__(TPB) void k_place1(LogArrays<W> lg, uint32_t max_ch
         int64_t ss[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t i = tile * T + j * TPB + threadIdx.x;
+            const uint32_t i = tile * T + j * PTPB + threadIdx.x;
             xs[j] = (i < used) ? lg.x[i] : NONE;
             if (xs[j] < n) {
                 const uint32_t w = lg.w[i];
@@ -732,11 +775,11 @@ __global__ __launch_bounds__(TPB) void k_place1(LogArrays<W> lg, uint32_t max_ch
 }
 
 template <bool W, bool ROOT>
-__global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
+__global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
                                                 uint32_t* __restrict__ fill2, PlaceArrays<W> out) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
-    constexpr uint32_t T = PER * TPB;
+    constexpr uint32_t T = PER * PTPB;
     const uint32_t tiles = (n + T - 1) / T;
     const uint32_t fan = 1u << (s1 - s2);
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -745,7 +788,7 @@ __global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, u
         int64_t ss[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t i = tile * T + j * TPB + threadIdx.x;
+            const uint32_t i = tile * T + j * PTPB + threadIdx.x;
             xs[j] = (i < n) ? in.x[i] : NONE;
             if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
                 atomicOr(&ctrl->err, 64u);
@@ -765,7 +808,7 @@ __global__ __launch_bounds__(TPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, u
 // One workgroup per fine range of 2^s2 elements: place the records by x in
 // LDS, then write the outputs in element order.
 template <bool W, bool ROOT, class Out>
-__global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
+__global__ __launch_bounds__(PTPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
                                                 const uint32_t* __restrict__ fill2, int check, Out out) {
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -777,14 +820,14 @@ __global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, u
     for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
         const uint32_t base = f << s2;
         const uint32_t len = min(R, n - base);
-        for (uint32_t i = t; i < len; i += TPB) {
+        for (uint32_t i = t; i < len; i += PTPB) {
             lr[i] = NONE;
             if constexpr (ROOT) lt[i] = NONE;
             if constexpr (W) ls[i] = INT64_MIN;
         }
         if (check && t == 0 && fill2[f] != len) atomicOr(&ctrl->err, 128u);
         __syncthreads();
-        for (uint32_t i = t; i < len; i += TPB) {
+        for (uint32_t i = t; i < len; i += PTPB) {
             const uint32_t k = in.x[base + i] - base;
             if (k < len) {
                 lr[k] = in.r[base + i];
@@ -795,7 +838,7 @@ __global__ __launch_bounds__(TPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, u
         __syncthreads();
         if (t < len) {
             auto cur = out.begin(base + t);
-            for (uint32_t i = t; i < len; i += TPB) {
+            for (uint32_t i = t; i < len; i += PTPB) {
                 typename L::Val v;
                 v.c = lr[i];
                 if constexpr (W) v.s = ls[i];
@@ -958,10 +1001,10 @@ static LogArrays<W> log_arrays(char* ws, const size_t* off) {
     return a;
 }
 
-template <bool W, bool LOG, class Src>
+template <bool W, bool LOG, int NW, class Src>
 static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st) {
     using L = Lay<W>;
-    auto kern = k_chase<W, Src, LOG>;
+    auto kern = k_chase<W, Src, LOG, NW>;
     static uint32_t grid = 0;  // one per template instance
     if (!grid) {
         grid = persistent_grid(kern, CHASE_TPB);
@@ -1015,26 +1058,26 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
     const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
     LR_TRY(allow_lds(k_place1<W, ROOT>, l1));
-    hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), dim3(TPB), l1, st, log_arrays<W>(ws, p.off_log),
+    hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), dim3(PTPB), l1, st, log_arrays<W>(ws, p.off_log),
                        p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
     LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
-    hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), dim3(TPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2,
+    hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), dim3(PTPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2,
                        Q);
     LR_TRY(hipGetLastError());
     const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
     LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
     hipLaunchKernelGGL((k_place3<W, ROOT, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)),
-                       dim3(TPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0);
+                       dim3(PTPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0);
     return hipGetLastError();
 }
 
 template <bool W, class Out0>
 static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S, Ctrl* ctrl,
                             Out0 out0) {
-    if (a.desc || a.root) return run_place_t<W, true>(a, p, res, S, ctrl, out0);
+    if (a.desc ? a.any_root : a.root != nullptr) return run_place_t<W, true>(a, p, res, S, ctrl, out0);
     return run_place_t<W, false>(a, p, res, S, ctrl, out0);
 }
 
@@ -1104,14 +1147,16 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         if (l == 0) {
             if (p.log0) {
                 LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st));
-                LR_TRY((launch_chase<W, true>(p, 0, src0, smp, ctrl, ws, st)));
+                if (p.lane_walks == 2) LR_TRY((launch_chase<W, true, 2>(p, 0, src0, smp, ctrl, ws, st)));
+                else LR_TRY((launch_chase<W, true, 1>(p, 0, src0, smp, ctrl, ws, st)));
             } else {
-                LR_TRY((launch_chase<W, false>(p, 0, src0, smp, ctrl, ws, st)));
+                if (p.lane_walks == 2) LR_TRY((launch_chase<W, false, 2>(p, 0, src0, smp, ctrl, ws, st)));
+                else LR_TRY((launch_chase<W, false, 1>(p, 0, src0, smp, ctrl, ws, st)));
             }
             rec_ev(a, EV_CHASE0);
         } else {
             SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]), m};
-            LR_TRY((launch_chase<W, false>(p, (int)l, src, smp, ctrl, ws, st)));
+            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st)));
         }
     }
     {

@@ -17,8 +17,8 @@ constexpr uint32_t LOG_CHUNK = 1024;         // records per visit-log chunk
 constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
 constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
 constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
-// records per grouping tile (256 lanes x 16 unweighted / 8 weighted records)
-constexpr uint32_t place_tile_records(bool weighted) { return (weighted ? 8u : 16u) * 256u; }
+// records per grouping tile (512 lanes x 8 unweighted / 4 weighted records)
+constexpr uint32_t place_tile_records(bool weighted) { return (weighted ? 4u : 8u) * 512u; }
 
 struct Plan {
     bool weighted = false;
@@ -28,6 +28,7 @@ struct Plan {
     uint32_t log2k[LR_MAX_LEVELS] = {};
     uint32_t lseed[LR_MAX_LEVELS] = {};
     uint32_t refill = 0;
+    uint32_t lane_walks = 1;               // level-0 chase: walks held per lane (1 or 2)
     uint32_t ntiles[LR_MAX_LEVELS] = {};
     size_t rec_bytes = 0;                  // slot / record / result size (8 or 16)
     // workspace layout (byte offsets)

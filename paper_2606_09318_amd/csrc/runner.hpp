@@ -23,6 +23,7 @@ struct RunArgs {
     const BatchDesc* desc = nullptr;
     const uint32_t* bases = nullptr;
     uint32_t count = 0;
+    bool any_root = false;            // batch: some request wants roots
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     bool validate = false;

@@ -65,6 +65,23 @@ def test_batch_of_every_tiny_forest():
         assert np.array_equal(host_u32(r), er) and np.array_equal(host_u32(t), et)
 
 
+def test_batch_log_mode_without_roots():
+    """A batch whose concatenation takes the visit-log path, no root outputs."""
+    sizes = [1 << 21, 3, (1 << 21) + 999, 70000, 1]
+    items, inputs = [], []
+    for i, n in enumerate(sizes):
+        L = workloads.random_list(n, seed=500 + i) if i % 2 == 0 else workloads.block_list(n, 4096, seed=500 + i)
+        items.append((dev(L.succ), torch.full((n,), -3, dtype=torch.int32, device="cuda"), None))
+        inputs.append(L)
+    reqs = lr.requests(items)
+    assert sum(sizes) >= 1 << 22
+    ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items)))
+    assert lr.lr_rank_batch(reqs, len(items), ws) == lr.LR_OK
+    torch.cuda.synchronize()
+    for (s, r, t), L in zip(items, inputs):
+        assert np.array_equal(host_u32(r), oracle.rank(L.succ)[1])
+
+
 def test_batch_forced_levels():
     sizes = [3000, 50000, 1, 70000, 999]
     items, inputs = make_requests(sizes, seed=77)

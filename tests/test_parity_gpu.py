@@ -35,11 +35,12 @@ def test_random_list_sizes(n):
 
 
 @pytest.mark.parametrize("k0", [2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096])
-def test_spacing_invariance(k0):
-    """Outputs do not depend on the ruler spacing (several levels forced)."""
-    print(f"case: spacing k0={k0}", flush=True)
+@pytest.mark.parametrize("lane_walks", [1, 2])
+def test_spacing_invariance(k0, lane_walks):
+    """Outputs do not depend on the ruler spacing or walks per lane (several levels forced)."""
+    print(f"case: spacing k0={k0} lane_walks={lane_walks}", flush=True)
     L = workloads.random_list(200003, seed=7)
-    check_rank(L.succ, lr.make_opts(spacing=(k0,), base_max=64, seed=k0))
+    check_rank(L.succ, lr.make_opts(spacing=(k0,), base_max=64, seed=k0, lane_walks=lane_walks))
 
 
 @pytest.mark.parametrize("spacing,base", [((2, 2, 2, 2, 2), 8), ((4, 8, 2), 16), ((64, 2), 1), ((16,), 16384)])
@@ -206,11 +207,15 @@ def test_profile_phases():
 # Inputs of 2^22 elements and more take the visit-log path at level 0.
 
 @pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 12345, 5000011])
-def test_log_mode_random_lists(n):
-    print(f"case: log mode random list n={n}", flush=True)
+@pytest.mark.parametrize("lane_walks", [1, 2])
+def test_log_mode_random_lists(n, lane_walks):
+    print(f"case: log mode random list n={n} lane_walks={lane_walks}", flush=True)
     p = lr.lr_plan_query(n)
     assert p.levels >= 1
-    check_rank(workloads.random_list(n, seed=n % 1000).succ)
+    L = workloads.random_list(n, seed=n % 1000)
+    check_rank(L.succ, lr.make_opts(lane_walks=lane_walks))
+    st, r, _ = gpu_rank(L.succ, lr.make_opts(lane_walks=lane_walks), want_root=False)
+    assert st == lr.LR_OK and np.array_equal(r, oracle.rank(L.succ)[1])
 
 
 def test_log_mode_block_list_and_forest():
