@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-weighted", action="store_true")
     ap.add_argument("--serve-count", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
@@ -197,6 +198,9 @@ def main():
     del ws, order, succ, rank, root, B, L
     torch.cuda.empty_cache()
 
+    if not args.no_weighted:
+        extra.update(weighted_bench())
+
     if not args.no_serve:
         extra["serving"] = serve_bench(args.serve_count)
 
@@ -212,6 +216,82 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
+
+
+def weighted_bench() -> dict:
+    """The weighted workloads: the 2^27-element forest with int64 weights
+    (rank, root and exact sums) and the Euler tour of a 2^26-vertex random
+    recursive tree with +1/-1 int32 weights (sums give depths)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import certificate_gpu
+
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+
+    def timed(call, reps=5):
+        call()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            call()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    n = 1 << 27
+    F = workloads.forest(n, mean=64, n_long=16, long_len=1 << 20, seed=3)
+    succ = torch.from_numpy(F.succ.view(np.int32)).cuda()
+    w = torch.from_numpy(F.weight).cuda()
+    sm = torch.empty(n, dtype=torch.int64, device="cuda")
+    rk = torch.empty(n, dtype=torch.int32, device="cuda")
+    rt = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_I64))
+
+    def call():
+        st = lr.lr_prefix_sum(succ, w, sm, rk, rt, ws, None, stream)
+        if st:
+            raise lr.LrError(st, "lr_prefix_sum")
+    ms = timed(call)
+    ok = certificate_gpu(succ, rk, rt, sm, w)
+    out["forest_2p27_int64"] = {"ms": round(ms, 3), "g_elements_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                                "lists": int(F.starts.size - 1), "outputs": "rank, root, int64 sum",
+                                "certificate_ok": bool(ok)}
+    del F, succ, w, sm, rk, rt, ws
+    torch.cuda.empty_cache()
+
+    V = 1 << 26
+    E = workloads.euler_tour(V, seed=4)
+    m = E.succ.size
+    succ = torch.from_numpy(E.succ.view(np.int32)).cuda()
+    w = torch.from_numpy(E.weight).cuda()
+    sm = torch.empty(m, dtype=torch.int64, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(m, lr.LR_W_I32))
+
+    def call2():
+        st = lr.lr_prefix_sum(succ, w, sm, None, None, ws, None, stream)
+        if st:
+            raise lr.LrError(st, "lr_prefix_sum")
+    ms = timed(call2)
+    # depths from the sums: depth(v) = sum[head] - sum[down(v)] + 1; the head is the arc without predecessor
+    has_pred = torch.zeros(m, dtype=torch.bool, device="cuda")
+    nt = succ != torch.arange(m, dtype=torch.int32, device="cuda")
+    has_pred[succ[nt].long()] = True
+    head = int(torch.nonzero(~has_pred)[0])
+    down = torch.from_numpy(E.down_arc[1:].astype(np.int64)).cuda()
+    depth = sm[head] - sm.index_select(0, down) + 1
+    ok = bool(torch.equal(depth.cpu(), torch.from_numpy(E.depth[1:].astype(np.int64))))
+    out["euler_2p26_int32"] = {"ms": round(ms, 3), "g_elements_per_s": round(m / (ms * 1e-3) / 1e9, 3),
+                               "arcs": m, "outputs": "int64 sum (depths)", "depths_ok": ok}
+    del E, succ, w, sm, ws, has_pred, nt, down, depth
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve_bench(count: int) -> dict:

@@ -165,6 +165,21 @@ lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtyp
                                uint32_t* rank, uint32_t* root, uint64_t n,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* Plan autotuner (the paper fixes its ruler-count constants by a parameter
+ * study, Section 3 "Methodology"; this does the same on the caller's input).
+ * Times lr_rank (w == LR_W_NONE, weight NULL) or lr_prefix_sum (any other w)
+ * on `succ` for a set of candidate ruler spacings of the first two levels,
+ * keeping `base`'s seed, flags other than LR_VALIDATE, base_max and
+ * lane_walks, and writes the fastest option set to *best (its spacing list
+ * filled for every level). The trial calls write their outputs to the tail
+ * of `ws` (n x 4 B, weighted n x 8 B) and use the rest as their workspace;
+ * candidates that do not fit are skipped (LR_ERR_WORKSPACE if none fits).
+ * `ms` (may be NULL) receives up to `cap` timings, in the order the
+ * candidates were tried; *tried (may be NULL) their number. Synchronises
+ * `stream`. */
+lr_status lr_autotune(const uint32_t* succ, const void* weight, lr_wtype w, uint64_t n, void* ws, size_t ws_bytes,
+                      const lr_opts* base, lr_opts* best, double* ms, int cap, int* tried, void* stream);
+
 /* Per-phase device times (milliseconds) of the last call made with
  * LR_PROFILE on this thread: [0] predecessor marks, [1] head compaction,
  * [2] level-0 chase, [3] upper levels, base case and their propagation,

@@ -75,6 +75,7 @@ def load():
         "lr_rank_wyllie": (st, [vp, vp, vp, u64, vp, sz, vp]),
         "lr_prefix_sum_wyllie": (st, [vp, vp, st, vp, vp, vp, u64, vp, sz, vp]),
         "lr_profile_last": (st, [P(ctypes.c_double), st]),
+        "lr_autotune": (st, [vp, vp, st, u64, vp, sz, P(lr_opts), P(lr_opts), P(ctypes.c_double), st, P(st), vp]),
         "lr_server_create": (st, [P(lr_server_config), P(vp)]),
         "lr_server_submit": (st, [vp, P(lr_request), P(u64)]),
         "lr_server_poll": (st, [vp, u64, P(st), P(ctypes.c_double)]),
@@ -187,6 +188,17 @@ def lr_batch_workspace_bytes(reqs: ctypes.Array, count: int, opts=None) -> int:
 def lr_rank_batch(reqs: ctypes.Array, count: int, ws, opts=None, stream=None) -> int:
     return load().lr_rank_batch(reqs, count, _ptr(ws), ws.numel() * ws.element_size(), _opts(opts),
                                 _stream(stream))
+
+
+def lr_autotune(succ, weight, ws, base=None, stream=None):
+    """Time candidate ruler spacings on this input; returns (status, best lr_opts, timings in ms)."""
+    best = lr_opts()
+    ms = (ctypes.c_double * 64)()
+    tried = ctypes.c_int()
+    s = load().lr_autotune(_ptr(succ), _ptr(weight), _wtype(weight), succ.numel(), _ptr(ws),
+                           ws.numel() * ws.element_size(), _opts(base), ctypes.byref(best), ms, 64,
+                           ctypes.byref(tried), _stream(stream))
+    return s, best, list(ms[:tried.value])
 
 
 def lr_profile_last() -> list[float]:

@@ -1,0 +1,69 @@
+"""A ranking call captured into a HIP graph replays correctly (inputs changed
+between replays, other work and synchronisations in between), and the plan
+autotuner returns options whose results equal the oracle's."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2606_09318_amd as lr
+import workloads
+from gpu_util import dev, host_u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n", [1 << 16, (1 << 22) + 5])
+def test_graph_capture_and_replays(n):
+    print(f"case: graph capture n={n}", flush=True)
+    lists = [workloads.random_list(n, seed=60 + i) if i % 2 == 0 else workloads.block_list(n, 4096, seed=60 + i)
+             for i in range(4)]
+    succ = dev(lists[0].succ)
+    rank = torch.empty(n, dtype=torch.int32, device="cuda")
+    root = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(n))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        assert lr.lr_rank(succ, rank, root, ws, None, s) == lr.LR_OK  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        st = lr.lr_rank(succ, rank, root, ws, None, s)
+    assert st == lr.LR_OK
+    for i, L in enumerate(lists * 2):
+        succ.copy_(torch.from_numpy(L.succ.view(np.int32)))
+        rank.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _, er, et, _ = oracle.rank(L.succ)
+        assert np.array_equal(host_u32(rank), er), f"replay {i}"
+        assert np.array_equal(host_u32(root), et), f"replay {i}"
+        torch.empty(1 << 20, device="cuda").normal_()  # unrelated work between replays
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_autotune_returns_valid_options(weighted):
+    n = (1 << 22) + 77
+    print(f"case: autotune weighted={weighted}", flush=True)
+    F = workloads.forest(n, mean=64, n_long=2, long_len=1 << 20, seed=71)
+    succ = dev(F.succ)
+    w = dev(F.weight) if weighted else None
+    ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_I64, lr.make_opts(spacing=(16, 8))) + n * 8 + 4096)
+    st, best, ms = lr.lr_autotune(succ, w, ws)
+    assert st == lr.LR_OK, lr.status_string(st)
+    assert len(ms) >= 4 and all(t > 0 for t in ms)
+    ks = [best.spacing[i] for i in range(lr.LR_MAX_LEVELS) if best.spacing[i]]
+    assert ks and all(k & (k - 1) == 0 for k in ks)
+    p = lr.lr_plan_query(n, lr.LR_W_I64 if weighted else lr.LR_W_NONE, best)
+    assert [p.spacing[i] for i in range(p.levels)] == ks
+    ost, er, et, es = oracle.rank(F.succ, F.weight if weighted else None)
+    if weighted:
+        s_, r, t = lr.prefix_sum(succ, w, opts=best)
+        torch.cuda.synchronize()
+        assert np.array_equal(s_.cpu().numpy(), es) and np.array_equal(host_u32(r), er)
+    else:
+        r, t = lr.rank(succ, opts=best)
+        torch.cuda.synchronize()
+        assert np.array_equal(host_u32(r), er) and np.array_equal(host_u32(t), et)
