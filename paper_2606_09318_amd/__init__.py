@@ -12,7 +12,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblr.so")
+# LR_LIBRARY selects another build of the same library (tuning-constant sweeps)
+LIB_PATH = os.environ.get("LR_LIBRARY") or os.path.join(HERE, "liblr.so")
 
 LR_OK, LR_ERR_INVALID_ARG, LR_ERR_UNSUPPORTED, LR_ERR_WORKSPACE = 0, 1, 2, 3
 LR_ERR_OUT_OF_MEMORY, LR_ERR_BAD_LIST, LR_ERR_HIP = 4, 5, 6

@@ -22,9 +22,9 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", out]
+def _compile(src: str, defines=(), obj=OBJ) -> str:
+    out = os.path.join(obj, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", out]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -34,20 +34,23 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB):
-        return LIB
-    os.makedirs(OBJ, exist_ok=True)
+def build(force: bool = True, defines=(), lib: str = LIB) -> str:
+    """Compile and link liblr.so. `defines` (NAME=VALUE) override the tuning
+    constants (tile sizes, chunk size); `lib` is the output path."""
+    if not force and os.path.exists(lib):
+        return lib
+    obj = OBJ if lib == LIB else lib + ".obj"
+    os.makedirs(obj, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, defines, obj), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

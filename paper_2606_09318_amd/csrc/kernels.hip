@@ -29,11 +29,14 @@
 namespace lr {
 
 constexpr int TPB = 256;
-constexpr int CHASE_TPB = 256;
+#ifndef LR_CHASE_TPB
+#define LR_CHASE_TPB 256
+#endif
+constexpr int CHASE_TPB = LR_CHASE_TPB;
 constexpr int BASE_TPB = 1024;
 constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
 constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
-constexpr int PTPB = 512;                            // placement kernels: lanes per workgroup
+constexpr int PTPB = LR_PLACE_TPB;                   // placement kernels: lanes per workgroup
 
 // ------------------------------------------------------------------ fill --
 __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,

@@ -13,12 +13,23 @@ constexpr uint32_t TILE = 4096;            // elements per compaction tile
 constexpr uint32_t BASE_MAX_LIMIT = 16384; // one workgroup of 1024 lanes x 16 elements
 constexpr size_t ALIGN = 256;
 constexpr uint32_t HEADSUM_BLOCKS = 2048;      // partial sums of the one-list head search
-constexpr uint32_t LOG_CHUNK = 1024;         // records per visit-log chunk
+#ifndef LR_LOG_CHUNK
+#define LR_LOG_CHUNK 1024
+#endif
+constexpr uint32_t LOG_CHUNK = LR_LOG_CHUNK;  // records per visit-log chunk
 constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
 constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
 constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
-// records per grouping tile (512 lanes x 8 unweighted / 4 weighted records)
-constexpr uint32_t place_tile_records(bool weighted) { return (weighted ? 4u : 8u) * 512u; }
+// grouping tiles: LR_PLACE_TPB lanes x LR_PLACE_PER records (half as many weighted)
+#ifndef LR_PLACE_TPB
+#define LR_PLACE_TPB 512
+#endif
+#ifndef LR_PLACE_PER
+#define LR_PLACE_PER 8
+#endif
+constexpr uint32_t place_tile_records(bool weighted) {
+    return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * LR_PLACE_TPB;
+}
 
 struct Plan {
     bool weighted = false;
