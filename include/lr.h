@@ -67,7 +67,16 @@ typedef enum lr_wtype {
 
 enum {
     LR_VALIDATE = 1u,  /* check input and result; synchronises the stream */
-    LR_PROFILE = 2u    /* record per-phase times, read with lr_profile_last */
+    LR_PROFILE = 2u,   /* record per-phase times, read with lr_profile_last */
+    LR_LOCAL = 4u      /* tile-local contraction first (Section 2.3): chains of
+                          links that stay inside a tile of 4096 consecutive ids
+                          are contracted to their first element, the ruling-set
+                          levels rank the contracted list, and every element
+                          then takes its rank from its chain's first element.
+                          Pays off when most links are local (a list stored
+                          mostly in list order); costs about three extra
+                          streaming passes when few are. Results are identical
+                          either way. lr_rank, lr_prefix_sum, lr_rank_batch. */
 };
 
 #define LR_MAX_LEVELS 8

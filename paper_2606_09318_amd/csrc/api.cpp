@@ -79,7 +79,8 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         p->m[L] = m;
     }
     p->levels = L;
-    p->log0 = L >= 1 && n >= LOG_MIN_N;
+    p->local = o && (o->flags & LR_LOCAL);
+    p->log0 = !p->local && L >= 1 && n >= LOG_MIN_N;
     // layout
     size_t off = 0;
     p->off_ctrl = off;
@@ -125,6 +126,21 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
             p->off_tile[l] = off;
             off += align_up((size_t)(p->ntiles[l] + 1) * 4);
         }
+    }
+    if (p->local) {
+        p->lc_ntiles = (uint32_t)((n + LOCAL_TILE - 1) / LOCAL_TILE);
+        p->off_lc_cnt = off;
+        off += align_up((size_t)(p->lc_ntiles + 1) * 4);
+        p->off_lc_dir = off;
+        off += align_up((size_t)((n + 31) / 32) * 8);
+        p->off_lc_pos = off;
+        off += align_up((size_t)n * 4);
+        if (weighted) {
+            p->off_lc_wd = off;
+            off += align_up((size_t)n * 8);
+        }
+        p->off_lrec = off;
+        off += align_up(std::max<size_t>((size_t)n * p->rec_bytes, 16));
     }
     if (batch_count) {
         p->batch_count = batch_count;

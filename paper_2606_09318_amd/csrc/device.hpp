@@ -33,8 +33,11 @@ struct Ctrl {
     uint32_t nterm;                         // level 0: number of terminals (= number of lists)
     uint32_t single;                        // level 0: one list, whose head is known from hsum
     uint64_t hsum;                          // level 0: sum of ids minus sum of successors of non-terminals
-    uint32_t pad[10];
+    uint32_t dm[MAXL + 1];                  // element count per level when sizes are known only on the
+                                            // device (the contracted list of tile-local contraction)
+    uint32_t pad[1];
 };
+static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 
 // Visit log of the level-0 chase (log mode), structure of arrays: one record
 // (element, walk, offset) per visited element. The same layout holds the

@@ -240,8 +240,10 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* sh, uint3
 
 __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__ hp, Sampler smp,
                                                      uint32_t* __restrict__ tilecnt, uint32_t* zero_p,
-                                                     uint32_t zero_words, const Ctrl* skip_if_single) {
+                                                     uint32_t zero_words, const Ctrl* skip_if_single,
+                                                     const uint32_t* dm) {
     __shared__ uint32_t sh[TPB / 64];
+    if (dm) smp.m = dm[0];
     // clear the next level's predecessor marks (free memory at this point)
     if (zero_p) {
         const uint32_t stride = gridDim.x * blockDim.x;
@@ -283,9 +285,11 @@ __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tile
 // Writes walk start j into the first word of walk record S + j.
 __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__ hp, Sampler smp,
                                                      const uint32_t* __restrict__ tileoff, char* __restrict__ eb,
-                                                     uint32_t S, uint32_t rec_bytes, const Ctrl* skip_if_single) {
+                                                     uint32_t S, uint32_t rec_bytes, const Ctrl* skip_if_single,
+                                                     const uint32_t* dm) {
     __shared__ uint32_t sh[TPB / 64];
     if (skip_if_single && skip_if_single->single) return;
+    if (dm) { smp.m = dm[0]; S = dm[1]; }
     const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
     uint32_t bits;
     const uint32_t c = tile_heads(hp, smp, x0, bits);
@@ -321,9 +325,10 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                                                      typename Lay<W>::Slot* __restrict__ slot,
                                                      typename Lay<W>::Rec* __restrict__ eb,
                                                      uint8_t* __restrict__ hp_next, uint32_t refill,
-                                                     LogArrays<W> lg, uint32_t max_chunks) {
+                                                     LogArrays<W> lg, uint32_t max_chunks, const uint32_t* dm) {
     using L = Lay<W>;
     using Val = typename L::Val;
+    if (dm) { smp.m = src.m = dm[0]; S = dm[1]; }
     const uint32_t lane = lane_id();
     const uint32_t total = S + ctrl->lv[lvl].H;
     const uint32_t m = smp.m;
@@ -468,13 +473,15 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
 // them fixed, and after ceil(log2 len) rounds f[i] is i's terminal. The
 // result adds the terminal's own value (its weight at this level).
 template <bool W, class Src, class Out>
-__global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m, Ctrl* ctrl) {
+__global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m, Ctrl* ctrl, const uint32_t* dm) {
     using L = Lay<W>;
     using Val = typename L::Val;
     extern __shared__ __align__(16) unsigned char lds[];
+    // LDS is carved for the planned size m; a device-side size is at most that
     int64_t* ds = reinterpret_cast<int64_t*>(lds);
     uint32_t* dc = reinterpret_cast<uint32_t*>(lds + (W ? 8 * (size_t)m : 0));
     uint16_t* f = reinterpret_cast<uint16_t*>(lds + (W ? 8 * (size_t)m : 0) + 4 * (size_t)m);
+    if (dm) m = src.m = min(dm[0], m);
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < m; i += BASE_TPB) {
         uint32_t nxt;
@@ -553,8 +560,10 @@ __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m,
 // result of the ruler it ended on, or plus nothing when it ended on a
 // terminal (whose weight the chase already added).
 template <bool W>
-__global__ __launch_bounds__(TPB) void k_resolve(char* __restrict__ eb_raw, uint32_t S, const Ctrl* ctrl, int lvl) {
+__global__ __launch_bounds__(TPB) void k_resolve(char* __restrict__ eb_raw, uint32_t S, const Ctrl* ctrl, int lvl,
+                                                 const uint32_t* dm) {
     using L = Lay<W>;
+    if (dm) S = dm[1];
     auto* rec = reinterpret_cast<typename L::Rec*>(eb_raw);
     auto* res = reinterpret_cast<typename L::Res*>(eb_raw);
     const uint32_t H = ctrl->lv[lvl].H;
@@ -581,8 +590,9 @@ __global__ __launch_bounds__(TPB) void k_resolve(char* __restrict__ eb_raw, uint
 template <bool W, class Out>
 __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __restrict__ slot, uint32_t m,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
-                                                Ctrl* ctrl, int lvl, Out out) {
+                                                Ctrl* ctrl, int lvl, Out out, const uint32_t* dm) {
     using L = Lay<W>;
+    if (dm) { m = dm[0]; S = dm[1]; }
     const uint32_t nw = S + ctrl->lv[lvl].H;
     const uint32_t lane = lane_id();
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -926,6 +936,291 @@ __global__ __launch_bounds__(TPB) void k_batch_gather(const BatchDesc* __restric
     }
 }
 
+// ------------------------------------------------ tile-local contraction --
+// Section 2.3: sublists whose links stay inside one tile of LOCAL_TILE
+// consecutive ids are contracted before the ruling-set levels run. A local
+// chain starts at an element that no element of its tile links to and ends at
+// the first element whose successor lies outside the tile (or that is a
+// terminal). The contracted list has one element per chain start, linked to
+// the start that the chain's exit leads to, with the chain's link count (and
+// weight) as its value; after it is ranked, every element takes the rank of
+// its chain start minus its distance from that start. Elements are owned
+// lane-strided (element j * LC_TPB + lane), so every global access of these
+// kernels is coalesced.
+constexpr int LC_TPB = 512;
+constexpr uint32_t LC_T = LOCAL_TILE;
+constexpr int LC_PER = LC_T / LC_TPB;   // elements per lane
+constexpr int LC_ROUNDS = 14;           // > log2(LC_T): chains of a tile converge within this many rounds
+
+static_assert(LC_T == (1u << LOCAL_SHIFT) && LC_T <= 65536, "local tile");
+
+// start ids are compact: tile base (scanned start counts) + starts before the
+// element in its tile (word prefix + bits below it in its 32-id word)
+__device__ __forceinline__ uint32_t lc_below(uint2 d, uint32_t y) {
+    return d.y + __popc(d.x & ((1u << (y & 31)) - 1u));
+}
+
+// Pass 1: local predecessor marks -> start bits and counts.
+__global__ __launch_bounds__(LC_TPB) void k_lc_mark(const uint32_t* __restrict__ succ, uint32_t n,
+                                                    uint32_t* __restrict__ cnt, uint2* __restrict__ dir) {
+    __shared__ uint32_t hasp[LC_T / 32];
+    __shared__ uint32_t sh[LC_TPB / 64];
+    const uint32_t b = blockIdx.x * LC_T;
+    const uint32_t len = min(LC_T, n - b);
+    if (threadIdx.x < LC_T / 32) hasp[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t sv[LC_PER];
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+        const uint32_t i = j * LC_TPB + threadIdx.x;
+        sv[j] = (i < len) ? succ[b + i] : NONE;
+    }
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+        const uint32_t i = j * LC_TPB + threadIdx.x;
+        const uint32_t d = sv[j] - b;
+        if (i < len && d < len && d != i) atomicOr(&hasp[d >> 5], 1u << (d & 31));
+    }
+    __syncthreads();
+    const uint32_t wd = threadIdx.x;
+    const uint32_t nwd = (len + 31) / 32;
+    uint32_t bits = 0;
+    if (wd < nwd) {
+        const uint32_t left = len - wd * 32;
+        bits = ~hasp[wd] & (left >= 32 ? ~0u : ((1u << left) - 1u));
+    }
+    uint32_t total;
+    const uint32_t pre = block_exscan(__popc(bits), sh, &total);
+    if (wd < nwd) dir[(b >> 5) + wd] = make_uint2(bits, pre);
+    if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+// Exclusive scan of the per-tile start counts (one workgroup); publishes the
+// contracted list's size and the sizes of the ruling-set levels above it.
+struct LevelShifts { uint8_t lg[MAXL]; };
+
+__global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, uint32_t ntiles, Ctrl* ctrl,
+                                                  uint32_t levels, LevelShifts ks) {
+    __shared__ uint32_t sh[1024 / 64];
+    const uint32_t per = (ntiles + blockDim.x - 1) / blockDim.x;
+    const uint32_t a = threadIdx.x * per;
+    const uint32_t e = min(a + per, ntiles);
+    uint32_t s = 0;
+    for (uint32_t i = a; i < e; ++i) s += cnt[i];
+    uint32_t total;
+    uint32_t run = block_exscan(s, sh, &total);
+    for (uint32_t i = a; i < e; ++i) {
+        const uint32_t v = cnt[i];
+        cnt[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        cnt[ntiles] = total;
+        uint32_t m = total;
+        ctrl->dm[0] = m;
+        for (uint32_t l = 0; l < levels; ++l) {
+            m = (m + (1u << ks.lg[l]) - 1u) >> ks.lg[l];
+            ctrl->dm[l + 1] = m;
+        }
+        ctrl->single = 0;
+    }
+}
+
+// Zero the first dm bytes of p (the contracted level's predecessor marks).
+__global__ __launch_bounds__(TPB) void k_zero_dyn(uint32_t* __restrict__ p, const uint32_t* dm) {
+    const uint32_t words = (dm[0] + 3) / 4;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0;
+}
+
+// Pass 2: pointer jumping toward the chain starts in LDS. PD packs the
+// current jump target (low 16 bits, tile-relative) and the link count to it
+// (high 16 bits); starts point to themselves. Writes, per element, its chain
+// start's compact id and its distance from it (pos: start << 16 | distance,
+// NONE when the element is on a cycle), for weighted input also the weight
+// from the start (wd), and per chain the contracted record at the start's
+// compact id, marking the record it links to as having a predecessor.
+template <bool W, int WT>
+__global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict__ succ, const void* __restrict__ weight,
+                                                     uint32_t n, const uint32_t* __restrict__ cnt,
+                                                     const uint2* __restrict__ dir,
+                                                     typename Lay<W>::Rec* __restrict__ lrec, uint8_t* __restrict__ hp,
+                                                     uint32_t* __restrict__ pos, int64_t* __restrict__ wd,
+                                                     Ctrl* ctrl) {
+    using L = Lay<W>;
+    using Val = typename L::Val;
+    __shared__ uint32_t PD[LC_T];
+    __shared__ int64_t WS[W ? LC_T : 1];
+    __shared__ uint2 DIR[LC_T / 32];
+    const uint32_t b = blockIdx.x * LC_T;
+    const uint32_t len = min(LC_T, n - b);
+    const uint32_t base = cnt[blockIdx.x];
+    uint32_t sv[LC_PER];
+    int64_t wv[LC_PER];
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+        const uint32_t i = j * LC_TPB + threadIdx.x;
+        sv[j] = NONE;
+        wv[j] = 1;
+        if (i < len) {
+            sv[j] = succ[b + i];
+            if constexpr (WT == 1) wv[j] = static_cast<const int32_t*>(weight)[b + i];
+            if constexpr (WT == 2) wv[j] = static_cast<const int64_t*>(weight)[b + i];
+            PD[i] = i;
+            if constexpr (W) WS[i] = 0;
+        }
+    }
+    if (threadIdx.x < (len + 31) / 32) DIR[threadIdx.x] = dir[(b >> 5) + threadIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+        const uint32_t i = j * LC_TPB + threadIdx.x;
+        const uint32_t d = sv[j] - b;
+        if (i < len && d < len && d != i) {
+            PD[d] = i | (1u << 16);
+            if constexpr (W) WS[d] = wv[j];
+        }
+    }
+    __syncthreads();
+    uint32_t v[LC_PER];
+    int64_t ws[LC_PER];
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+        const uint32_t i = j * LC_TPB + threadIdx.x;
+        v[j] = (i < len) ? PD[i] : i;
+        ws[j] = 0;
+        if constexpr (W) if (i < len) ws[j] = WS[i];
+    }
+    for (int round = 0; round < LC_ROUNDS; ++round) {
+        int changed = 0;
+        if constexpr (!W) {
+            // in place: a 32-bit entry always holds a consistent (target, count)
+            // pair, so reading a neighbour's newer value only jumps further
+#pragma unroll
+            for (int j = 0; j < LC_PER; ++j) {
+                const uint32_t i = j * LC_TPB + threadIdx.x;
+                const uint32_t p = v[j] & 0xffffu;
+                if (i < len && p != i) {
+                    const uint32_t u = PD[p];
+                    const uint32_t q = u & 0xffffu;
+                    if (q != p) {
+                        v[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
+                        PD[i] = v[j];
+                        changed = 1;
+                    }
+                }
+            }
+        } else {
+            // target, count and weight live in two words: read all, then write all
+            uint32_t nv[LC_PER];
+            int64_t nw[LC_PER];
+#pragma unroll
+            for (int j = 0; j < LC_PER; ++j) {
+                const uint32_t i = j * LC_TPB + threadIdx.x;
+                const uint32_t p = v[j] & 0xffffu;
+                nv[j] = v[j];
+                nw[j] = ws[j];
+                if (i < len && p != i) {
+                    const uint32_t u = PD[p];
+                    const uint32_t q = u & 0xffffu;
+                    if (q != p) {
+                        nv[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
+                        nw[j] = ws[j] + WS[p];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < LC_PER; ++j) {
+                const uint32_t i = j * LC_TPB + threadIdx.x;
+                if (nv[j] != v[j]) {
+                    v[j] = nv[j];
+                    ws[j] = nw[j];
+                    PD[i] = v[j];
+                    WS[i] = ws[j];
+                    changed = 1;
+                }
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+        const uint32_t i = j * LC_TPB + threadIdx.x;
+        if (i >= len) continue;
+        const uint32_t x = b + i;
+        const uint32_t p = v[j] & 0xffffu;
+        const uint32_t dist = v[j] >> 16;
+        if ((PD[p] & 0xffffu) != p) {  // never reached a start: x is on a cycle inside the tile
+            pos[x] = NONE;
+            atomicOr(&ctrl->err, 8u);
+            continue;
+        }
+        const uint32_t lid = lc_below(DIR[p >> 5], p);
+        pos[x] = (lid << 16) | dist;
+        if constexpr (W) wd[x] = ws[j];
+        const uint32_t s = sv[j];
+        const uint32_t d = s - b;
+        if (d < len && d != i) continue;  // the chain continues inside the tile
+        Val val;
+        uint32_t nxt;
+        if (s == x || s >= n) {           // the chain ends at the terminal x
+            val.c = dist;
+            if constexpr (W) val.s = ws[j];
+            nxt = TERM | x;
+        } else {                          // the chain leaves the tile: link to the start s
+            val.c = dist + 1;
+            if constexpr (W) val.s = ws[j] + wv[j];
+            nxt = cnt[s >> LOCAL_SHIFT] + lc_below(dir[s >> 5], s);
+            if (hp) hp[nxt] = 1;
+        }
+        lrec[base + lid] = L::rec(nxt, val);
+    }
+}
+
+// Pass 3: every element from its chain start's result (lane-strided wave
+// tiles like the level expansion; the result gathers stay inside the tile's
+// compact range).
+template <bool W, class Out>
+__global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ pos, const int64_t* __restrict__ wd,
+                                                   const uint32_t* __restrict__ cnt,
+                                                   const typename Lay<W>::Res* __restrict__ res, uint32_t n,
+                                                   Ctrl* ctrl, Out out) {
+    using L = Lay<W>;
+    const uint32_t mc = ctrl->dm[0];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t ntile = (n + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
+    for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
+        const uint32_t base = tile * 64 * EXPAND_CH;
+        if (base + lane >= n) continue;
+        auto cur = out.begin(base + lane);
+        uint32_t pv[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            pv[j] = (i < n) ? pos[i] : NONE;
+        }
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            if (i >= n) continue;
+            const uint32_t c = (pv[j] == NONE) ? NONE : cnt[i >> LOCAL_SHIFT] + (pv[j] >> 16);
+            if (c < mc) {
+                const typename L::Res r = res[c];
+                typename L::Val v = L::val(r);
+                v.c -= pv[j] & 0xffffu;
+                if constexpr (W) v.s -= wd[i];
+                out.store(cur, i, v, r.root);
+            } else {
+                atomicOr(&ctrl->err, 4u);
+                out.store(cur, i, L::junk(), NONE);
+            }
+        }
+    }
+}
+
 // ============================================================== host side ==
 
 static int g_cus = 0;
@@ -983,14 +1278,15 @@ static inline void rec_ev(const RunArgs& a, int i) {
 }
 
 template <bool W, class Src, class Out>
-static hipError_t launch_base(Src src, Out out, uint32_t m, Ctrl* ctrl, hipStream_t st) {
+static hipError_t launch_base(Src src, Out out, uint32_t m, Ctrl* ctrl, hipStream_t st,
+                             const uint32_t* dm = nullptr) {
     const size_t lds = base_lds_bytes(m, W);
     auto kern = k_base<W, Src, Out>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(1), dim3(BASE_TPB), lds, st, src, out, m, ctrl);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(BASE_TPB), lds, st, src, out, m, ctrl, dm);
     return hipGetLastError();
 }
 
@@ -1005,7 +1301,8 @@ static LogArrays<W> log_arrays(char* ws, const size_t* off) {
 }
 
 template <bool W, bool LOG, int NW, class Src>
-static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st) {
+static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st,
+                               const uint32_t* dm = nullptr) {
     using L = Lay<W>;
     auto kern = k_chase<W, Src, LOG, NW>;
     static uint32_t grid = 0;  // one per template instance
@@ -1019,7 +1316,7 @@ static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl*
     uint8_t* hp_next = (l + 1 < (int)p.levels) ? reinterpret_cast<uint8_t*>(ws + p.off_slot[l + 1]) : nullptr;
     LogArrays<W> lg = LOG ? log_arrays<W>(ws, p.off_log) : LogArrays<W>{};
     hipLaunchKernelGGL(kern, dim3(grid), dim3(CHASE_TPB), 0, st, src, smp, S, ctrl, l, slot, eb, hp_next,
-                       p.refill, lg, p.max_chunks);
+                       p.refill, lg, p.max_chunks, dm);
     return hipGetLastError();
 }
 
@@ -1137,12 +1434,13 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
         const uint32_t zw = more ? (S + 3) / 4 : 0;
         const Ctrl* skip = (l == 0) ? ctrl : nullptr;
-        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw, skip);
+        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw, skip,
+                           nullptr);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
-                           (uint32_t)p.rec_bytes, skip);
+                           (uint32_t)p.rec_bytes, skip, nullptr);
         LR_TRY(hipGetLastError());
         if (a.validate && !(l == 0 && p.log0))
             LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st));
@@ -1173,7 +1471,7 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const uint32_t m = (uint32_t)p.m[l];
         const uint32_t S = (uint32_t)p.m[l + 1];
         hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
-                           ctrl, l);
+                           ctrl, l, nullptr);
         LR_TRY(hipGetLastError());
         const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
         const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
@@ -1184,12 +1482,13 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
                 LR_TRY((run_place<W, Out0>(a, p, res, S, ctrl, out0)));
             } else {
                 rec_ev(a, EV_PART);
-                hipLaunchKernelGGL((k_expand<W, Out0>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0);
+                hipLaunchKernelGGL((k_expand<W, Out0>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0,
+                                   nullptr);
             }
         } else {
             OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1])};
             hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, l,
-                               out);
+                               out, nullptr);
         }
         LR_TRY(hipGetLastError());
     }
@@ -1197,18 +1496,116 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     return hipSuccess;
 }
 
+// Tile-local contraction, then the ruling-set levels on the contracted list
+// (sizes from the device), then every element from its chain start.
+template <bool W, int WT, class Out0>
+static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
+    using L = Lay<W>;
+    const Plan& p = *a.plan;
+    char* ws = a.ws;
+    hipStream_t st = a.stream;
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
+    const uint32_t n = (uint32_t)p.m[0];
+    const uint32_t Lv = p.levels;
+    rec_ev(a, EV_START);
+    if (a.validate) {
+        LR_TRY(fill(ctrl, sizeof(Ctrl), 0u, st));
+        uint32_t* counts = reinterpret_cast<uint32_t*>(ws + p.off_slot[0]);
+        LR_TRY(fill(counts, (uint64_t)n * 4, 0u, st));
+        LR_TRY(run_validate_input(a.succ, n, counts, &ctrl->err, st));
+    }
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + p.off_lc_cnt);
+    uint2* dir = reinterpret_cast<uint2*>(ws + p.off_lc_dir);
+    uint32_t* pos = reinterpret_cast<uint32_t*>(ws + p.off_lc_pos);
+    int64_t* wd = W ? reinterpret_cast<int64_t*>(ws + p.off_lc_wd) : nullptr;
+    auto* lrec = reinterpret_cast<typename L::Rec*>(ws + p.off_lrec);
+    uint8_t* hp0 = Lv ? reinterpret_cast<uint8_t*>(ws + p.off_slot[0]) : nullptr;
+    hipLaunchKernelGGL(k_lc_mark, dim3(p.lc_ntiles), dim3(LC_TPB), 0, st, a.succ, n, cnt, dir);
+    LR_TRY(hipGetLastError());
+    LevelShifts ks{};
+    for (uint32_t l = 0; l < Lv; ++l) ks.lg[l] = (uint8_t)p.log2k[l];
+    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks);
+    LR_TRY(hipGetLastError());
+    if (hp0) {
+        hipLaunchKernelGGL(k_zero_dyn, dim3(grid_for(n / 4 + 1, TPB * 4)), dim3(TPB), 0, st,
+                           reinterpret_cast<uint32_t*>(hp0), (const uint32_t*)&ctrl->dm[0]);
+        LR_TRY(hipGetLastError());
+    }
+    rec_ev(a, EV_DETECT);
+    hipLaunchKernelGGL((k_lc_chain<W, WT>), dim3(p.lc_ntiles), dim3(LC_TPB), 0, st, a.succ, a.weight, n, cnt, dir,
+                       lrec, hp0, pos, wd, ctrl);
+    LR_TRY(hipGetLastError());
+    rec_ev(a, EV_HEADS);
+    for (uint32_t l = 0; l < Lv; ++l) {
+        const uint32_t* dm = &ctrl->dm[l];
+        const Sampler smp{(uint32_t)p.m[l], p.log2k[l], p.lseed[l]};
+        const uint32_t S = (uint32_t)p.m[l + 1];
+        const uint8_t* hp = reinterpret_cast<const uint8_t*>(ws + p.off_slot[l]);
+        uint32_t* tile = reinterpret_cast<uint32_t*>(ws + p.off_tile[l]);
+        const bool more = l + 1 < Lv;
+        uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
+        const uint32_t zw = more ? (S + 3) / 4 : 0;
+        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw, nullptr, dm);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
+                           (uint32_t)p.rec_bytes, nullptr, dm);
+        LR_TRY(hipGetLastError());
+        if (a.validate) LR_TRY(fill(ws + p.off_slot[l], (uint64_t)p.m[l] * p.rec_bytes, 0xffffffffu, st));
+        const auto* rec = (l == 0) ? lrec : reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]);
+        SrcLvl<W> src{rec, (uint32_t)p.m[l]};
+        LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm)));
+        if (l == 0) rec_ev(a, EV_CHASE0);
+    }
+    {
+        auto* top = Lv ? reinterpret_cast<typename L::Rec*>(ws + p.off_eb[Lv - 1]) : lrec;
+        SrcLvl<W> src{top, (uint32_t)p.m[Lv]};
+        OutLvl<W> out{reinterpret_cast<typename L::Res*>(top)};
+        LR_TRY((launch_base<W>(src, out, (uint32_t)p.m[Lv], ctrl, st, &ctrl->dm[Lv])));
+    }
+    for (int l = (int)Lv - 1; l >= 0; --l) {
+        const uint32_t m = (uint32_t)p.m[l];
+        const uint32_t S = (uint32_t)p.m[l + 1];
+        const uint32_t* dm = &ctrl->dm[l];
+        hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
+                           ctrl, l, dm);
+        LR_TRY(hipGetLastError());
+        const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
+        const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
+        auto* below = (l == 0) ? reinterpret_cast<typename L::Res*>(lrec)
+                               : reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1]);
+        OutLvl<W> out{below};
+        hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(grid_for(m, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot, m,
+                           res, S, ctrl, l, out, dm);
+        LR_TRY(hipGetLastError());
+    }
+    rec_ev(a, EV_UPPER);
+    rec_ev(a, EV_PART);
+    hipLaunchKernelGGL((k_lc_expand<W, Out0>), dim3(grid_for(n, TPB * EXPAND_CH)), dim3(TPB), 0, st, pos, wd, cnt,
+                       reinterpret_cast<const typename L::Res*>(lrec), n, ctrl, out0);
+    LR_TRY(hipGetLastError());
+    rec_ev(a, EV_EXPAND);
+    return hipSuccess;
+}
+
+template <bool W, int WT, class Out0>
+static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
+    return a.plan->local ? run_local_t<W, WT>(a, out0) : run_srs_t<W, WT>(a, out0);
+}
+
 hipError_t run_srs(const RunArgs& a) {
     const Plan& p = *a.plan;
     if (a.desc) {
         OutBatch out{a.desc, a.bases, a.count};
-        return run_srs_t<false, 0>(a, out);
+        return run_any_t<false, 0>(a, out);
     }
-    if (!p.weighted) return run_srs_t<false, 0>(a, OutUser<false>{a.rank, a.root, nullptr});
+    if (!p.weighted) return run_any_t<false, 0>(a, OutUser<false>{a.rank, a.root, nullptr});
     OutUser<true> out{a.rank, a.root, a.sum};
     switch (a.wt) {
-        case 1: return run_srs_t<true, 1>(a, out);
-        case 2: return run_srs_t<true, 2>(a, out);
-        default: return run_srs_t<true, 0>(a, out);
+        case 1: return run_any_t<true, 1>(a, out);
+        case 2: return run_any_t<true, 2>(a, out);
+        default: return run_any_t<true, 0>(a, out);
     }
 }
 

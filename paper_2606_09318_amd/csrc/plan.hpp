@@ -20,6 +20,8 @@ constexpr uint32_t LOG_CHUNK = LR_LOG_CHUNK;  // records per visit-log chunk
 constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
 constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
 constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
+constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
+constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
 // grouping tiles: LR_PLACE_TPB lanes x LR_PLACE_PER records (half as many weighted)
 #ifndef LR_PLACE_TPB
 #define LR_PLACE_TPB 512
@@ -58,6 +60,16 @@ struct Plan {
     uint32_t chunk = 0, max_chunks = 0, s1 = 0, s2 = 0, nb1 = 0, nb2 = 0;
     size_t off_log[4] = {}, off_p[4] = {}, off_fill = 0;  // fill: nb1 then nb2 counters
     uint32_t batch_count = 0;
+    // tile-local contraction (LR_LOCAL): the ruling-set levels run on the
+    // contracted list, whose size is known only on the device; m[] are then
+    // capacities (m[0] = n) and the kernels read the actual sizes from Ctrl.
+    bool local = false;
+    uint32_t lc_ntiles = 0;
+    size_t off_lc_cnt = 0;   // lc_ntiles + 1 start counts, scanned in place
+    size_t off_lc_dir = 0;   // per 32 ids: start bits and starts before the word in its tile
+    size_t off_lc_pos = 0;   // per element: chain start (compact, tile-relative) << 16 | distance
+    size_t off_lc_wd = 0;    // per element: weight from its chain start (weighted only)
+    size_t off_lrec = 0;     // contracted records, then their results
     size_t total = 0;
 };
 

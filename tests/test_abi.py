@@ -103,3 +103,17 @@ def test_batch_workspace_counts_all_requests():
     b1 = lr.lr_batch_workspace_bytes(reqs, 1)
     assert b3 > b1 > 0
     assert b3 >= lr.lr_workspace_bytes(321000)
+
+
+def test_local_contraction_workspace():
+    """LR_LOCAL sizes the contraction arrays (start counts, start bits, per
+    element chain position, contracted records) on top of the levels."""
+    for n, w in [(1, lr.LR_W_NONE), (5000, lr.LR_W_NONE), (1 << 20, lr.LR_W_NONE), (1 << 20, lr.LR_W_I64)]:
+        o = lr.make_opts(flags=lr.LR_LOCAL)
+        b = lr.lr_workspace_bytes(n, w, o)
+        rec = 16 if w != lr.LR_W_NONE else 8
+        assert b >= n * (4 + rec + (8 if w != lr.LR_W_NONE else 0)) + n // 4
+        p = lr.lr_plan_query(n, w, o)
+        assert p.workspace_bytes == b
+        plain = lr.lr_plan_query(n, w)
+        assert p.levels == plain.levels and list(p.m) == list(plain.m)

@@ -54,3 +54,22 @@ def test_serving_trace_sizes():
     t = np.array([r.arrival_s for r in tr])
     assert np.all(np.diff(t) > 0)
     assert {r.kind for r in tr} == {"random", "block"}
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.001, 0.25, 1.0])
+def test_gamma_order(gamma):
+    """List(n, gamma): a permutation that moves at most round(gamma n) ids, and
+    only ids of the sampled positions; gamma = 0 is the identity."""
+    n = 100003
+    o = workloads.gamma_order(n, gamma, seed=6)
+    assert np.array_equal(np.sort(o), np.arange(n, dtype=np.uint32))
+    moved = np.nonzero(o != np.arange(n))[0]
+    assert moved.size <= round(gamma * n)
+    assert np.array_equal(np.sort(o[moved]), moved)       # ids stay within the sampled positions
+    if gamma >= 0.25:
+        assert moved.size > 0.9 * gamma * n               # almost every sampled id moves
+    assert np.array_equal(o, workloads.gamma_order(n, gamma, seed=6))
+    L = workloads.gamma_list(n, gamma, seed=6)
+    assert np.array_equal(L.succ[L.order[:-1]], L.order[1:])
+    with pytest.raises(ValueError):
+        workloads.gamma_order(10, 1.5, seed=1)

@@ -48,6 +48,7 @@ def _load():
     lib.wl_perm.argtypes = [u64, u64, u64, vp]
     lib.wl_link_order.argtypes = [vp, u64, vp]
     lib.wl_block_order.argtypes = [u64, u64, u64, u64, vp]
+    lib.wl_gamma_order.argtypes = [u64, u64, u64, u64, vp]
     lib.wl_forest_lengths.restype = u64
     lib.wl_forest_lengths.argtypes = [u64, u64, ctypes.c_double, u64, u64, vp, u64]
     lib.wl_link_chunks.argtypes = [vp, vp, u64, vp]
@@ -97,6 +98,17 @@ def block_order(n: int, block: int, seed: int, stream: int = 0) -> np.ndarray:
     return out
 
 
+def gamma_order(n: int, gamma: float, seed: int, stream: int = 0) -> np.ndarray:
+    """Visiting order of List(n, gamma): identity order with round(gamma n)
+    uniformly chosen positions holding a random permutation of their ids."""
+    if not 0.0 <= gamma <= 1.0:
+        raise ValueError("gamma must lie in [0, 1]")
+    out = np.empty(n, dtype=np.uint32)
+    if n:
+        _load().wl_gamma_order(seed, stream, n, int(round(gamma * n)), _ptr(out))
+    return out
+
+
 @dataclass
 class ListInput:
     succ: np.ndarray          # uint32[n]
@@ -112,6 +124,13 @@ def random_list(n: int, seed: int = 1, stream: int = 0) -> ListInput:
 def block_list(n: int, block: int = 4096, seed: int = 2, stream: int = 1) -> ListInput:
     """One list with block locality (blocks of `block` ids, chained in random order)."""
     order = block_order(n, block, seed, stream)
+    return ListInput(link_order(order), order)
+
+
+def gamma_list(n: int, gamma: float, seed: int = 6, stream: int = 0) -> ListInput:
+    """The paper's List(n, gamma): locality from gamma = 0 (succ[i] = i + 1)
+    to gamma = 1 (a random list)."""
+    order = gamma_order(n, gamma, seed, stream)
     return ListInput(link_order(order), order)
 
 

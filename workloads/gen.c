@@ -113,6 +113,24 @@ void wl_block_order(uint64_t seed, uint64_t stream, uint64_t n, uint64_t block, 
     }
 }
 
+/* Order of the paper's List(n, gamma) (Section 3, input instances): the
+ * identity order 0, 1, ..., n-1, then the ids at k = round(gamma n) list
+ * positions, drawn uniformly without replacement, are permuted at random
+ * among those positions. k = 0 gives succ[i] = i + 1; k = n a random list. */
+void wl_gamma_order(uint64_t seed, uint64_t stream, uint64_t n, uint64_t k, uint32_t* order) {
+    if (n == 0) return;
+    if (k > n) k = n;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < (int64_t)n; j++) order[j] = (uint32_t)j;
+    if (k == 0) return;
+    prp_t pos, sh;
+    prp_init(&pos, seed, stream * 2 + 1, n);
+    prp_init(&sh, seed, stream * 2 + 2, k);
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < (int64_t)k; i++)
+        order[prp_eval(&pos, (uint64_t)i)] = (uint32_t)prp_eval(&pos, prp_eval(&sh, (uint64_t)i));
+}
+
 /* ------------------------------------------------------------ forest ---- */
 
 /* List lengths for a forest: lengths drawn from the geometric distribution on
