@@ -68,16 +68,20 @@ typedef enum lr_wtype {
 enum {
     LR_VALIDATE = 1u,  /* check input and result; synchronises the stream */
     LR_PROFILE = 2u,   /* record per-phase times, read with lr_profile_last */
-    LR_LOCAL = 4u      /* tile-local contraction first (Section 2.3): chains of
-                          links that stay inside a tile of 4096 consecutive ids
-                          are contracted to their first element, the ruling-set
-                          levels rank the contracted list, and every element
-                          then takes its rank from its chain's first element.
-                          Pays off when most links are local (a list stored
-                          mostly in list order); costs about three extra
-                          streaming passes when few are. Results are identical
-                          either way. lr_rank, lr_prefix_sum, lr_rank_batch. */
+    LR_LOCAL = 4u,     /* always contract tile-local chains first (Section 2.3) */
+    LR_NO_LOCAL = 8u   /* never contract tile-local chains */
 };
+/* Tile-local contraction (Section 2.3): chains of links that stay inside a
+ * tile of 4096 consecutive ids are contracted to their first element, the
+ * ruling-set levels rank the contracted list, and every element then takes
+ * its rank from its chain's first element. It pays off when most links are
+ * local (a list stored mostly in list order) and costs extra passes when few
+ * are. By default (neither flag) inputs of 2^21 elements or more choose on
+ * the device: the pass that looks for the head of a single list also counts
+ * the local links, and the contracted path runs when at least three quarters
+ * of the links are local; nothing is synchronised, both paths are enqueued
+ * and the one not taken returns at once. Results are identical in every
+ * mode. Applies to lr_rank, lr_prefix_sum and lr_rank_batch. */
 
 #define LR_MAX_LEVELS 8
 

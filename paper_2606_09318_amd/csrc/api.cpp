@@ -44,9 +44,8 @@ static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max) {
     return (kmin <= k) ? kmin : k;
 }
 
-lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, Plan* p) {
-    *p = Plan{};
-    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+// Levels, spacing and seeds for a level-0 list of (at most) m0 elements.
+static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool user_spacing, Plan* p) {
     p->weighted = weighted;
     p->rec_bytes = weighted ? 16 : 8;
     uint32_t bm = (o && o->base_max) ? o->base_max : (weighted ? 4096u : 8192u);
@@ -63,10 +62,10 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         for (int l = 0; l < LR_MAX_LEVELS && o->spacing[l]; ++l)
             if (!pow2_in(o->spacing[l], 2, 4096)) return LR_ERR_INVALID_ARG;
     }
-    uint64_t m = n;
+    uint64_t m = m0;
     uint32_t L = 0;
-    bool user = o && o->spacing[0];
-    p->m[0] = n;
+    bool user = user_spacing && o && o->spacing[0];
+    p->m[0] = m0;
     while (m > bm) {
         if (L >= (uint32_t)LR_MAX_LEVELS) return LR_ERR_UNSUPPORTED;
         uint32_t k;
@@ -79,14 +78,15 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         p->m[L] = m;
     }
     p->levels = L;
-    p->local = o && (o->flags & LR_LOCAL);
-    p->log0 = !p->local && L >= 1 && n >= LOG_MIN_N;
-    // layout
-    size_t off = 0;
-    p->off_ctrl = off;
-    off += align_up(sizeof(Ctrl));
-    p->off_hsum = off;
-    off += align_up((size_t)HEADSUM_BLOCKS * 16);
+    return LR_OK;
+}
+
+// Visit log and grouping areas (level 0 in log mode), then per level the
+// slot, walk-record and tile-count arrays. Returns the end offset.
+static size_t layout_levels(Plan* p, size_t off) {
+    const uint64_t n = p->m[0];
+    const uint32_t L = p->levels;
+    const bool weighted = p->weighted;
     if (p->log0) {
         p->chunk = LOG_CHUNK;
         // a chunk is given up only when a step's records (at most 64 per walk a lane holds) do not fit
@@ -127,20 +127,66 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
             off += align_up((size_t)(p->ntiles[l] + 1) * 4);
         }
     }
-    if (p->local) {
-        p->lc_ntiles = (uint32_t)((n + LOCAL_TILE - 1) / LOCAL_TILE);
-        p->off_lc_cnt = off;
-        off += align_up((size_t)(p->lc_ntiles + 1) * 4);
-        p->off_lc_dir = off;
-        off += align_up((size_t)((n + 31) / 32) * 8);
-        p->off_lc_pos = off;
-        off += align_up((size_t)n * 4);
-        if (weighted) {
-            p->off_lc_wd = off;
-            off += align_up((size_t)n * 8);
-        }
-        p->off_lrec = off;
-        off += align_up(std::max<size_t>((size_t)n * p->rec_bytes, 16));
+    return off;
+}
+
+// Tile-local contraction of an n-element input: start counts, start bits,
+// per-element chain positions (and weights), staged and final contracted
+// records (the latter for at most m[0] of them). Returns the end offset.
+static size_t layout_local(Plan* p, uint64_t n, size_t off) {
+    p->local = true;
+    p->lc_n = n;
+    p->lc_ntiles = (uint32_t)((n + LOCAL_TILE - 1) / LOCAL_TILE);
+    p->off_lc_cnt = off;
+    off += align_up((size_t)(p->lc_ntiles + 1) * 4);
+    p->off_lc_dir = off;
+    off += align_up((size_t)((n + 31) / 32) * 8);
+    p->off_lc_pos = off;
+    off += align_up((size_t)n * 4);
+    if (p->weighted) {
+        p->off_lc_wd = off;
+        off += align_up((size_t)n * 8);
+    }
+    p->off_lc_stage = off;
+    off += align_up(std::max<size_t>((size_t)n * p->rec_bytes, 16));
+    p->off_lrec = off;
+    off += align_up(std::max<size_t>((size_t)p->m[0] * p->rec_bytes, 16));
+    return off;
+}
+
+lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, PlanSet* ps) {
+    *ps = PlanSet{};
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    const bool force = o && (o->flags & LR_LOCAL);
+    const bool never = o && (o->flags & LR_NO_LOCAL);
+    if (force && never) return LR_ERR_INVALID_ARG;
+    Plan* p = &ps->p;
+    lr_status s = plan_levels(n, weighted, o, true, p);
+    if (s != LR_OK) return s;
+    size_t off = 0;
+    p->off_ctrl = off;
+    off += align_up(sizeof(Ctrl));
+    p->off_hsum = off;
+    off += align_up((size_t)HEADSUM_BLOCKS * 16);
+    const size_t body = off;
+    if (force) {
+        off = layout_levels(p, layout_local(p, n, body));
+    } else {
+        p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
+        off = layout_levels(p, body);
+    }
+    // Automatic contraction: the contracted path's arrays share the workspace
+    // with the plain path's (only one of them runs), after the common header.
+    ps->autol = !force && !never && p->levels >= 1 && n >= LOCAL_AUTO_MIN_N;
+    if (ps->autol) {
+        Plan* q = &ps->lp;
+        lr_opts lo = o ? *o : lr_opts{};
+        for (int l = 0; l < LR_MAX_LEVELS; ++l) lo.spacing[l] = 0;  // user spacing describes the plain levels
+        s = plan_levels((n + LOCAL_AUTO_DIV - 1) / LOCAL_AUTO_DIV, weighted, &lo, false, q);
+        if (s != LR_OK) return s;
+        q->off_ctrl = p->off_ctrl;
+        q->off_hsum = p->off_hsum;
+        off = std::max(off, layout_levels(q, layout_local(q, n, body)));
     }
     if (batch_count) {
         p->batch_count = batch_count;
@@ -152,7 +198,15 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
         off += align_up((size_t)(batch_count + 1) * 4);
     }
     p->total = off + ALIGN;  // room to align the caller's base pointer
+    ps->lp.total = p->total;
     return LR_OK;
+}
+
+lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, Plan* p) {
+    PlanSet ps;
+    const lr_status s = make_plans(n, weighted, o, batch_count, &ps);
+    *p = ps.p;
+    return s;
 }
 
 // ------------------------------------------------------------- profiling --
@@ -197,13 +251,16 @@ static lr_status check_base_lds(const Plan& p) {
 static lr_status rank_common(const uint32_t* succ, const void* weight, int wt, bool weighted, int64_t* sum,
                              uint32_t* rank, uint32_t* root, uint64_t n, void* ws, size_t ws_bytes,
                              const lr_opts* opts, void* stream) {
-    Plan p;
-    lr_status s = make_plan(n, weighted, opts, 0, &p);
+    PlanSet ps;
+    lr_status s = make_plans(n, weighted, opts, 0, &ps);
     if (s != LR_OK) return s;
+    const Plan& p = ps.p;
     if (!ws || ws_bytes < p.total) return LR_ERR_WORKSPACE;
     if ((s = check_base_lds(p)) != LR_OK) return s;
+    if (ps.autol && (s = check_base_lds(ps.lp)) != LR_OK) return s;
     RunArgs a;
     a.plan = &p;
+    a.lplan = ps.autol ? &ps.lp : nullptr;
     a.succ = succ;
     a.weight = weight;
     a.wt = wt;
@@ -358,11 +415,13 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     }
     if (N >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
     if (N == 0) return LR_OK;
-    Plan p;
-    lr_status s = make_plan(N, false, opts, count, &p);
+    PlanSet ps;
+    lr_status s = make_plans(N, false, opts, count, &ps);
     if (s != LR_OK) return s;
+    const Plan& p = ps.p;
     if (!ws || ws_bytes < p.total) return LR_ERR_WORKSPACE;
     if ((s = check_base_lds(p)) != LR_OK) return s;
+    if (ps.autol && (s = check_base_lds(ps.lp)) != LR_OK) return s;
     const size_t desc_bytes = (size_t)count * sizeof(BatchDesc);
     const size_t base_bytes = (size_t)(count + 1) * 4;
     if (host_cap < desc_bytes + base_bytes) return LR_ERR_INVALID_ARG;
@@ -385,6 +444,7 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     if (run_batch_gather(dd, db, count, (uint32_t)N, concat, st) != hipSuccess) return LR_ERR_HIP;
     RunArgs a;
     a.plan = &p;
+    a.lplan = ps.autol ? &ps.lp : nullptr;
     a.succ = concat;
     a.desc = dd;
     a.bases = db;

@@ -35,9 +35,18 @@ struct Ctrl {
     uint64_t hsum;                          // level 0: sum of ids minus sum of successors of non-terminals
     uint32_t dm[MAXL + 1];                  // element count per level when sizes are known only on the
                                             // device (the contracted list of tile-local contraction)
-    uint32_t pad[1];
+    uint32_t mode;                          // automatic contraction: 0 plain path, 1 tile-local contraction
 };
 static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
+
+// Device-side choice between two enqueued kernel sequences: a kernel whose
+// gate is set runs only when the word it points to holds `want`, and
+// otherwise returns before touching memory. A null gate always runs.
+struct Gate {
+    const uint32_t* p;
+    uint32_t want;
+    __device__ __forceinline__ bool off() const { return p && *p != want; }
+};
 
 // Visit log of the level-0 chase (log mode), structure of arrays: one record
 // (element, walk, offset) per visited element. The same layout holds the

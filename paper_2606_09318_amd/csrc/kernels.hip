@@ -40,7 +40,8 @@ constexpr int PTPB = LR_PLACE_TPB;                   // placement kernels: lanes
 
 // ------------------------------------------------------------------ fill --
 __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,
-                                              const Ctrl* skip_if_single) {
+                                              const Ctrl* skip_if_single, Gate gate) {
+    if (gate.off()) return;
     if (skip_if_single && skip_if_single->single) return;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n4 = words / 4;
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t
 // stores suffice (no atomics, no cross-XCD coherence traffic).
 template <bool VEC>
 __global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ succ, uint32_t m,
-                                                uint8_t* __restrict__ hp, const Ctrl* ctrl) {
+                                                uint8_t* __restrict__ hp, const Ctrl* ctrl, Gate gate) {
+    if (gate.off()) return;
     if (ctrl->single) return;
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,10 +93,10 @@ __global__ __launch_bounds__(TPB) void k_headsum(const uint32_t* __restrict__ su
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t hs = 0;
-    uint32_t nt = 0;
+    uint32_t nt = 0, loc = 0;
     auto one = [&](uint32_t x, uint32_t s) {
         if (s == x || s >= m) { ++nt; hs += x; }
-        else hs += (uint64_t)x - s;
+        else { hs += (uint64_t)x - s; loc += (s >> LOCAL_SHIFT) == (x >> LOCAL_SHIFT); }
     };
     uint32_t done = 0;
     if constexpr (VEC) {
@@ -110,47 +112,55 @@ __global__ __launch_bounds__(TPB) void k_headsum(const uint32_t* __restrict__ su
     }
     for (uint32_t i = done + g; i < m; i += stride) one(i, succ[i]);
     __shared__ uint64_t shs[TPB / 64];
-    __shared__ uint32_t snt[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64], sloc[TPB / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         hs += __shfl_xor(hs, o);
         nt += __shfl_xor(nt, o);
+        loc += __shfl_xor(loc, o);
     }
-    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
+    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; sloc[threadIdx.x >> 6] = loc; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
+        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; loc += sloc[i]; }
         partial[4 * blockIdx.x] = nt;
-        partial[4 * blockIdx.x + 1] = 0;
+        partial[4 * blockIdx.x + 1] = loc;
         reinterpret_cast<uint64_t*>(partial)[2 * blockIdx.x + 1] = hs;
     }
 }
 
-// Sums the partials; with exactly one terminal (and a head inside the range)
-// it publishes the head as the level's only initial-element walk.
+// Sums the partials. Automatic contraction (auto_cap > 0): the contracted
+// list has one element per element without a predecessor in its tile, i.e.
+// m minus the local links; the tile-local path is taken (mode 1) when that is
+// at most auto_cap. Otherwise, with exactly one terminal (and a head inside
+// the range), it publishes the head as the level's only initial-element walk.
 __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restrict__ partial, uint32_t nparts,
                                                        Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
-                                                       uint32_t rec_bytes) {
+                                                       uint32_t rec_bytes, uint32_t auto_cap) {
     uint64_t hs = 0;
-    uint32_t nt = 0;
+    uint32_t nt = 0, loc = 0;
     for (uint32_t i = threadIdx.x; i < nparts; i += TPB) {
         nt += partial[4 * i];
+        loc += partial[4 * i + 1];
         hs += reinterpret_cast<const uint64_t*>(partial)[2 * i + 1];
     }
     __shared__ uint64_t shs[TPB / 64];
-    __shared__ uint32_t snt[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64], sloc[TPB / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         hs += __shfl_xor(hs, o);
         nt += __shfl_xor(nt, o);
+        loc += __shfl_xor(loc, o);
     }
-    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
+    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; sloc[threadIdx.x >> 6] = loc; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
+        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; loc += sloc[i]; }
         ctrl->nterm = nt;
         ctrl->hsum = hs;
-        const bool single = nt == 1 && hs < smp.m;
+        const uint32_t mode = (auto_cap && smp.m - loc <= auto_cap) ? 1u : 0u;
+        ctrl->mode = mode;
+        const bool single = mode == 0 && nt == 1 && hs < smp.m;
         ctrl->single = single ? 1u : 0u;
         if (single) {
             const uint32_t h = (uint32_t)hs;
@@ -238,10 +248,47 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* sh, uint3
     return before + inc - v;
 }
 
+// In-place exclusive scan of a[0, n) by one workgroup of 1024 lanes; returns
+// the total to every lane. Each lane owns a contiguous run of a multiple of 4
+// entries, read and written as 16-byte vectors, so both passes issue all of a
+// lane's loads at once (a must be 16-byte aligned).
+__device__ uint32_t wg_exscan_inplace(uint32_t* __restrict__ a, uint32_t n, uint32_t* sh) {
+    const uint32_t per = (((n + 1023u) >> 10) + 3u) & ~3u;
+    const uint32_t lo = min(threadIdx.x * per, n);
+    const uint32_t hi = min(lo + per, n);
+    const uint32_t nv = (hi - lo) >> 2;  // whole vectors; the rest one by one
+    uint4* av = reinterpret_cast<uint4*>(a + lo);
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < nv; ++k) {
+        const uint4 v = av[k];
+        s += v.x + v.y + v.z + v.w;
+    }
+    for (uint32_t i = lo + 4 * nv; i < hi; ++i) s += a[i];
+    uint32_t total;
+    uint32_t run = block_exscan(s, sh, &total);
+    for (uint32_t k = 0; k < nv; ++k) {
+        const uint4 v = av[k];
+        uint4 o;
+        o.x = run;
+        o.y = o.x + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        run = o.w + v.w;
+        av[k] = o;
+    }
+    for (uint32_t i = lo + 4 * nv; i < hi; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    return total;
+}
+
 __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__ hp, Sampler smp,
-                                                     uint32_t* __restrict__ tilecnt, uint32_t* zero_p,
+                                                     uint32_t* __restrict__ tilecnt, uint32_t ntiles, uint32_t* zero_p,
                                                      uint32_t zero_words, const Ctrl* skip_if_single,
-                                                     const uint32_t* dm) {
+                                                     const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     __shared__ uint32_t sh[TPB / 64];
     if (dm) smp.m = dm[0];
     // clear the next level's predecessor marks (free memory at this point)
@@ -250,31 +297,23 @@ __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < zero_words; i += stride) zero_p[i] = 0;
     }
     if (skip_if_single && skip_if_single->single) return;
-    const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
-    uint32_t bits;
-    const uint32_t c = tile_heads(hp, smp, x0, bits);
-    const uint32_t t = block_sum(c, sh);
-    if (threadIdx.x == 0) tilecnt[blockIdx.x] = t;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint32_t bits;
+        const uint32_t c = tile_heads(hp, smp, tile * TILE + threadIdx.x * 16, bits);
+        const uint32_t t = block_sum(c, sh);
+        if (threadIdx.x == 0) tilecnt[tile] = t;
+        __syncthreads();  // sh is reused by the next tile
+    }
 }
 
 // One workgroup: exclusive scan of the tile counts in place; publishes the
 // walk count and resets the chase queue of this level.
 __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles,
-                                                     Ctrl* ctrl, int lvl) {
+                                                     Ctrl* ctrl, int lvl, Gate gate) {
+    if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
     if (lvl == 0 && ctrl->single) return;
-    const uint32_t per = (ntiles + blockDim.x - 1) / blockDim.x;
-    const uint32_t a = threadIdx.x * per;
-    const uint32_t b = min(a + per, ntiles);
-    uint32_t s = 0;
-    for (uint32_t i = a; i < b; ++i) s += tilecnt[i];
-    uint32_t total;
-    uint32_t run = block_exscan(s, sh, &total);
-    for (uint32_t i = a; i < b; ++i) {
-        const uint32_t v = tilecnt[i];
-        tilecnt[i] = run;
-        run += v;
-    }
+    const uint32_t total = wg_exscan_inplace(tilecnt, ntiles, sh);
     if (threadIdx.x == 0) {
         ctrl->lv[lvl].H = total;
         ctrl->lv[lvl].q = 0;
@@ -284,22 +323,26 @@ __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tile
 
 // Writes walk start j into the first word of walk record S + j.
 __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__ hp, Sampler smp,
-                                                     const uint32_t* __restrict__ tileoff, char* __restrict__ eb,
-                                                     uint32_t S, uint32_t rec_bytes, const Ctrl* skip_if_single,
-                                                     const uint32_t* dm) {
+                                                     const uint32_t* __restrict__ tileoff, uint32_t ntiles,
+                                                     char* __restrict__ eb, uint32_t S, uint32_t rec_bytes,
+                                                     const Ctrl* skip_if_single, const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     __shared__ uint32_t sh[TPB / 64];
     if (skip_if_single && skip_if_single->single) return;
     if (dm) { smp.m = dm[0]; S = dm[1]; }
-    const uint32_t x0 = blockIdx.x * TILE + threadIdx.x * 16;
-    uint32_t bits;
-    const uint32_t c = tile_heads(hp, smp, x0, bits);
-    uint32_t total;
-    uint32_t pos = tileoff[blockIdx.x] + block_exscan(c, sh, &total);
-    while (bits) {
-        const int j = __ffs(bits) - 1;
-        bits &= bits - 1;
-        *reinterpret_cast<uint32_t*>(eb + (size_t)(S + pos) * rec_bytes) = x0 + j;
-        ++pos;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t x0 = tile * TILE + threadIdx.x * 16;
+        uint32_t bits;
+        const uint32_t c = tile_heads(hp, smp, x0, bits);
+        uint32_t total;
+        uint32_t pos = tileoff[tile] + block_exscan(c, sh, &total);
+        while (bits) {
+            const int j = __ffs(bits) - 1;
+            bits &= bits - 1;
+            *reinterpret_cast<uint32_t*>(eb + (size_t)(S + pos) * rec_bytes) = x0 + j;
+            ++pos;
+        }
+        __syncthreads();  // sh is reused by the next tile
     }
 }
 
@@ -325,7 +368,8 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                                                      typename Lay<W>::Slot* __restrict__ slot,
                                                      typename Lay<W>::Rec* __restrict__ eb,
                                                      uint8_t* __restrict__ hp_next, uint32_t refill,
-                                                     LogArrays<W> lg, uint32_t max_chunks, const uint32_t* dm) {
+                                                     LogArrays<W> lg, uint32_t max_chunks, const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     using Val = typename L::Val;
     if (dm) { smp.m = src.m = dm[0]; S = dm[1]; }
@@ -473,7 +517,8 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
 // them fixed, and after ceil(log2 len) rounds f[i] is i's terminal. The
 // result adds the terminal's own value (its weight at this level).
 template <bool W, class Src, class Out>
-__global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m, Ctrl* ctrl, const uint32_t* dm) {
+__global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m, Ctrl* ctrl, const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     using Val = typename L::Val;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -561,7 +606,8 @@ __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m,
 // terminal (whose weight the chase already added).
 template <bool W>
 __global__ __launch_bounds__(TPB) void k_resolve(char* __restrict__ eb_raw, uint32_t S, const Ctrl* ctrl, int lvl,
-                                                 const uint32_t* dm) {
+                                                 const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     if (dm) S = dm[1];
     auto* rec = reinterpret_cast<typename L::Rec*>(eb_raw);
@@ -590,7 +636,8 @@ __global__ __launch_bounds__(TPB) void k_resolve(char* __restrict__ eb_raw, uint
 template <bool W, class Out>
 __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __restrict__ slot, uint32_t m,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
-                                                Ctrl* ctrl, int lvl, Out out, const uint32_t* dm) {
+                                                Ctrl* ctrl, int lvl, Out out, const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     if (dm) { m = dm[0]; S = dm[1]; }
     const uint32_t nw = S + ctrl->lv[lvl].H;
@@ -608,14 +655,22 @@ __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __r
             const uint32_t i = base + j * 64 + lane;
             if (i < m) sv[j] = slot[i];
         }
+        // all gathers before any store: the outputs may alias nothing here,
+        // but the compiler cannot know that and would order each gather
+        // after the previous element's store
+        typename L::Res rv[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            if (i < m && sv[j].w < nw) rv[j] = res[sv[j].w];
+        }
 #pragma unroll
         for (int j = 0; j < EXPAND_CH; ++j) {
             const uint32_t i = base + j * 64 + lane;
             if (i < m) {
                 const typename L::Slot s = sv[j];
                 if (s.w < nw) {
-                    const typename L::Res b = res[s.w];
-                    out.store(cur, i, L::sub(L::val(b), L::val(s)), b.root);
+                    out.store(cur, i, L::sub(L::val(rv[j]), L::val(s)), rv[j].root);
                 } else {
                     atomicOr(&ctrl->err, 4u);
                     out.store(cur, i, L::junk(), NONE);
@@ -748,7 +803,8 @@ template <bool W, bool ROOT>
 __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
-                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out) {
+                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
@@ -789,7 +845,8 @@ __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_c
 
 template <bool W, bool ROOT>
 __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
-                                                uint32_t* __restrict__ fill2, PlaceArrays<W> out) {
+                                                uint32_t* __restrict__ fill2, PlaceArrays<W> out, Gate gate) {
+    if (gate.off()) return;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
     constexpr uint32_t T = PER * PTPB;
@@ -822,7 +879,8 @@ __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, 
 // LDS, then write the outputs in element order.
 template <bool W, bool ROOT, class Out>
 __global__ __launch_bounds__(PTPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
-                                                const uint32_t* __restrict__ fill2, int check, Out out) {
+                                                const uint32_t* __restrict__ fill2, int check, Out out, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t R = 1u << s2;
@@ -944,15 +1002,26 @@ __global__ __launch_bounds__(TPB) void k_batch_gather(const BatchDesc* __restric
 // terminal). The contracted list has one element per chain start, linked to
 // the start that the chain's exit leads to, with the chain's link count (and
 // weight) as its value; after it is ranked, every element takes the rank of
-// its chain start minus its distance from that start. Elements are owned
-// lane-strided (element j * LC_TPB + lane), so every global access of these
-// kernels is coalesced.
+// its chain start minus its distance from that start.
+//   chain    one workgroup per tile: chains by pointer jumping in LDS; per
+//            element its chain start and distance; per 32 ids the start
+//            bits; per chain its record, staged at the tile's own offset
+//   scan     start counts -> compact ids of the first start of every tile
+//   compact  staged records -> compact positions, exit successors -> compact
+//            ids, predecessor marks for the first ruling-set level
+//   expand   every element from its chain start's result
+// Elements are owned lane-strided (element j * LC_TPB + lane), so every
+// global access of the tile kernels is coalesced.
 constexpr int LC_TPB = 512;
+#ifndef LR_LC_GRID_PER_CU
+#define LR_LC_GRID_PER_CU 64  // chain kernel workgroups per CU, each looping over tiles; 0 = one per tile
+#endif
 constexpr uint32_t LC_T = LOCAL_TILE;
 constexpr int LC_PER = LC_T / LC_TPB;   // elements per lane
 constexpr int LC_ROUNDS = 14;           // > log2(LC_T): chains of a tile converge within this many rounds
+constexpr int LC_CHUNKS = LC_T / 64;    // 64-id chunks of a tile (one wave ballot each)
 
-static_assert(LC_T == (1u << LOCAL_SHIFT) && LC_T <= 65536, "local tile");
+static_assert(LC_T == (1u << LOCAL_SHIFT) && LC_T <= 65536 && LC_CHUNKS <= 64, "local tile");
 
 // start ids are compact: tile base (scanned start counts) + starts before the
 // element in its tile (word prefix + bits below it in its 32-id word)
@@ -960,39 +1029,174 @@ __device__ __forceinline__ uint32_t lc_below(uint2 d, uint32_t y) {
     return d.y + __popc(d.x & ((1u << (y & 31)) - 1u));
 }
 
-// Pass 1: local predecessor marks -> start bits and counts.
-__global__ __launch_bounds__(LC_TPB) void k_lc_mark(const uint32_t* __restrict__ succ, uint32_t n,
-                                                    uint32_t* __restrict__ cnt, uint2* __restrict__ dir) {
-    __shared__ uint32_t hasp[LC_T / 32];
-    __shared__ uint32_t sh[LC_TPB / 64];
-    const uint32_t b = blockIdx.x * LC_T;
-    const uint32_t len = min(LC_T, n - b);
-    if (threadIdx.x < LC_T / 32) hasp[threadIdx.x] = 0;
-    __syncthreads();
-    uint32_t sv[LC_PER];
+// Chains by pointer jumping toward their starts. PD packs the current jump
+// target (low 16 bits, tile-relative) and the link count to it (high 16
+// bits); starts point to themselves. Writes pos (start's tile-relative
+// compact index << 16 | distance, NONE on a cycle inside the tile), wd (weight
+// from the start, weighted only), the tile's start bits and word prefixes
+// (dir), its start count (cnt), and per chain its record at stage[tile *
+// LC_T + index] with the exit's successor still a global id.
+template <bool W, int WT>
+__global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict__ succ, const void* __restrict__ weight,
+                                                     uint32_t n, uint32_t ntiles, uint32_t* __restrict__ cnt,
+                                                     uint2* __restrict__ dir,
+                                                     typename Lay<W>::Rec* __restrict__ stage,
+                                                     uint32_t* __restrict__ pos, int64_t* __restrict__ wd,
+                                                     Ctrl* ctrl, Gate gate) {
+    if (gate.off()) return;
+    using L = Lay<W>;
+    using Val = typename L::Val;
+    __shared__ uint32_t PD[LC_T];
+    __shared__ int64_t WS[W ? LC_T : 1];
+    __shared__ uint2 DIR[LC_T / 32];
+    __shared__ uint32_t CH[LC_CHUNKS];
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t b = tile * LC_T;
+        const uint32_t len = min(LC_T, n - b);
+        const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        uint32_t sv[LC_PER];
+        int64_t wv[LC_PER];
 #pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-        const uint32_t i = j * LC_TPB + threadIdx.x;
-        sv[j] = (i < len) ? succ[b + i] : NONE;
-    }
+        for (int j = 0; j < LC_PER; ++j) {
+            const uint32_t i = j * LC_TPB + threadIdx.x;
+            sv[j] = NONE;
+            wv[j] = 1;
+            if (i < len) {
+                sv[j] = succ[b + i];
+                if constexpr (WT == 1) wv[j] = static_cast<const int32_t*>(weight)[b + i];
+                if constexpr (WT == 2) wv[j] = static_cast<const int64_t*>(weight)[b + i];
+                PD[i] = i;
+                if constexpr (W) WS[i] = 0;
+            }
+        }
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-        const uint32_t i = j * LC_TPB + threadIdx.x;
-        const uint32_t d = sv[j] - b;
-        if (i < len && d < len && d != i) atomicOr(&hasp[d >> 5], 1u << (d & 31));
+        for (int j = 0; j < LC_PER; ++j) {
+            const uint32_t i = j * LC_TPB + threadIdx.x;
+            const uint32_t d = sv[j] - b;
+            if (i < len && d < len && d != i) {
+                PD[d] = i | (1u << 16);
+                if constexpr (W) WS[d] = wv[j];
+            }
+        }
+        __syncthreads();
+        uint32_t v[LC_PER];
+        int64_t ws[LC_PER];
+#pragma unroll
+        for (int j = 0; j < LC_PER; ++j) {
+            const uint32_t i = j * LC_TPB + threadIdx.x;
+            v[j] = (i < len) ? PD[i] : i;
+            ws[j] = 0;
+            if constexpr (W) if (i < len) ws[j] = WS[i];
+            // chunk j * 8 + wave covers ids [64 (j * 8 + wave), +64), lane = id offset
+            const uint64_t starts = __ballot(i < len && (v[j] >> 16) == 0);
+            if (lane == 0) CH[j * (LC_TPB / 64) + wave] = __popcll(starts);
+            if (lane < 2) DIR[2 * (j * (LC_TPB / 64) + wave) + lane] = make_uint2((uint32_t)(starts >> (32 * lane)), 0u);
+        }
+        __syncthreads();
+        if (wave == 0) {  // exclusive scan of the 64 chunk counts, then the word prefixes
+            const uint32_t c = (lane < (uint32_t)LC_CHUNKS) ? CH[lane] : 0u;
+            uint32_t inc = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o);
+                if (lane >= (uint32_t)o) inc += y;
+            }
+            if (lane < (uint32_t)LC_CHUNKS) {
+                const uint32_t pre = inc - c;
+                const uint32_t lo = DIR[2 * lane].x;
+                DIR[2 * lane].y = pre;
+                DIR[2 * lane + 1].y = pre + __popc(lo);
+            }
+            if (lane == 63) cnt[tile] = inc;
+        }
+        for (int round = 0; round < LC_ROUNDS; ++round) {
+            int changed = 0;
+            if constexpr (!W) {
+                // in place: a 32-bit entry always holds a consistent (target, count)
+                // pair, so reading a neighbour's newer value only jumps further
+#pragma unroll
+                for (int j = 0; j < LC_PER; ++j) {
+                    const uint32_t i = j * LC_TPB + threadIdx.x;
+                    const uint32_t p = v[j] & 0xffffu;
+                    if (i < len && p != i) {
+                        const uint32_t u = PD[p];
+                        const uint32_t q = u & 0xffffu;
+                        if (q != p) {
+                            v[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
+                            PD[i] = v[j];
+                            changed = 1;
+                        }
+                    }
+                }
+            } else {
+                // target, count and weight live in two words: read all, then write all
+                uint32_t nv[LC_PER];
+                int64_t nw[LC_PER];
+#pragma unroll
+                for (int j = 0; j < LC_PER; ++j) {
+                    const uint32_t i = j * LC_TPB + threadIdx.x;
+                    const uint32_t p = v[j] & 0xffffu;
+                    nv[j] = v[j];
+                    nw[j] = ws[j];
+                    if (i < len && p != i) {
+                        const uint32_t u = PD[p];
+                        const uint32_t q = u & 0xffffu;
+                        if (q != p) {
+                            nv[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
+                            nw[j] = ws[j] + WS[p];
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < LC_PER; ++j) {
+                    const uint32_t i = j * LC_TPB + threadIdx.x;
+                    if (nv[j] != v[j]) {
+                        v[j] = nv[j];
+                        ws[j] = nw[j];
+                        PD[i] = v[j];
+                        WS[i] = ws[j];
+                        changed = 1;
+                    }
+                }
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
+        if (threadIdx.x < (len + 31) / 32) dir[(b >> 5) + threadIdx.x] = DIR[threadIdx.x];
+#pragma unroll
+        for (int j = 0; j < LC_PER; ++j) {
+            const uint32_t i = j * LC_TPB + threadIdx.x;
+            if (i >= len) continue;
+            const uint32_t x = b + i;
+            const uint32_t p = v[j] & 0xffffu;
+            const uint32_t dist = v[j] >> 16;
+            if ((PD[p] & 0xffffu) != p) {  // never reached a start: x is on a cycle inside the tile
+                pos[x] = NONE;
+                atomicOr(&ctrl->err, 8u);
+                continue;
+            }
+            const uint32_t lid = lc_below(DIR[p >> 5], p);
+            pos[x] = (lid << 16) | dist;
+            if constexpr (W) wd[x] = ws[j];
+            const uint32_t s = sv[j];
+            const uint32_t d = s - b;
+            if (d < len && d != i) continue;  // the chain continues inside the tile
+            Val val;
+            uint32_t nxt;
+            if (s == x || s >= n) {           // the chain ends at the terminal x
+                val.c = dist;
+                if constexpr (W) val.s = ws[j];
+                nxt = TERM | x;
+            } else {                          // the chain leaves the tile for the start s
+                val.c = dist + 1;
+                if constexpr (W) val.s = ws[j] + wv[j];
+                nxt = s;
+            }
+            stage[(size_t)tile * LC_T + lid] = L::rec(nxt, val);
+        }
+        __syncthreads();  // LDS is reused by the next tile
     }
-    __syncthreads();
-    const uint32_t wd = threadIdx.x;
-    const uint32_t nwd = (len + 31) / 32;
-    uint32_t bits = 0;
-    if (wd < nwd) {
-        const uint32_t left = len - wd * 32;
-        bits = ~hasp[wd] & (left >= 32 ? ~0u : ((1u << left) - 1u));
-    }
-    uint32_t total;
-    const uint32_t pre = block_exscan(__popc(bits), sh, &total);
-    if (wd < nwd) dir[(b >> 5) + wd] = make_uint2(bits, pre);
-    if (threadIdx.x == 0) cnt[blockIdx.x] = total;
 }
 
 // Exclusive scan of the per-tile start counts (one workgroup); publishes the
@@ -1000,20 +1204,10 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_mark(const uint32_t* __restrict__
 struct LevelShifts { uint8_t lg[MAXL]; };
 
 __global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, uint32_t ntiles, Ctrl* ctrl,
-                                                  uint32_t levels, LevelShifts ks) {
+                                                  uint32_t levels, LevelShifts ks, Gate gate) {
+    if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
-    const uint32_t per = (ntiles + blockDim.x - 1) / blockDim.x;
-    const uint32_t a = threadIdx.x * per;
-    const uint32_t e = min(a + per, ntiles);
-    uint32_t s = 0;
-    for (uint32_t i = a; i < e; ++i) s += cnt[i];
-    uint32_t total;
-    uint32_t run = block_exscan(s, sh, &total);
-    for (uint32_t i = a; i < e; ++i) {
-        const uint32_t v = cnt[i];
-        cnt[i] = run;
-        run += v;
-    }
+    const uint32_t total = wg_exscan_inplace(cnt, ntiles, sh);
     if (threadIdx.x == 0) {
         cnt[ntiles] = total;
         uint32_t m = total;
@@ -1027,154 +1221,36 @@ __global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, ui
 }
 
 // Zero the first dm bytes of p (the contracted level's predecessor marks).
-__global__ __launch_bounds__(TPB) void k_zero_dyn(uint32_t* __restrict__ p, const uint32_t* dm) {
+__global__ __launch_bounds__(TPB) void k_zero_dyn(uint32_t* __restrict__ p, const uint32_t* dm, Gate gate) {
+    if (gate.off()) return;
     const uint32_t words = (dm[0] + 3) / 4;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0;
 }
 
-// Pass 2: pointer jumping toward the chain starts in LDS. PD packs the
-// current jump target (low 16 bits, tile-relative) and the link count to it
-// (high 16 bits); starts point to themselves. Writes, per element, its chain
-// start's compact id and its distance from it (pos: start << 16 | distance,
-// NONE when the element is on a cycle), for weighted input also the weight
-// from the start (wd), and per chain the contracted record at the start's
-// compact id, marking the record it links to as having a predecessor.
-template <bool W, int WT>
-__global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict__ succ, const void* __restrict__ weight,
-                                                     uint32_t n, const uint32_t* __restrict__ cnt,
-                                                     const uint2* __restrict__ dir,
-                                                     typename Lay<W>::Rec* __restrict__ lrec, uint8_t* __restrict__ hp,
-                                                     uint32_t* __restrict__ pos, int64_t* __restrict__ wd,
-                                                     Ctrl* ctrl) {
-    using L = Lay<W>;
-    using Val = typename L::Val;
-    __shared__ uint32_t PD[LC_T];
-    __shared__ int64_t WS[W ? LC_T : 1];
-    __shared__ uint2 DIR[LC_T / 32];
-    const uint32_t b = blockIdx.x * LC_T;
-    const uint32_t len = min(LC_T, n - b);
-    const uint32_t base = cnt[blockIdx.x];
-    uint32_t sv[LC_PER];
-    int64_t wv[LC_PER];
-#pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-        const uint32_t i = j * LC_TPB + threadIdx.x;
-        sv[j] = NONE;
-        wv[j] = 1;
-        if (i < len) {
-            sv[j] = succ[b + i];
-            if constexpr (WT == 1) wv[j] = static_cast<const int32_t*>(weight)[b + i];
-            if constexpr (WT == 2) wv[j] = static_cast<const int64_t*>(weight)[b + i];
-            PD[i] = i;
-            if constexpr (W) WS[i] = 0;
-        }
-    }
-    if (threadIdx.x < (len + 31) / 32) DIR[threadIdx.x] = dir[(b >> 5) + threadIdx.x];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-        const uint32_t i = j * LC_TPB + threadIdx.x;
-        const uint32_t d = sv[j] - b;
-        if (i < len && d < len && d != i) {
-            PD[d] = i | (1u << 16);
-            if constexpr (W) WS[d] = wv[j];
-        }
-    }
-    __syncthreads();
-    uint32_t v[LC_PER];
-    int64_t ws[LC_PER];
-#pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-        const uint32_t i = j * LC_TPB + threadIdx.x;
-        v[j] = (i < len) ? PD[i] : i;
-        ws[j] = 0;
-        if constexpr (W) if (i < len) ws[j] = WS[i];
-    }
-    for (int round = 0; round < LC_ROUNDS; ++round) {
-        int changed = 0;
-        if constexpr (!W) {
-            // in place: a 32-bit entry always holds a consistent (target, count)
-            // pair, so reading a neighbour's newer value only jumps further
-#pragma unroll
-            for (int j = 0; j < LC_PER; ++j) {
-                const uint32_t i = j * LC_TPB + threadIdx.x;
-                const uint32_t p = v[j] & 0xffffu;
-                if (i < len && p != i) {
-                    const uint32_t u = PD[p];
-                    const uint32_t q = u & 0xffffu;
-                    if (q != p) {
-                        v[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
-                        PD[i] = v[j];
-                        changed = 1;
-                    }
-                }
+// One wave per tile: move the tile's staged records to their compact
+// positions; an exit successor s (a chain start of another tile) becomes its
+// compact id, whose record is marked as having a predecessor.
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_lc_compact(const typename Lay<W>::Rec* __restrict__ stage,
+                                                    const uint32_t* __restrict__ cnt, const uint2* __restrict__ dir,
+                                                    uint32_t ntiles, uint32_t n, typename Lay<W>::Rec* __restrict__ lrec,
+                                                    uint8_t* __restrict__ hp, Gate gate) {
+    if (gate.off()) return;
+    const uint32_t lane = lane_id();
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < ntiles; t += nwaves) {
+        const uint32_t base = cnt[t];
+        const uint32_t c = cnt[t + 1] - base;
+        for (uint32_t k = lane; k < c; k += 64) {
+            typename Lay<W>::Rec r = stage[(size_t)t * LC_T + k];
+            if (!(r.nxt & TERM)) {
+                const uint32_t s = r.nxt < n ? r.nxt : n - 1;
+                r.nxt = cnt[s >> LOCAL_SHIFT] + lc_below(dir[s >> 5], s);
+                if (hp) hp[r.nxt] = 1;
             }
-        } else {
-            // target, count and weight live in two words: read all, then write all
-            uint32_t nv[LC_PER];
-            int64_t nw[LC_PER];
-#pragma unroll
-            for (int j = 0; j < LC_PER; ++j) {
-                const uint32_t i = j * LC_TPB + threadIdx.x;
-                const uint32_t p = v[j] & 0xffffu;
-                nv[j] = v[j];
-                nw[j] = ws[j];
-                if (i < len && p != i) {
-                    const uint32_t u = PD[p];
-                    const uint32_t q = u & 0xffffu;
-                    if (q != p) {
-                        nv[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
-                        nw[j] = ws[j] + WS[p];
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < LC_PER; ++j) {
-                const uint32_t i = j * LC_TPB + threadIdx.x;
-                if (nv[j] != v[j]) {
-                    v[j] = nv[j];
-                    ws[j] = nw[j];
-                    PD[i] = v[j];
-                    WS[i] = ws[j];
-                    changed = 1;
-                }
-            }
+            lrec[base + k] = r;
         }
-        if (!__syncthreads_or(changed)) break;
-    }
-#pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-        const uint32_t i = j * LC_TPB + threadIdx.x;
-        if (i >= len) continue;
-        const uint32_t x = b + i;
-        const uint32_t p = v[j] & 0xffffu;
-        const uint32_t dist = v[j] >> 16;
-        if ((PD[p] & 0xffffu) != p) {  // never reached a start: x is on a cycle inside the tile
-            pos[x] = NONE;
-            atomicOr(&ctrl->err, 8u);
-            continue;
-        }
-        const uint32_t lid = lc_below(DIR[p >> 5], p);
-        pos[x] = (lid << 16) | dist;
-        if constexpr (W) wd[x] = ws[j];
-        const uint32_t s = sv[j];
-        const uint32_t d = s - b;
-        if (d < len && d != i) continue;  // the chain continues inside the tile
-        Val val;
-        uint32_t nxt;
-        if (s == x || s >= n) {           // the chain ends at the terminal x
-            val.c = dist;
-            if constexpr (W) val.s = ws[j];
-            nxt = TERM | x;
-        } else {                          // the chain leaves the tile: link to the start s
-            val.c = dist + 1;
-            if constexpr (W) val.s = ws[j] + wv[j];
-            nxt = cnt[s >> LOCAL_SHIFT] + lc_below(dir[s >> 5], s);
-            if (hp) hp[nxt] = 1;
-        }
-        lrec[base + lid] = L::rec(nxt, val);
     }
 }
 
@@ -1185,7 +1261,8 @@ template <bool W, class Out>
 __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ pos, const int64_t* __restrict__ wd,
                                                    const uint32_t* __restrict__ cnt,
                                                    const typename Lay<W>::Res* __restrict__ res, uint32_t n,
-                                                   Ctrl* ctrl, Out out) {
+                                                   Ctrl* ctrl, Out out, Gate gate) {
+    if (gate.off()) return;
     using L = Lay<W>;
     const uint32_t mc = ctrl->dm[0];
     const uint32_t lane = lane_id();
@@ -1202,17 +1279,27 @@ __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ 
             const uint32_t i = base + j * 64 + lane;
             pv[j] = (i < n) ? pos[i] : NONE;
         }
+        // every gather before any store (see k_expand)
+        uint32_t cv[EXPAND_CH];
+        typename L::Res rv[EXPAND_CH];
+        int64_t wv[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            cv[j] = (i >= n || pv[j] == NONE) ? NONE : cnt[i >> LOCAL_SHIFT] + (pv[j] >> 16);
+            if (cv[j] < mc) rv[j] = res[cv[j]];
+            wv[j] = 0;
+            if constexpr (W) if (i < n) wv[j] = wd[i];
+        }
 #pragma unroll
         for (int j = 0; j < EXPAND_CH; ++j) {
             const uint32_t i = base + j * 64 + lane;
             if (i >= n) continue;
-            const uint32_t c = (pv[j] == NONE) ? NONE : cnt[i >> LOCAL_SHIFT] + (pv[j] >> 16);
-            if (c < mc) {
-                const typename L::Res r = res[c];
-                typename L::Val v = L::val(r);
+            if (cv[j] < mc) {
+                typename L::Val v = L::val(rv[j]);
                 v.c -= pv[j] & 0xffffu;
-                if constexpr (W) v.s -= wd[i];
-                out.store(cur, i, v, r.root);
+                if constexpr (W) v.s -= wv[j];
+                out.store(cur, i, v, rv[j].root);
             } else {
                 atomicOr(&ctrl->err, 4u);
                 out.store(cur, i, L::junk(), NONE);
@@ -1265,11 +1352,12 @@ static uint32_t persistent_grid(K kernel, int tpb) {
     return (uint32_t)nb * (uint32_t)device_cus();
 }
 
-static hipError_t fill(void* p, uint64_t bytes, uint32_t val, hipStream_t st, const Ctrl* skip_if_single = nullptr) {
+static hipError_t fill(void* p, uint64_t bytes, uint32_t val, hipStream_t st, const Ctrl* skip_if_single = nullptr,
+                       Gate gate = Gate{}) {
     const uint64_t words = (bytes + 3) / 4;
     if (!words) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(words, TPB * 4)), dim3(TPB), 0, st, (uint32_t*)p, words, val,
-                       skip_if_single);
+                       skip_if_single, gate);
     return hipGetLastError();
 }
 
@@ -1279,14 +1367,14 @@ static inline void rec_ev(const RunArgs& a, int i) {
 
 template <bool W, class Src, class Out>
 static hipError_t launch_base(Src src, Out out, uint32_t m, Ctrl* ctrl, hipStream_t st,
-                             const uint32_t* dm = nullptr) {
+                             const uint32_t* dm = nullptr, Gate gate = Gate{}) {
     const size_t lds = base_lds_bytes(m, W);
     auto kern = k_base<W, Src, Out>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(1), dim3(BASE_TPB), lds, st, src, out, m, ctrl, dm);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(BASE_TPB), lds, st, src, out, m, ctrl, dm, gate);
     return hipGetLastError();
 }
 
@@ -1302,7 +1390,7 @@ static LogArrays<W> log_arrays(char* ws, const size_t* off) {
 
 template <bool W, bool LOG, int NW, class Src>
 static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st,
-                               const uint32_t* dm = nullptr) {
+                               const uint32_t* dm = nullptr, Gate gate = Gate{}) {
     using L = Lay<W>;
     auto kern = k_chase<W, Src, LOG, NW>;
     static uint32_t grid = 0;  // one per template instance
@@ -1316,7 +1404,7 @@ static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl*
     uint8_t* hp_next = (l + 1 < (int)p.levels) ? reinterpret_cast<uint8_t*>(ws + p.off_slot[l + 1]) : nullptr;
     LogArrays<W> lg = LOG ? log_arrays<W>(ws, p.off_log) : LogArrays<W>{};
     hipLaunchKernelGGL(kern, dim3(grid), dim3(CHASE_TPB), 0, st, src, smp, S, ctrl, l, slot, eb, hp_next,
-                       p.refill, lg, p.max_chunks, dm);
+                       p.refill, lg, p.max_chunks, dm, gate);
     return hipGetLastError();
 }
 
@@ -1359,18 +1447,18 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
     LR_TRY(allow_lds(k_place1<W, ROOT>, l1));
     hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), dim3(PTPB), l1, st, log_arrays<W>(ws, p.off_log),
-                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P);
+                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, a.gate);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
     LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
     hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), dim3(PTPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2,
-                       Q);
+                       Q, a.gate);
     LR_TRY(hipGetLastError());
     const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
     LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
     hipLaunchKernelGGL((k_place3<W, ROOT, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)),
-                       dim3(PTPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0);
+                       dim3(PTPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0, a.gate);
     return hipGetLastError();
 }
 
@@ -1382,24 +1470,51 @@ static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<
 }
 
 
+// Validation of the input (LR_VALIDATE): range and in-degree counts.
+static hipError_t run_validate(const RunArgs& a, const Plan& p, uint32_t n) {
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);
+    LR_TRY(fill(ctrl, sizeof(Ctrl), 0u, a.stream));
+    uint32_t* counts = reinterpret_cast<uint32_t*>(a.ws + p.off_slot[0]);
+    LR_TRY(fill(counts, (uint64_t)n * 4, 0u, a.stream));
+    return run_validate_input(a.succ, n, counts, &ctrl->err, a.stream);
+}
+
+// One streaming pass over the input: terminal count, head sum (the one-list
+// shortcut) and local links; with auto_cap > 0 it also picks the path.
+static hipError_t run_headsum(const RunArgs& a, const Plan& p, uint32_t auto_cap) {
+    const uint32_t n = (uint32_t)p.m[0];
+    hipStream_t st = a.stream;
+    const bool vec = ((uintptr_t)a.succ % 16) == 0;
+    const uint32_t gs = std::min<uint32_t>(grid_for(n, TPB * 16), HEADSUM_BLOCKS);
+    uint32_t* part = reinterpret_cast<uint32_t*>(a.ws + p.off_hsum);
+    if (vec) hipLaunchKernelGGL(k_headsum<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
+    else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
+    LR_TRY(hipGetLastError());
+    const Sampler smp0{n, p.log2k[0], p.lseed[0]};
+    hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs,
+                       reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl), smp0, a.ws + p.off_eb[0], (uint32_t)p.m[1],
+                       (uint32_t)p.rec_bytes, auto_cap);
+    return hipGetLastError();
+}
+
+// The plain path. With a.prologue the call starts here (validation, head
+// sum); otherwise the caller ran them and a.gate selects this path.
 template <bool W, int WT, class Out0>
 static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     using L = Lay<W>;
     const Plan& p = *a.plan;
     char* ws = a.ws;
     hipStream_t st = a.stream;
+    const Gate g = a.gate;
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
     const uint32_t n = (uint32_t)p.m[0];
     SrcIn<W, WT> src0{a.succ, a.weight, n};
-    rec_ev(a, EV_START);
-    if (a.validate) {
-        LR_TRY(fill(ctrl, sizeof(Ctrl), 0u, st));
-        uint32_t* counts = reinterpret_cast<uint32_t*>(ws + p.off_slot[0]);
-        LR_TRY(fill(counts, (uint64_t)n * 4, 0u, st));
-        LR_TRY(run_validate_input(a.succ, n, counts, &ctrl->err, st));
+    if (a.prologue) {
+        rec_ev(a, EV_START);
+        if (a.validate) LR_TRY(run_validate(a, p, n));
     }
     if (p.levels == 0) {
-        LR_TRY((launch_base<W>(src0, out0, n, ctrl, st)));
+        LR_TRY((launch_base<W>(src0, out0, n, ctrl, st, nullptr, g)));
         for (int i = EV_DETECT; i < EV_COUNT; ++i) rec_ev(a, i);
         return hipSuccess;
     }
@@ -1407,20 +1522,12 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     // Otherwise: predecessor marks (the one-list case skips these kernels).
     uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
     {
+        if (a.prologue) LR_TRY(run_headsum(a, p, 0));
+        LR_TRY(fill(hp0, n, 0u, st, ctrl, g));
         const bool vec = ((uintptr_t)a.succ % 16) == 0;
-        const uint32_t gs = std::min<uint32_t>(grid_for(n, TPB * 16), HEADSUM_BLOCKS);
-        uint32_t* part = reinterpret_cast<uint32_t*>(ws + p.off_hsum);
-        if (vec) hipLaunchKernelGGL(k_headsum<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
-        else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
-        LR_TRY(hipGetLastError());
-        const Sampler smp0{n, p.log2k[0], p.lseed[0]};
-        hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs, ctrl, smp0, ws + p.off_eb[0],
-                           (uint32_t)p.m[1], (uint32_t)p.rec_bytes);
-        LR_TRY(hipGetLastError());
-        LR_TRY(fill(hp0, n, 0u, st, ctrl));
-        const uint32_t g = grid_for(n, TPB * 4 * 4);
-        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0, ctrl);
-        else hipLaunchKernelGGL(k_detect<false>, dim3(g), dim3(TPB), 0, st, a.succ, n, hp0, ctrl);
+        const uint32_t gd = grid_for(n, TPB * 4 * 4);
+        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
+        else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
         LR_TRY(hipGetLastError());
     }
     rec_ev(a, EV_DETECT);
@@ -1434,30 +1541,31 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
         const uint32_t zw = more ? (S + 3) / 4 : 0;
         const Ctrl* skip = (l == 0) ? ctrl : nullptr;
-        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw, skip,
-                           nullptr);
+        const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
+        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, skip,
+                           nullptr, g);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
-                           (uint32_t)p.rec_bytes, skip, nullptr);
+        hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
+                           S, (uint32_t)p.rec_bytes, skip, nullptr, g);
         LR_TRY(hipGetLastError());
         if (a.validate && !(l == 0 && p.log0))
-            LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st));
+            LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st, nullptr, g));
         if (l == 0) rec_ev(a, EV_HEADS);
         if (l == 0) {
             if (p.log0) {
-                LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st));
-                if (p.lane_walks == 2) LR_TRY((launch_chase<W, true, 2>(p, 0, src0, smp, ctrl, ws, st)));
-                else LR_TRY((launch_chase<W, true, 1>(p, 0, src0, smp, ctrl, ws, st)));
+                LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
+                if (p.lane_walks == 2) LR_TRY((launch_chase<W, true, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                else LR_TRY((launch_chase<W, true, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
             } else {
-                if (p.lane_walks == 2) LR_TRY((launch_chase<W, false, 2>(p, 0, src0, smp, ctrl, ws, st)));
-                else LR_TRY((launch_chase<W, false, 1>(p, 0, src0, smp, ctrl, ws, st)));
+                if (p.lane_walks == 2) LR_TRY((launch_chase<W, false, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                else LR_TRY((launch_chase<W, false, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
             }
             rec_ev(a, EV_CHASE0);
         } else {
             SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]), m};
-            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st)));
+            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, nullptr, g)));
         }
     }
     {
@@ -1465,30 +1573,30 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const uint32_t mL = (uint32_t)p.m[L_];
         SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[L_ - 1]), mL};
         OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[L_ - 1])};
-        LR_TRY((launch_base<W>(src, out, mL, ctrl, st)));
+        LR_TRY((launch_base<W>(src, out, mL, ctrl, st, nullptr, g)));
     }
     for (int l = (int)p.levels - 1; l >= 0; --l) {
         const uint32_t m = (uint32_t)p.m[l];
         const uint32_t S = (uint32_t)p.m[l + 1];
         hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
-                           ctrl, l, nullptr);
+                           ctrl, l, nullptr, g);
         LR_TRY(hipGetLastError());
         const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
         const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
-        const uint32_t g = grid_for(m, TPB * EXPAND_CH);
+        const uint32_t ge = grid_for(m, TPB * EXPAND_CH);
         if (l == 0) {
             rec_ev(a, EV_UPPER);
             if (p.log0) {
                 LR_TRY((run_place<W, Out0>(a, p, res, S, ctrl, out0)));
             } else {
                 rec_ev(a, EV_PART);
-                hipLaunchKernelGGL((k_expand<W, Out0>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0,
-                                   nullptr);
+                hipLaunchKernelGGL((k_expand<W, Out0>), dim3(ge), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0,
+                                   nullptr, g);
             }
         } else {
             OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1])};
-            hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(g), dim3(TPB), 0, st, slot, m, res, S, ctrl, l,
-                               out, nullptr);
+            hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(ge), dim3(TPB), 0, st, slot, m, res, S, ctrl, l,
+                               out, nullptr, g);
         }
         LR_TRY(hipGetLastError());
     }
@@ -1497,43 +1605,47 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
 }
 
 // Tile-local contraction, then the ruling-set levels on the contracted list
-// (sizes from the device), then every element from its chain start.
+// (sizes from the device), then every element from its chain start. The plan
+// sizes the levels for a contracted list of at most m[0] elements; lc_n is
+// the input's length.
 template <bool W, int WT, class Out0>
 static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
     using L = Lay<W>;
     const Plan& p = *a.plan;
     char* ws = a.ws;
     hipStream_t st = a.stream;
+    const Gate g = a.gate;
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
-    const uint32_t n = (uint32_t)p.m[0];
+    const uint32_t n = (uint32_t)p.lc_n;
     const uint32_t Lv = p.levels;
-    rec_ev(a, EV_START);
-    if (a.validate) {
-        LR_TRY(fill(ctrl, sizeof(Ctrl), 0u, st));
-        uint32_t* counts = reinterpret_cast<uint32_t*>(ws + p.off_slot[0]);
-        LR_TRY(fill(counts, (uint64_t)n * 4, 0u, st));
-        LR_TRY(run_validate_input(a.succ, n, counts, &ctrl->err, st));
+    if (a.prologue) {
+        rec_ev(a, EV_START);
+        if (a.validate) LR_TRY(run_validate(a, p, n));
     }
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + p.off_lc_cnt);
     uint2* dir = reinterpret_cast<uint2*>(ws + p.off_lc_dir);
     uint32_t* pos = reinterpret_cast<uint32_t*>(ws + p.off_lc_pos);
     int64_t* wd = W ? reinterpret_cast<int64_t*>(ws + p.off_lc_wd) : nullptr;
     auto* lrec = reinterpret_cast<typename L::Rec*>(ws + p.off_lrec);
+    auto* stage = reinterpret_cast<typename L::Rec*>(ws + p.off_lc_stage);
     uint8_t* hp0 = Lv ? reinterpret_cast<uint8_t*>(ws + p.off_slot[0]) : nullptr;
-    hipLaunchKernelGGL(k_lc_mark, dim3(p.lc_ntiles), dim3(LC_TPB), 0, st, a.succ, n, cnt, dir);
+    const uint32_t gc = LR_LC_GRID_PER_CU ? std::min<uint32_t>(p.lc_ntiles, (uint32_t)device_cus() * LR_LC_GRID_PER_CU)
+                                          : p.lc_ntiles;
+    hipLaunchKernelGGL((k_lc_chain<W, WT>), dim3(gc), dim3(LC_TPB), 0, st, a.succ, a.weight, n, p.lc_ntiles, cnt, dir,
+                       stage, pos, wd, ctrl, g);
     LR_TRY(hipGetLastError());
     LevelShifts ks{};
     for (uint32_t l = 0; l < Lv; ++l) ks.lg[l] = (uint8_t)p.log2k[l];
-    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks);
+    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks, g);
     LR_TRY(hipGetLastError());
+    rec_ev(a, EV_DETECT);
     if (hp0) {
-        hipLaunchKernelGGL(k_zero_dyn, dim3(grid_for(n / 4 + 1, TPB * 4)), dim3(TPB), 0, st,
-                           reinterpret_cast<uint32_t*>(hp0), (const uint32_t*)&ctrl->dm[0]);
+        hipLaunchKernelGGL(k_zero_dyn, dim3(grid_for(p.m[0] / 4 + 1, TPB * 4)), dim3(TPB), 0, st,
+                           reinterpret_cast<uint32_t*>(hp0), (const uint32_t*)&ctrl->dm[0], g);
         LR_TRY(hipGetLastError());
     }
-    rec_ev(a, EV_DETECT);
-    hipLaunchKernelGGL((k_lc_chain<W, WT>), dim3(p.lc_ntiles), dim3(LC_TPB), 0, st, a.succ, a.weight, n, cnt, dir,
-                       lrec, hp0, pos, wd, ctrl);
+    hipLaunchKernelGGL((k_lc_compact<W>), dim3(grid_for((uint64_t)p.lc_ntiles * 64, TPB)), dim3(TPB), 0, st, stage,
+                       cnt, dir, p.lc_ntiles, n, lrec, hp0, g);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_HEADS);
     for (uint32_t l = 0; l < Lv; ++l) {
@@ -1545,31 +1657,34 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
         const bool more = l + 1 < Lv;
         uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
         const uint32_t zw = more ? (S + 3) / 4 : 0;
-        hipLaunchKernelGGL(k_heads_count, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, zp, zw, nullptr, dm);
+        const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
+        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, nullptr, dm,
+                           g);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l);
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_write, dim3(p.ntiles[l]), dim3(TPB), 0, st, hp, smp, tile, ws + p.off_eb[l], S,
-                           (uint32_t)p.rec_bytes, nullptr, dm);
+        hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
+                           S, (uint32_t)p.rec_bytes, nullptr, dm, g);
         LR_TRY(hipGetLastError());
-        if (a.validate) LR_TRY(fill(ws + p.off_slot[l], (uint64_t)p.m[l] * p.rec_bytes, 0xffffffffu, st));
+        if (a.validate)
+            LR_TRY(fill(ws + p.off_slot[l], (uint64_t)p.m[l] * p.rec_bytes, 0xffffffffu, st, nullptr, g));
         const auto* rec = (l == 0) ? lrec : reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]);
         SrcLvl<W> src{rec, (uint32_t)p.m[l]};
-        LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm)));
+        LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
         if (l == 0) rec_ev(a, EV_CHASE0);
     }
     {
         auto* top = Lv ? reinterpret_cast<typename L::Rec*>(ws + p.off_eb[Lv - 1]) : lrec;
         SrcLvl<W> src{top, (uint32_t)p.m[Lv]};
         OutLvl<W> out{reinterpret_cast<typename L::Res*>(top)};
-        LR_TRY((launch_base<W>(src, out, (uint32_t)p.m[Lv], ctrl, st, &ctrl->dm[Lv])));
+        LR_TRY((launch_base<W>(src, out, (uint32_t)p.m[Lv], ctrl, st, &ctrl->dm[Lv], g)));
     }
     for (int l = (int)Lv - 1; l >= 0; --l) {
         const uint32_t m = (uint32_t)p.m[l];
         const uint32_t S = (uint32_t)p.m[l + 1];
         const uint32_t* dm = &ctrl->dm[l];
         hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
-                           ctrl, l, dm);
+                           ctrl, l, dm, g);
         LR_TRY(hipGetLastError());
         const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
         const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
@@ -1577,21 +1692,38 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
                                : reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1]);
         OutLvl<W> out{below};
         hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(grid_for(m, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot, m,
-                           res, S, ctrl, l, out, dm);
+                           res, S, ctrl, l, out, dm, g);
         LR_TRY(hipGetLastError());
     }
     rec_ev(a, EV_UPPER);
     rec_ev(a, EV_PART);
     hipLaunchKernelGGL((k_lc_expand<W, Out0>), dim3(grid_for(n, TPB * EXPAND_CH)), dim3(TPB), 0, st, pos, wd, cnt,
-                       reinterpret_cast<const typename L::Res*>(lrec), n, ctrl, out0);
+                       reinterpret_cast<const typename L::Res*>(lrec), n, ctrl, out0, g);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_EXPAND);
     return hipSuccess;
 }
 
+// Forced paths run alone. Automatic contraction: the head-sum pass decides on
+// the device; both paths are enqueued and the one not chosen returns from
+// every kernel at once (no host synchronisation, so the call stays capturable).
 template <bool W, int WT, class Out0>
 static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
-    return a.plan->local ? run_local_t<W, WT>(a, out0) : run_srs_t<W, WT>(a, out0);
+    if (!a.lplan) return a.plan->local ? run_local_t<W, WT>(a, out0) : run_srs_t<W, WT>(a, out0);
+    const Plan& p = *a.plan;
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);
+    rec_ev(a, EV_START);
+    if (a.validate) LR_TRY(run_validate(a, p, (uint32_t)p.m[0]));
+    LR_TRY(run_headsum(a, p, (uint32_t)a.lplan->m[0]));
+    RunArgs la = a;
+    la.plan = a.lplan;
+    la.prologue = false;
+    la.gate = Gate{&ctrl->mode, 1u};
+    LR_TRY((run_local_t<W, WT>(la, out0)));
+    RunArgs pa = a;
+    pa.prologue = false;
+    pa.gate = Gate{&ctrl->mode, 0u};
+    return run_srs_t<W, WT>(pa, out0);
 }
 
 hipError_t run_srs(const RunArgs& a) {

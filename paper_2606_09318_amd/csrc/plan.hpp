@@ -22,6 +22,10 @@ constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the v
 constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
 constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
 constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
+// automatic contraction: considered from this size on, taken when the
+// contracted list has at most n / LOCAL_AUTO_DIV elements
+constexpr uint64_t LOCAL_AUTO_MIN_N = 1ull << 21;
+constexpr uint64_t LOCAL_AUTO_DIV = 4;
 // grouping tiles: LR_PLACE_TPB lanes x LR_PLACE_PER records (half as many weighted)
 #ifndef LR_PLACE_TPB
 #define LR_PLACE_TPB 512
@@ -64,17 +68,30 @@ struct Plan {
     // contracted list, whose size is known only on the device; m[] are then
     // capacities (m[0] = n) and the kernels read the actual sizes from Ctrl.
     bool local = false;
+    uint64_t lc_n = 0;       // input elements (m[0] is the contracted list's capacity)
     uint32_t lc_ntiles = 0;
     size_t off_lc_cnt = 0;   // lc_ntiles + 1 start counts, scanned in place
     size_t off_lc_dir = 0;   // per 32 ids: start bits and starts before the word in its tile
     size_t off_lc_pos = 0;   // per element: chain start (compact, tile-relative) << 16 | distance
     size_t off_lc_wd = 0;    // per element: weight from its chain start (weighted only)
+    size_t off_lc_stage = 0; // contracted records at their tile's offset, before compaction
     size_t off_lrec = 0;     // contracted records, then their results
     size_t total = 0;
 };
 
-// Build the plan for n elements. batch_count > 0 adds the batch staging
+// The plans of one call: p runs alone, or, with automatic contraction
+// (autol), p is the plain path and lp the contracted path over the same
+// workspace (common header: control block and head-sum partials).
+struct PlanSet {
+    Plan p;
+    Plan lp;
+    bool autol = false;
+};
+
+// Build the plans for n elements. batch_count > 0 adds the batch staging
 // areas (concatenated successor array and request table).
+lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, PlanSet* ps);
+// The same, keeping only p (its total covers every path).
 lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, Plan* p);
 
 // Base-case shared memory bytes for m elements.

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device.hpp"
 #include "plan.hpp"
 
 namespace lr {
@@ -13,6 +14,7 @@ enum { EV_START, EV_DETECT, EV_HEADS, EV_CHASE0, EV_UPPER, EV_PART, EV_EXPAND, E
 
 struct RunArgs {
     const Plan* plan = nullptr;
+    const Plan* lplan = nullptr;      // automatic contraction: the contracted path's plan (same workspace)
     const uint32_t* succ = nullptr;   // level-0 successor array (user's, or the batch concatenation)
     const void* weight = nullptr;
     int wt = 0;                       // 0: unit links, 1: int32, 2: int64
@@ -28,6 +30,8 @@ struct RunArgs {
     hipStream_t stream = nullptr;
     bool validate = false;
     hipEvent_t* ev = nullptr;         // EV_COUNT events to record, or null
+    bool prologue = true;             // run validation and the head-sum pass (false: the caller did)
+    Gate gate{};                      // device-side path selection (null: always run)
 };
 
 // Sparse ruling-set ranking over the whole plan. Enqueues only.

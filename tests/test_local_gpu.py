@@ -220,3 +220,72 @@ def test_large_random_takes_capacity_levels():
     n = (1 << 22) + 12345
     print(f"case: local random list n={n}", flush=True)
     check_rank(workloads.random_list(n, seed=17).succ, want_root=False)
+
+
+# ------------------------------------------------------------------------
+# Automatic choice (default flags, inputs of 2^21 elements or more): the
+# head-sum pass counts local links on the device and one of the two enqueued
+# paths runs. Outputs must not depend on the choice.
+
+AUTO_N = (1 << 21) + 4099
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.02, 0.2, 0.3, 1.0])
+def test_automatic_choice(gamma):
+    print(f"case: auto List(n={AUTO_N}, gamma={gamma})", flush=True)
+    L = workloads.gamma_list(AUTO_N, gamma, seed=16)
+    exp = np.empty(AUTO_N, np.uint32)
+    exp[L.order] = np.arange(AUTO_N - 1, -1, -1, dtype=np.uint32)
+    for flags in (0, lr.LR_NO_LOCAL, LOCAL):
+        st, r, t = gpu_rank(L.succ, lr.make_opts(flags=flags))
+        assert st == lr.LR_OK
+        assert np.array_equal(r, exp), f"flags={flags}"
+        assert np.all(t == L.order[-1])
+    check_rank(L.succ, lr.make_opts())
+
+
+def test_automatic_choice_forest_and_weights():
+    F = workloads.forest(AUTO_N, mean=64, n_long=2, long_len=100000, seed=18)
+    check_rank(F.succ, lr.make_opts())
+    L = workloads.gamma_list(AUTO_N, 0.01, seed=19)
+    w = workloads.weights(AUTO_N, 19, 3, -1000, 1000, np.int32)
+    st, s, r, t = gpu_prefix(L.succ, w, lr.make_opts())
+    assert st == lr.LR_OK
+    _, er, et, es = oracle.rank(L.succ, w)
+    assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+
+
+def test_automatic_choice_validate():
+    o = lr.make_opts(flags=lr.LR_VALIDATE)
+    ident = np.minimum(np.arange(AUTO_N) + 1, AUTO_N - 1).astype(np.uint32)
+    assert gpu_rank(ident, o)[0] == lr.LR_OK
+    bad = ident.copy()
+    bad[99] = 99
+    bad[110] = 100                          # a cycle inside one tile
+    assert gpu_rank(bad, o)[0] == lr.LR_ERR_BAD_LIST
+    R = workloads.random_list(AUTO_N, seed=20)
+    assert gpu_rank(R.succ, o)[0] == lr.LR_OK
+    rb = R.succ.copy()
+    rb[R.order[7]] = R.order[9]             # two predecessors
+    assert gpu_rank(rb, o)[0] == lr.LR_ERR_BAD_LIST
+
+
+def test_automatic_choice_batch():
+    """A batch of block-local requests takes the contracted path as one forest."""
+    sizes = [1 << 20, 5, 777777, 4096, 300001]
+    items, inputs = [], []
+    for i, n in enumerate(sizes):
+        L = workloads.block_list(n, 4096, seed=700 + i)
+        items.append((dev(L.succ), torch.full((n,), -7, dtype=torch.int32, device="cuda"),
+                      torch.full((n,), -7, dtype=torch.int32, device="cuda") if i % 2 else None))
+        inputs.append(L)
+    assert sum(sizes) >= 1 << 21
+    reqs = lr.requests(items)
+    ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items)))
+    assert lr.lr_rank_batch(reqs, len(items), ws) == lr.LR_OK
+    torch.cuda.synchronize()
+    for (s, r, t), L in zip(items, inputs):
+        _, er, et, _ = oracle.rank(L.succ)
+        assert np.array_equal(host_u32(r), er)
+        if t is not None:
+            assert np.array_equal(host_u32(t), et)
