@@ -78,8 +78,9 @@ enum {
  * local (a list stored mostly in list order) and costs extra passes when few
  * are. By default (neither flag) inputs of 2^21 elements or more choose on
  * the device: the pass that looks for the head of a single list also counts
- * the local links, and the contracted path runs when at least three quarters
- * of the links are local; nothing is synchronised, both paths are enqueued
+ * the local links, and the contracted path runs when the contracted list
+ * keeps at most 5/16 of the elements (at least about 69% of the links are
+ * local); nothing is synchronised, both paths are enqueued
  * and the one not taken returns at once. Results are identical in every
  * mode. Applies to lr_rank, lr_prefix_sum and lr_rank_batch. */
 

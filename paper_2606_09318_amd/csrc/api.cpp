@@ -170,6 +170,7 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
     off += align_up((size_t)HEADSUM_BLOCKS * 16);
     const size_t body = off;
     if (force) {
+        p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
         off = layout_levels(p, layout_local(p, n, body));
     } else {
         p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
@@ -182,10 +183,11 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         Plan* q = &ps->lp;
         lr_opts lo = o ? *o : lr_opts{};
         for (int l = 0; l < LR_MAX_LEVELS; ++l) lo.spacing[l] = 0;  // user spacing describes the plain levels
-        s = plan_levels((n + LOCAL_AUTO_DIV - 1) / LOCAL_AUTO_DIV, weighted, &lo, false, q);
+        s = plan_levels(local_auto_cap(n), weighted, &lo, false, q);
         if (s != LR_OK) return s;
         q->off_ctrl = p->off_ctrl;
         q->off_hsum = p->off_hsum;
+        q->log0 = q->levels >= 1 && q->m[0] >= LOG_MIN_N;
         off = std::max(off, layout_levels(q, layout_local(q, n, body)));
     }
     if (batch_count) {

@@ -803,8 +803,10 @@ template <bool W, bool ROOT>
 __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
-                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out, Gate gate) {
+                                                uint32_t* __restrict__ fill1, PlaceArrays<W> out, const uint32_t* dm,
+                                                Gate gate) {
     if (gate.off()) return;
+    if (dm) { n = dm[0]; S = dm[1]; }
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
@@ -845,8 +847,10 @@ __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_c
 
 template <bool W, bool ROOT>
 __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
-                                                uint32_t* __restrict__ fill2, PlaceArrays<W> out, Gate gate) {
+                                                uint32_t* __restrict__ fill2, PlaceArrays<W> out, const uint32_t* dm,
+                                                Gate gate) {
     if (gate.off()) return;
+    if (dm) n = dm[0];
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W>();
     constexpr uint32_t T = PER * PTPB;
@@ -879,8 +883,13 @@ __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, 
 // LDS, then write the outputs in element order.
 template <bool W, bool ROOT, class Out>
 __global__ __launch_bounds__(PTPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
-                                                const uint32_t* __restrict__ fill2, int check, Out out, Gate gate) {
+                                                const uint32_t* __restrict__ fill2, int check, Out out,
+                                                const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
+    if (dm) {  // a device-side size: only the ranges it covers
+        n = dm[0];
+        nb2 = (n + (1u << s2) - 1) >> s2;
+    }
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t R = 1u << s2;
@@ -1434,7 +1443,7 @@ static hipError_t allow_lds(K kern, size_t bytes) {
 // placement. The fine-grouped records reuse the visit-log arrays.
 template <bool W, bool ROOT, class Out0>
 static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S,
-                              Ctrl* ctrl, Out0 out0) {
+                              Ctrl* ctrl, Out0 out0, const uint32_t* dm) {
     char* ws = a.ws;
     hipStream_t st = a.stream;
     const uint32_t n = (uint32_t)p.m[0];
@@ -1447,26 +1456,26 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
     LR_TRY(allow_lds(k_place1<W, ROOT>, l1));
     hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), dim3(PTPB), l1, st, log_arrays<W>(ws, p.off_log),
-                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, a.gate);
+                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, dm, a.gate);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
     LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
     hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), dim3(PTPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2,
-                       Q, a.gate);
+                       Q, dm, a.gate);
     LR_TRY(hipGetLastError());
     const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
     LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
     hipLaunchKernelGGL((k_place3<W, ROOT, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)),
-                       dim3(PTPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0, a.gate);
+                       dim3(PTPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0, dm, a.gate);
     return hipGetLastError();
 }
 
 template <bool W, class Out0>
 static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<W>::Res* res, uint32_t S, Ctrl* ctrl,
-                            Out0 out0) {
-    if (a.desc ? a.any_root : a.root != nullptr) return run_place_t<W, true>(a, p, res, S, ctrl, out0);
-    return run_place_t<W, false>(a, p, res, S, ctrl, out0);
+                            Out0 out0, bool root, const uint32_t* dm) {
+    if (root) return run_place_t<W, true>(a, p, res, S, ctrl, out0, dm);
+    return run_place_t<W, false>(a, p, res, S, ctrl, out0, dm);
 }
 
 
@@ -1587,7 +1596,8 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         if (l == 0) {
             rec_ev(a, EV_UPPER);
             if (p.log0) {
-                LR_TRY((run_place<W, Out0>(a, p, res, S, ctrl, out0)));
+                LR_TRY((run_place<W, Out0>(a, p, res, S, ctrl, out0, a.desc ? a.any_root : a.root != nullptr,
+                                           nullptr)));
             } else {
                 rec_ev(a, EV_PART);
                 hipLaunchKernelGGL((k_expand<W, Out0>), dim3(ge), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0,
@@ -1666,11 +1676,16 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
         hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
                            S, (uint32_t)p.rec_bytes, nullptr, dm, g);
         LR_TRY(hipGetLastError());
-        if (a.validate)
+        if (a.validate && !(l == 0 && p.log0))
             LR_TRY(fill(ws + p.off_slot[l], (uint64_t)p.m[l] * p.rec_bytes, 0xffffffffu, st, nullptr, g));
         const auto* rec = (l == 0) ? lrec : reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]);
         SrcLvl<W> src{rec, (uint32_t)p.m[l]};
-        LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
+        if (l == 0 && p.log0) {  // a long contracted list: visit log and grouped placement, as the plain path
+            LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
+            LR_TRY((launch_chase<W, true, 1>(p, 0, src, smp, ctrl, ws, st, dm, g)));
+        } else {
+            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
+        }
         if (l == 0) rec_ev(a, EV_CHASE0);
     }
     {
@@ -1691,8 +1706,12 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
         auto* below = (l == 0) ? reinterpret_cast<typename L::Res*>(lrec)
                                : reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1]);
         OutLvl<W> out{below};
-        hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(grid_for(m, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot, m,
-                           res, S, ctrl, l, out, dm, g);
+        if (l == 0 && p.log0) {
+            LR_TRY((run_place<W, OutLvl<W>>(a, p, res, S, ctrl, out, true, dm)));
+        } else {
+            hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(grid_for(m, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot,
+                               m, res, S, ctrl, l, out, dm, g);
+        }
         LR_TRY(hipGetLastError());
     }
     rec_ev(a, EV_UPPER);

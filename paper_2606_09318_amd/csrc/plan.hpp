@@ -23,9 +23,12 @@ constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 el
 constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
 constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
 // automatic contraction: considered from this size on, taken when the
-// contracted list has at most n / LOCAL_AUTO_DIV elements
+// contracted list has at most LR_LOCAL_AUTO_16THS / 16 of the elements
 constexpr uint64_t LOCAL_AUTO_MIN_N = 1ull << 21;
-constexpr uint64_t LOCAL_AUTO_DIV = 4;
+#ifndef LR_LOCAL_AUTO_16THS
+#define LR_LOCAL_AUTO_16THS 5
+#endif
+constexpr uint64_t local_auto_cap(uint64_t n) { return (n * LR_LOCAL_AUTO_16THS + 15) / 16; }
 // grouping tiles: LR_PLACE_TPB lanes x LR_PLACE_PER records (half as many weighted)
 #ifndef LR_PLACE_TPB
 #define LR_PLACE_TPB 512
