@@ -30,10 +30,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
+    ap.add_argument("--list", choices=["random", "block"], default="random",
+                    help="with --only-main: the random list, or the block-local list of the same size")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-weighted", action="store_true")
     ap.add_argument("--serve-count", type=int, default=4096)
+    ap.add_argument("--gamma", type=float, nargs="*", default=[0.0, 0.01, 0.1, 0.3],
+                    help="List(n, gamma) locality sweep (empty: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -73,8 +77,11 @@ def main():
         return
 
     n = args.n
+    if args.list != "random" and not args.only_main:
+        raise SystemExit("--list applies to --only-main runs")
     t0 = time.time()
-    L = workloads.random_list(n, seed=2, stream=0)
+    L = workloads.random_list(n, seed=2, stream=0) if args.list == "random" else \
+        workloads.block_list(n, block=4096, seed=2, stream=1)
     gen_s = time.time() - t0
     succ = torch.from_numpy(L.succ.view(np.int32)).to(dev)
     rank = torch.empty(n, dtype=torch.int32, device=dev)
@@ -120,7 +127,7 @@ def main():
         raise SystemExit("bench: ranks/roots do not match the closed form of the generated list")
     if args.only_main:
         print(json.dumps({"metric": METRIC, "value": round(value, 4), "unit": "G elements/s",
-                          "ms_per_step": round(ms, 4), "n": n}))
+                          "ms_per_step": round(ms, 4), "n": n, "list": args.list}))
         return
 
     # per-phase times with HIP events on the launch stream (LR_PROFILE), and
@@ -178,24 +185,14 @@ def main():
     del wsw
     torch.cuda.empty_cache()
 
-    # locality-preserving variant of the same size (blocks of 4096 ids)
-    B = workloads.block_list(n, block=4096, seed=2, stream=1)
-    succ.copy_(torch.from_numpy(B.succ.view(np.int32)))
-    ws = lr.workspace(lr.lr_workspace_bytes(n), dev)
-    for _ in range(2):
-        step()
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(5):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    bms = ev0.elapsed_time(ev1) / 5
-    order = torch.from_numpy(B.order.view(np.int32)).to(dev)
-    bok = bool(torch.equal(rank.index_select(0, order), torch.arange(n - 1, -1, -1, dtype=torch.int32, device=dev)))
-    extra["block_local_4096"] = {"ms": round(bms, 3), "g_elements_per_s": round(n / (bms * 1e-3) / 1e9, 3),
-                                 "closed_form_ok": bok}
-    del ws, order, succ, rank, root, B, L
+    # inputs with locality (Section 2.3): the default call contracts tile-local
+    # chains when most links are local; LR_NO_LOCAL forces the plain path and
+    # LR_LOCAL the contracted one, for comparison
+    del succ
+    torch.cuda.empty_cache()
+    extra["locality"] = locality_bench(n, rank, stream, args.gamma)
+    extra["block_local_4096"] = extra["locality"]["block_local_4096"]
+    del rank, root, L
     torch.cuda.empty_cache()
 
     if not args.no_weighted:
@@ -216,6 +213,58 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
+
+
+def locality_bench(n: int, rank, stream, gammas) -> dict:
+    """Block-local list and the paper's List(n, gamma) at the main size: the
+    default call (automatic contraction) against the forced paths."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    dev = rank.device
+    modes = {"default": 0, "plain": lr.LR_NO_LOCAL, "contracted": lr.LR_LOCAL}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def measure(L):
+        succ = torch.from_numpy(L.succ.view(np.int32)).to(dev)
+        order = torch.from_numpy(L.order.view(np.int32)).to(dev)
+        expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device=dev)
+        row = {}
+        for name, flags in modes.items():
+            o = lr.make_opts(flags=flags)
+            ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_NONE, o), dev)
+            rank.fill_(-1)
+            for _ in range(2):
+                lr.lr_rank(succ, rank, None, ws, o, stream)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(5):
+                lr.lr_rank(succ, rank, None, ws, o, stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / 5
+            ok = bool(torch.equal(rank.index_select(0, order), expect))
+            if not ok:
+                raise SystemExit(f"bench: locality workload ranks do not match the closed form ({name})")
+            row[name + "_ms"] = round(ms, 3)
+            del ws
+            torch.cuda.empty_cache()
+        row["default_g_elements_per_s"] = round(n / (row["default_ms"] * 1e-3) / 1e9, 3)
+        row["default_speedup_over_plain"] = round(row["plain_ms"] / row["default_ms"], 2)
+        del succ, order, expect
+        torch.cuda.empty_cache()
+        return row
+
+    out = {"block_local_4096": measure(workloads.block_list(n, block=4096, seed=2, stream=1))}
+    out["gamma_sweep"] = []
+    for g in gammas:
+        r = measure(workloads.gamma_list(n, g, seed=6))
+        r["gamma"] = g
+        out["gamma_sweep"].append(r)
+    return out
 
 
 def weighted_bench() -> dict:
