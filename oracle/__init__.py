@@ -6,6 +6,10 @@ import this package. The GPU library does not use it.
 `rank(succ, weight=None)` returns (status, rank, root, sum) computed by plain
 sequential pointer chasing in C (oracle.c): the definition of list ranking
 from Section 1.1 of the paper, written out.
+
+`tree(parent, root)` returns (status, depth, preorder, size) of a rooted tree
+by a plain depth-first traversal (children in ascending id order): the tree
+quantities that Euler-tour list ranking computes.
 """
 from __future__ import annotations
 
@@ -42,6 +46,8 @@ def _load():
         vp = ctypes.c_void_p
         lib.oracle_rank.restype = ctypes.c_int
         lib.oracle_rank.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_int, vp, vp, vp]
+        lib.oracle_tree.restype = ctypes.c_int
+        lib.oracle_tree.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -66,3 +72,15 @@ def rank(succ: np.ndarray, weight: np.ndarray | None = None, want=("rank", "root
     s = np.empty(n, dtype=np.int64) if "sum" in want else None
     st = _load().oracle_rank(_p(succ), n, _p(weight), wt, _p(r), _p(t), _p(s))
     return st, r, t, s
+
+
+def tree(parent: np.ndarray, root: int = 0):
+    """Depth, preorder number and subtree size of every vertex of the tree
+    parent[] (parent[root] == root). Returns (status, depth, preorder, size)."""
+    parent = np.ascontiguousarray(parent, dtype=np.uint32)
+    V = parent.size
+    d = np.empty(V, dtype=np.uint32)
+    p = np.empty(V, dtype=np.uint32)
+    z = np.empty(V, dtype=np.uint32)
+    st = _load().oracle_tree(_p(parent), V, root, _p(d), _p(p), _p(z))
+    return st, d, p, z

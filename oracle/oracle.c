@@ -27,6 +27,14 @@
  * Parity status: pinned (brute-force enumeration of every successor array of
  * size <= 7, closed forms of generated inputs, local certificate, special
  * cases; see tests/test_oracle_pins.py).
+ *
+ * oracle_tree: the tree quantities that list ranking serves through Euler
+ * tours (Section 1 names tree algorithms as its users; Section 3 ranks Euler
+ * tours of BFS trees), by their plain definitions on a parent array: depth,
+ * preorder number (depth-first from the root, children in ascending id order)
+ * and subtree size. Pinned by enumeration of every parent array with at most
+ * 6 vertices (Cayley's count of rooted labelled trees), closed forms for paths
+ * and stars, and structural invariants.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -101,4 +109,66 @@ int oracle_rank(const uint32_t* succ, uint64_t n, const void* weight, int wtype,
     free(has_pred);
     /* every element of a valid forest lies on exactly one head-to-terminal path */
     return assigned == n ? ORACLE_OK : ORACLE_ERR_CYCLE;
+}
+
+/* Tree quantities of a rooted tree given by parent[0..V) with
+ * parent[root] == root:
+ *   depth[v]    = number of edges on the path from the root to v,
+ *   preorder[v] = position of v in the depth-first order from the root that
+ *                 takes children in ascending id order (the root is 0),
+ *   size[v]     = number of vertices in the subtree rooted at v.
+ * Any output may be NULL. Returns ORACLE_OK, ORACLE_ERR_ARG (bad root),
+ * ORACLE_ERR_RANGE (a parent id >= V or a second self-parent) or
+ * ORACLE_ERR_CYCLE (some vertex does not reach the root). */
+int oracle_tree(const uint32_t* parent, uint64_t V, uint32_t root,
+                uint32_t* depth, uint32_t* preorder, uint32_t* size) {
+    if (V == 0) return ORACLE_OK;
+    if (!parent || V > 0xffffffffULL || root >= V || parent[root] != root) return ORACLE_ERR_ARG;
+    uint64_t* first = (uint64_t*)calloc(V + 1, sizeof(uint64_t));  /* children of v: kids[first[v] .. first[v+1]) */
+    uint32_t* kids = (uint32_t*)malloc((V > 1 ? V - 1 : 1) * sizeof(uint32_t));
+    uint64_t* fill = (uint64_t*)malloc(V * sizeof(uint64_t));
+    uint32_t* stack = (uint32_t*)malloc(V * sizeof(uint32_t));
+    uint32_t* order = (uint32_t*)malloc(V * sizeof(uint32_t));
+    uint32_t* dep = (uint32_t*)malloc(V * sizeof(uint32_t));
+    uint32_t* sz = (uint32_t*)malloc(V * sizeof(uint32_t));
+    int rc = ORACLE_OK;
+    if (!first || !kids || !fill || !stack || !order || !dep || !sz) { rc = ORACLE_ERR_NOMEM; goto out; }
+    for (uint64_t v = 0; v < V; v++) {
+        if (v == root) continue;
+        if (parent[v] >= V || parent[v] == v) { rc = ORACLE_ERR_RANGE; goto out; }
+        first[parent[v] + 1]++;
+    }
+    for (uint64_t v = 0; v < V; v++) first[v + 1] += first[v];
+    for (uint64_t v = 0; v < V; v++) fill[v] = first[v];
+    for (uint64_t v = 0; v < V; v++)                 /* ascending v: each child list ascending */
+        if (v != root) kids[fill[parent[v]]++] = (uint32_t)v;
+    /* depth-first order: pop a vertex, number it, push its children last-first */
+    uint64_t top = 0, visited = 0;
+    stack[top++] = root;
+    dep[root] = 0;
+    while (top) {
+        uint32_t v = stack[--top];
+        order[visited++] = v;
+        for (uint64_t j = first[v + 1]; j > first[v]; j--) {
+            uint32_t c = kids[j - 1];
+            dep[c] = dep[v] + 1;
+            stack[top++] = c;
+        }
+    }
+    if (visited != V) { rc = ORACLE_ERR_CYCLE; goto out; }
+    /* sizes: every vertex after all of its descendants in reverse order */
+    for (uint64_t v = 0; v < V; v++) sz[v] = 1;
+    for (uint64_t j = V; j-- > 1;) {
+        uint32_t v = order[j];
+        sz[parent[v]] += sz[v];
+    }
+    for (uint64_t j = 0; j < V; j++) {
+        uint32_t v = order[j];
+        if (preorder) preorder[v] = (uint32_t)j;
+        if (depth) depth[v] = dep[v];
+        if (size) size[v] = sz[v];
+    }
+out:
+    free(first); free(kids); free(fill); free(stack); free(order); free(dep); free(sz);
+    return rc;
 }

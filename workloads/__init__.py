@@ -57,7 +57,7 @@ def _load():
     lib.wl_recursive_tree.argtypes = [u64, u64, vp]
     lib.wl_tree_depth.argtypes = [vp, u64, vp]
     lib.wl_euler_tour.restype = ctypes.c_int
-    lib.wl_euler_tour.argtypes = [u64, vp, u64, vp, vp, vp]
+    lib.wl_euler_tour.argtypes = [u64, vp, u64, vp, vp, vp, vp]
     del u32p
     _lib = lib
     return lib
@@ -193,25 +193,55 @@ class EulerInput:
     weight: np.ndarray        # int32: +1 down arcs, -1 up arcs
     parent: np.ndarray        # uint32[V]
     down_arc: np.ndarray      # uint32[V]: arc id of parent(v) -> v (entry 0 unused)
-    depth: np.ndarray         # uint32[V]: depth from parent recurrence
+    up_arc: np.ndarray        # uint32[V]: arc id of v -> parent(v) (entry 0 unused)
+    depth: np.ndarray | None  # uint32[V]: depth from the parent recurrence (trees with parent[v] < v)
+
+
+def recursive_tree(V: int, seed: int = 4) -> np.ndarray:
+    """Random recursive tree: parent[0] = 0, parent[v] uniform in [0, v)."""
+    parent = np.empty(V, dtype=np.uint32)
+    if V:
+        _load().wl_recursive_tree(seed, V, _ptr(parent))
+    return parent
+
+
+def relabel_tree(parent: np.ndarray, seed: int) -> np.ndarray:
+    """The same tree with vertices 1..V-1 renamed by a random permutation (the
+    root stays 0), so parents no longer have smaller ids."""
+    V = parent.size
+    if V < 3:
+        return parent.copy()
+    sigma = np.concatenate([[0], 1 + perm(V - 1, seed, 61)]).astype(np.uint32)
+    out = np.empty(V, dtype=np.uint32)
+    out[sigma] = sigma[parent]
+    return out
+
+
+def tour_of(parent: np.ndarray, seed: int = 4) -> EulerInput:
+    """Euler tour (arcs in random order, children visited in ascending id
+    order) of the tree parent[] rooted at 0."""
+    lib = _load()
+    parent = np.ascontiguousarray(parent, dtype=np.uint32)
+    V = parent.size
+    m = 2 * (V - 1) if V >= 2 else 0
+    succ = np.empty(m, dtype=np.uint32)
+    w = np.empty(m, dtype=np.int32)
+    down = np.full(V, 0xFFFFFFFF, dtype=np.uint32)
+    up = np.full(V, 0xFFFFFFFF, dtype=np.uint32)
+    if V >= 2:
+        rc = lib.wl_euler_tour(seed, _ptr(parent), V, _ptr(succ), _ptr(w), _ptr(down), _ptr(up))
+        if rc != 0:
+            raise MemoryError("wl_euler_tour")
+    depth = None
+    if V and bool(np.all(parent[1:] < np.arange(1, V, dtype=np.uint32))):
+        depth = np.empty(V, dtype=np.uint32)
+        lib.wl_tree_depth(_ptr(parent), V, _ptr(depth))
+    return EulerInput(succ, w, parent, down, up, depth)
 
 
 def euler_tour(V: int, seed: int = 4) -> EulerInput:
     """Euler tour of a random recursive tree (parent[v] uniform in [0, v))."""
-    lib = _load()
-    parent = np.empty(V, dtype=np.uint32)
-    lib.wl_recursive_tree(seed, V, _ptr(parent))
-    m = 2 * (V - 1) if V >= 2 else 0
-    succ = np.empty(m, dtype=np.uint32)
-    w = np.empty(m, dtype=np.int32)
-    down = np.empty(V, dtype=np.uint32)
-    if V >= 2:
-        rc = lib.wl_euler_tour(seed, _ptr(parent), V, _ptr(succ), _ptr(w), _ptr(down))
-        if rc != 0:
-            raise MemoryError("wl_euler_tour")
-    depth = np.empty(V, dtype=np.uint32)
-    lib.wl_tree_depth(_ptr(parent), V, _ptr(depth))
-    return EulerInput(succ, w, parent, down, depth)
+    return tour_of(recursive_tree(V, seed), seed)
 
 
 # ------------------------------------------------------------ serving trace --

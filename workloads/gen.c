@@ -211,10 +211,12 @@ void wl_tree_depth(const uint32_t* parent, uint64_t V, uint32_t* depth) {
  * pseudorandom permutation so the arcs sit in random order.
  * Children are visited in ascending id order. The tour starts at the down
  * arc of the root's first child and ends at the up arc of its last child.
- * w32: +1 on down arcs, -1 on up arcs. down_arc[v] = relabelled down(v)
- * (down_arc[0] is set to UINT32_MAX). Needs parent[v] < v. */
+ * w32: +1 on down arcs, -1 on up arcs. down_arc[v] = relabelled down(v),
+ * up_arc[v] = relabelled up(v) (entries of the root are UINT32_MAX; up_arc
+ * may be NULL). The root is vertex 0 (parent[0] == 0); other parents may have
+ * any id. */
 int wl_euler_tour(uint64_t seed, const uint32_t* parent, uint64_t V, uint32_t* succ, int32_t* w32,
-                  uint32_t* down_arc) {
+                  uint32_t* down_arc, uint32_t* up_arc) {
     if (V < 2) return 0;
     uint64_t m = 2 * (V - 1);
     uint32_t* first = (uint32_t*)malloc(V * sizeof(uint32_t));
@@ -230,11 +232,13 @@ int wl_euler_tour(uint64_t seed, const uint32_t* parent, uint64_t V, uint32_t* s
     prp_t p;
     prp_init(&p, seed, 43, m);
     down_arc[0] = NONE;
+    if (up_arc) up_arc[0] = NONE;
     #pragma omp parallel for schedule(static)
     for (int64_t v = 1; v < (int64_t)V; v++) {
         uint32_t dv = (uint32_t)prp_eval(&p, 2 * (uint64_t)(v - 1));
         uint32_t uv = (uint32_t)prp_eval(&p, 2 * (uint64_t)(v - 1) + 1);
         down_arc[v] = dv;
+        if (up_arc) up_arc[v] = uv;
         /* after entering v: go down to its first child, else come back up */
         uint32_t c = first[v];
         succ[dv] = (c != NONE) ? (uint32_t)prp_eval(&p, 2 * (uint64_t)(c - 1)) : uv;
