@@ -179,6 +179,34 @@ lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtyp
                                uint32_t* rank, uint32_t* root, uint64_t n,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* Tree computations by the Euler-tour technique (the paper ranks Euler tours
+ * of BFS trees as an input family, Section 3, and names tree algorithms as
+ * the users of list ranking, Section 1). One lr_prefix_sum over the tour with
+ * weight +1 on down arcs and -1 on up arcs gives, for every arc a, the number
+ * of arcs (rank) and #down - #up (sum) from a to the end of the tour; depth,
+ * preorder number and subtree size of every vertex follow from the values at
+ * the tour's first arc and at the vertex's two arcs.
+ *   succ  [m] uint32, m = 2(V-1): the tour as a successor array over its arcs
+ *         (one list; its last arc is the terminal). Ignored when V == 1.
+ *   down  [V] uint32: down[v] = id of the arc parent(v) -> v.
+ *   up    [V] uint32: up[v] = id of the arc v -> parent(v). The root's entries
+ *         of down and up are ignored.
+ *   root  the root vertex (< V).
+ *   depth    [V] uint32 output: edges from the root (root 0). May be NULL.
+ *   preorder [V] uint32 output: position of v in the depth-first order the
+ *         tour follows (root 0). May be NULL.
+ *   size     [V] uint32 output: vertices in v's subtree (root V). May be NULL.
+ * V <= 2^30. Workspace from lr_euler_tree_workspace_bytes (it holds the
+ * weights, the prefix sums, the ranks and an lr_prefix_sum workspace). With
+ * LR_VALIDATE the call also checks that down/up name every arc exactly once
+ * and that the tour is one list (LR_ERR_BAD_LIST otherwise); without it such
+ * input gives unspecified outputs, never an out-of-bounds access. opts apply
+ * to the inner lr_prefix_sum. */
+size_t lr_euler_tree_workspace_bytes(uint64_t V, const lr_opts* opts);
+lr_status lr_euler_tree(const uint32_t* succ, const uint32_t* down, const uint32_t* up, uint64_t V, uint32_t root,
+                        uint32_t* depth, uint32_t* preorder, uint32_t* size,
+                        void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
+
 /* Plan autotuner (the paper fixes its ruler-count constants by a parameter
  * study, Section 3 "Methodology"; this does the same on the caller's input).
  * Times lr_rank (w == LR_W_NONE, weight NULL) or lr_prefix_sum (any other w)

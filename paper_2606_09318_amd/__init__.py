@@ -77,6 +77,8 @@ def load():
         "lr_prefix_sum_wyllie": (st, [vp, vp, st, vp, vp, vp, u64, vp, sz, vp]),
         "lr_profile_last": (st, [P(ctypes.c_double), st]),
         "lr_autotune": (st, [vp, vp, st, u64, vp, sz, P(lr_opts), P(lr_opts), P(ctypes.c_double), st, P(st), vp]),
+        "lr_euler_tree_workspace_bytes": (sz, [u64, P(lr_opts)]),
+        "lr_euler_tree": (st, [vp, vp, vp, u64, u32, vp, vp, vp, vp, sz, P(lr_opts), vp]),
         "lr_server_create": (st, [P(lr_server_config), P(vp)]),
         "lr_server_submit": (st, [vp, P(lr_request), P(u64)]),
         "lr_server_poll": (st, [vp, u64, P(st), P(ctypes.c_double)]),
@@ -191,6 +193,16 @@ def lr_rank_batch(reqs: ctypes.Array, count: int, ws, opts=None, stream=None) ->
                                 _stream(stream))
 
 
+def lr_euler_tree_workspace_bytes(V: int, opts: lr_opts | None = None) -> int:
+    return int(load().lr_euler_tree_workspace_bytes(V, _opts(opts)))
+
+
+def lr_euler_tree(succ, down, up, V: int, root: int, depth, preorder, size, ws, opts=None, stream=None) -> int:
+    return load().lr_euler_tree(_ptr(succ), _ptr(down), _ptr(up), V, root, _ptr(depth), _ptr(preorder), _ptr(size),
+                                _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(), _opts(opts),
+                                _stream(stream))
+
+
 def lr_autotune(succ, weight, ws, base=None, stream=None):
     """Time candidate ruler spacings on this input; returns (status, best lr_opts, timings in ms)."""
     best = lr_opts()
@@ -249,3 +261,19 @@ def prefix_sum(succ, weight=None, want_rank=True, want_root=True, opts=None, str
     if s:
         raise LrError(s, "lr_prefix_sum")
     return sm, r, t
+
+
+def euler_tree(succ, down, up, root: int = 0, opts=None, stream=None):
+    """Depth, preorder number and subtree size of every vertex from an Euler
+    tour on the device (uint32 data as int32 tensors). Returns three tensors."""
+    import torch
+    V = down.numel()
+    dev = down.device
+    d = torch.empty(V, dtype=torch.int32, device=dev)
+    p = torch.empty(V, dtype=torch.int32, device=dev)
+    z = torch.empty(V, dtype=torch.int32, device=dev)
+    ws = workspace(lr_euler_tree_workspace_bytes(V, opts), dev)
+    s = lr_euler_tree(succ, down, up, V, root, d, p, z, ws, opts, stream)
+    if s:
+        raise LrError(s, "lr_euler_tree")
+    return d, p, z

@@ -81,3 +81,21 @@ def test_euler_tour_2p26_depths():
     assert torch.equal(depth.cpu(), torch.from_numpy(E.depth[1:].astype(np.int64)))
     del idx
     torch.cuda.empty_cache()
+
+
+def test_euler_tree_2p26():
+    """Tree computations on the 2^26-vertex random recursive tree: depth equals
+    the parent recurrence; sizes and preorder satisfy the tree invariants
+    (checked on the device)."""
+    V = 1 << 26
+    print(f"case: euler tree V={V}", flush=True)
+    E = workloads.euler_tour(V, seed=4)
+    d, p, z = lr.euler_tree(dev(E.succ), dev(E.down_arc), dev(E.up_arc), 0)
+    torch.cuda.synchronize()
+    assert torch.equal(d, dev(E.depth))
+    par = dev(E.parent).long()
+    nr = torch.arange(V, device="cuda") != 0
+    pl, zl, dl = p.long(), z.long(), d.long()
+    assert int(zl.sum()) == int((dl + 1).sum()) and int(z[0]) == V and int(p[0]) == 0
+    assert bool((pl[nr] > pl[par[nr]]).all()) and bool((pl[nr] < pl[par[nr]] + zl[par[nr]]).all())
+    assert torch.equal(torch.sort(p).values, torch.arange(V, dtype=torch.int32, device="cuda"))
