@@ -338,7 +338,26 @@ def weighted_bench() -> dict:
     ok = bool(torch.equal(depth.cpu(), torch.from_numpy(E.depth[1:].astype(np.int64))))
     out["euler_2p26_int32"] = {"ms": round(ms, 3), "g_elements_per_s": round(m / (ms * 1e-3) / 1e9, 3),
                                "arcs": m, "outputs": "int64 sum (depths)", "depths_ok": ok}
-    del E, succ, w, sm, ws, has_pred, nt, down, depth
+    del sm, ws, has_pred, nt, down, depth
+    torch.cuda.empty_cache()
+
+    # tree computations on the same tour: depth, preorder number and subtree
+    # size of every vertex (one prefix sum over the tour + per-vertex pass)
+    dn = torch.from_numpy(E.down_arc.view(np.int32)).cuda()
+    upa = torch.from_numpy(E.up_arc.view(np.int32)).cuda()
+    dv, pv, zv = (torch.empty(V, dtype=torch.int32, device="cuda") for _ in range(3))
+    tws = lr.workspace(lr.lr_euler_tree_workspace_bytes(V))
+
+    def call3():
+        st = lr.lr_euler_tree(succ, dn, upa, V, 0, dv, pv, zv, tws, None, stream)
+        if st:
+            raise lr.LrError(st, "lr_euler_tree")
+    ms = timed(call3)
+    ok = bool(torch.equal(dv.cpu(), torch.from_numpy(E.depth.view(np.int32)))) and int(zv[0]) == V \
+        and int(zv.long().sum()) == int((dv.long() + 1).sum())
+    out["euler_tree_2p26"] = {"ms": round(ms, 3), "g_vertices_per_s": round(V / (ms * 1e-3) / 1e9, 3),
+                              "vertices": V, "outputs": "depth, preorder, subtree size", "checks_ok": ok}
+    del E, succ, w, dn, upa, dv, pv, zv, tws
     torch.cuda.empty_cache()
     return out
 

@@ -67,3 +67,43 @@ def test_autotune_returns_valid_options(weighted):
         r, t = lr.rank(succ, opts=best)
         torch.cuda.synchronize()
         assert np.array_equal(host_u32(r), er) and np.array_equal(host_u32(t), et)
+
+
+def test_graph_capture_prefix_sum_switching_paths():
+    """A captured prefix sum whose automatic choice flips between replays
+    (local chains, then a random forest, then local chains again)."""
+    n = (1 << 21) + 3
+    print(f"case: graph capture prefix sum n={n}", flush=True)
+    inputs = []
+    for i in range(3):
+        if i % 2 == 0:
+            L = workloads.gamma_list(n, 0.001, seed=80 + i)
+            inputs.append((L.succ, workloads.weights(n, 80 + i, 3, -1000, 1000, np.int64)))
+        else:
+            F = workloads.forest(n, mean=64, n_long=1, long_len=1 << 19, seed=80 + i)
+            inputs.append((F.succ, F.weight))
+    succ = dev(inputs[0][0])
+    w = dev(inputs[0][1])
+    sm = torch.empty(n, dtype=torch.int64, device="cuda")
+    rank = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_I64))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        assert lr.lr_prefix_sum(succ, w, sm, rank, None, ws, None, s) == lr.LR_OK
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        st = lr.lr_prefix_sum(succ, w, sm, rank, None, ws, None, s)
+    assert st == lr.LR_OK
+    for i, (sc, wc) in enumerate(inputs * 2):
+        succ.copy_(torch.from_numpy(sc.view(np.int32)))
+        w.copy_(torch.from_numpy(wc))
+        sm.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _, er, _, es = oracle.rank(sc, wc)
+        assert np.array_equal(sm.cpu().numpy(), es), f"replay {i}"
+        assert np.array_equal(host_u32(rank), er), f"replay {i}"
+        torch.empty(1 << 20, device="cuda").normal_()
