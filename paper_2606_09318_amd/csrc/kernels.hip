@@ -37,6 +37,9 @@ constexpr int BASE_TPB = 1024;
 constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
 constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
 constexpr int PTPB = LR_PLACE_TPB;                   // placement kernels: lanes per workgroup
+#ifndef LR_XCD_GROUPS
+#define LR_XCD_GROUPS 1   // second grouping pass: the tiles of one coarse range on one XCD
+#endif
 
 // ------------------------------------------------------------------ fill --
 __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,
@@ -856,7 +859,22 @@ __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, 
     constexpr uint32_t T = PER * PTPB;
     const uint32_t tiles = (n + T - 1) / T;
     const uint32_t fan = 1u << (s1 - s2);
-    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    // All tiles of one coarse range append to the same fan frontiers. Workgroup
+    // i runs on XCD i mod 8, so the tiles of coarse range c go to workgroups
+    // on XCD c mod 8: the partial lines at a frontier then meet in one L2.
+    const uint32_t tpc = (1u << s1) / T;                        // tiles per coarse range
+    const bool xcd = LR_XCD_GROUPS && (gridDim.x % 8) == 0;
+    const uint32_t lane8 = blockIdx.x % 8, step = xcd ? gridDim.x / 8 : gridDim.x;
+    for (uint32_t q = xcd ? blockIdx.x / 8 : blockIdx.x;; q += step) {
+        uint32_t tile = q;
+        if (xcd) {
+            const uint32_t c = lane8 + 8 * (q / tpc);
+            tile = c * tpc + q % tpc;
+            if (c * tpc >= tiles) break;
+            if (tile >= tiles) continue;
+        } else if (tile >= tiles) {
+            break;
+        }
         const uint32_t c = (tile * T) >> s1;  // coarse range of this tile (T divides 2^s1)
         uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
         int64_t ss[PER];
