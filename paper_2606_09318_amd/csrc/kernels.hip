@@ -36,7 +36,6 @@ constexpr int CHASE_TPB = LR_CHASE_TPB;
 constexpr int BASE_TPB = 1024;
 constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
 constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
-constexpr int PTPB = LR_PLACE_TPB;                   // placement kernels: lanes per workgroup
 #ifndef LR_XCD_GROUPS
 #define LR_XCD_GROUPS 1   // second grouping pass: the tiles of one coarse range on one XCD
 #endif
@@ -706,12 +705,12 @@ struct PlaceArrays {
     int64_t* s;    // weighted rank (weighted levels only)
 };
 
-template <bool W>
-constexpr int place_per() { return (int)place_tile_records(W) / PTPB; }
+template <bool W, bool ROOT>
+constexpr int place_per() { return (int)place_tile_records(W, ROOT) / place_tpb(ROOT); }
 
 // LDS bytes of one grouping tile over nb ranges (device and host agree).
 __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, uint32_t nb) {
-    const size_t T = place_tile_records(weighted);
+    const size_t T = place_tile_records(weighted, root);
     size_t o = 8 * (size_t)nb + (root ? 12 : 8) * T;
     if (weighted) o = ((o + 7) & ~(size_t)7) + 8 * T;
     return o + 2 * T;
@@ -725,7 +724,8 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
                            const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t shift,
                            uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
                            Ctrl* ctrl, unsigned char* lds) {
-    constexpr uint32_t T = (uint32_t)PER * PTPB;
+    constexpr int TPB_ = place_tpb(ROOT);
+    constexpr uint32_t T = (uint32_t)PER * TPB_;
     size_t o = 0;
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + o);
     o += 4 * (size_t)nb;
@@ -747,18 +747,18 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
         o += 8 * (size_t)T;
     }
     uint16_t* sb = reinterpret_cast<uint16_t*>(lds + o);
-    __shared__ uint32_t scan_sh[PTPB / 64];
+    __shared__ uint32_t scan_sh[TPB_ / 64];
     __shared__ uint32_t tile_total;
     const uint32_t t = threadIdx.x;
     uint32_t lr[PER];
-    for (uint32_t b = t; b < nb; b += PTPB) hist[b] = 0;
+    for (uint32_t b = t; b < nb; b += TPB_) hist[b] = 0;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; ++j)
         if (xs[j] < n) lr[j] = atomicAdd(&hist[bs[j]], 1u);
     __syncthreads();
     // exclusive scan of hist (each lane owns a run of consecutive ranges) and reservations
-    const uint32_t chunk = (nb + PTPB - 1) / PTPB;
+    const uint32_t chunk = (nb + TPB_ - 1) / TPB_;
     const uint32_t a = min(t * chunk, nb), e = min(a + chunk, nb);
     uint32_t sum = 0;
     for (uint32_t b = a; b < e; ++b) sum += hist[b];
@@ -785,7 +785,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     }
     __syncthreads();
     const uint32_t cnt = tile_total;
-    for (uint32_t i = t; i < cnt; i += PTPB) {
+    for (uint32_t i = t; i < cnt; i += TPB_) {
         const uint32_t b = sb[i];
         const uint64_t lo = (uint64_t)(lo_bucket + b) << shift;
         const uint64_t hi = min(lo + (1ull << shift), (uint64_t)n);
@@ -803,7 +803,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
 }
 
 template <bool W, bool ROOT>
-__global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
+__global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
                                                 uint32_t* __restrict__ fill1, PlaceArrays<W> out, const uint32_t* dm,
@@ -812,8 +812,9 @@ __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_c
     if (dm) { n = dm[0]; S = dm[1]; }
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int PER = place_per<W>();
-    constexpr uint32_t T = PER * PTPB;
+    constexpr int PER = place_per<W, ROOT>();
+    constexpr int TPB_ = place_tpb(ROOT);
+    constexpr uint32_t T = PER * TPB_;
     const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
     const uint32_t nw = S + ctrl->lv[0].H;
     const uint32_t tiles = (used + T - 1) / T;
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_c
         int64_t ss[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t i = tile * T + j * PTPB + threadIdx.x;
+            const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
             xs[j] = (i < used) ? lg.x[i] : NONE;
             if (xs[j] < n) {
                 const uint32_t w = lg.w[i];
@@ -849,14 +850,15 @@ __global__ __launch_bounds__(PTPB) void k_place1(LogArrays<W> lg, uint32_t max_c
 }
 
 template <bool W, bool ROOT>
-__global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
+__global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
                                                 uint32_t* __restrict__ fill2, PlaceArrays<W> out, const uint32_t* dm,
                                                 Gate gate) {
     if (gate.off()) return;
     if (dm) n = dm[0];
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int PER = place_per<W>();
-    constexpr uint32_t T = PER * PTPB;
+    constexpr int PER = place_per<W, ROOT>();
+    constexpr int TPB_ = place_tpb(ROOT);
+    constexpr uint32_t T = PER * TPB_;
     const uint32_t tiles = (n + T - 1) / T;
     const uint32_t fan = 1u << (s1 - s2);
     // All tiles of one coarse range append to the same fan frontiers. Workgroup
@@ -880,7 +882,7 @@ __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, 
         int64_t ss[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t i = tile * T + j * PTPB + threadIdx.x;
+            const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
             xs[j] = (i < n) ? in.x[i] : NONE;
             if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
                 atomicOr(&ctrl->err, 64u);
@@ -900,7 +902,7 @@ __global__ __launch_bounds__(PTPB) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, 
 // One workgroup per fine range of 2^s2 elements: place the records by x in
 // LDS, then write the outputs in element order.
 template <bool W, bool ROOT, class Out>
-__global__ __launch_bounds__(PTPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
+__global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
                                                 const uint32_t* __restrict__ fill2, int check, Out out,
                                                 const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
@@ -918,14 +920,14 @@ __global__ __launch_bounds__(PTPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, 
     for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
         const uint32_t base = f << s2;
         const uint32_t len = min(R, n - base);
-        for (uint32_t i = t; i < len; i += PTPB) {
+        for (uint32_t i = t; i < len; i += place_tpb(ROOT)) {
             lr[i] = NONE;
             if constexpr (ROOT) lt[i] = NONE;
             if constexpr (W) ls[i] = INT64_MIN;
         }
         if (check && t == 0 && fill2[f] != len) atomicOr(&ctrl->err, 128u);
         __syncthreads();
-        for (uint32_t i = t; i < len; i += PTPB) {
+        for (uint32_t i = t; i < len; i += place_tpb(ROOT)) {
             const uint32_t k = in.x[base + i] - base;
             if (k < len) {
                 lr[k] = in.r[base + i];
@@ -936,7 +938,7 @@ __global__ __launch_bounds__(PTPB) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, 
         __syncthreads();
         if (t < len) {
             auto cur = out.begin(base + t);
-            for (uint32_t i = t; i < len; i += PTPB) {
+            for (uint32_t i = t; i < len; i += place_tpb(ROOT)) {
                 typename L::Val v;
                 v.c = lr[i];
                 if constexpr (W) v.s = ls[i];
@@ -1469,23 +1471,24 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     uint32_t* fill2 = fill1 + p.nb1;
     const PlaceArrays<W> P = place_arrays<W>(ws, p.off_p);
     const PlaceArrays<W> Q = place_arrays<W>(ws, p.off_log);
-    constexpr uint32_t T = place_tile_records(W);
+    constexpr uint32_t T = place_tile_records(W, ROOT);
+    const dim3 tpb(place_tpb(ROOT));
     const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
     const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
     LR_TRY(allow_lds(k_place1<W, ROOT>, l1));
-    hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), dim3(PTPB), l1, st, log_arrays<W>(ws, p.off_log),
+    hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), tpb, l1, st, log_arrays<W>(ws, p.off_log),
                        p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, dm, a.gate);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
     LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
-    hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), dim3(PTPB), l2, st, P, ctrl, n, p.s1, p.s2, fill2,
+    hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), tpb, l2, st, P, ctrl, n, p.s1, p.s2, fill2,
                        Q, dm, a.gate);
     LR_TRY(hipGetLastError());
     const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
     LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
     hipLaunchKernelGGL((k_place3<W, ROOT, Out0>), dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)),
-                       dim3(PTPB), l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0, dm, a.gate);
+                       tpb, l3, st, Q, ctrl, n, p.s2, p.nb2, fill2, (int)a.validate, out0, dm, a.gate);
     return hipGetLastError();
 }
 

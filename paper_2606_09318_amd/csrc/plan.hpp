@@ -29,15 +29,21 @@ constexpr uint64_t LOCAL_AUTO_MIN_N = 1ull << 21;
 #define LR_LOCAL_AUTO_16THS 5
 #endif
 constexpr uint64_t local_auto_cap(uint64_t n) { return (n * LR_LOCAL_AUTO_16THS + 15) / 16; }
-// grouping tiles: LR_PLACE_TPB lanes x LR_PLACE_PER records (half as many weighted)
+// grouping tiles: lanes x LR_PLACE_PER records (half as many weighted); the
+// passes that also carry roots use wider workgroups (measured faster there,
+// slower without roots)
 #ifndef LR_PLACE_TPB
 #define LR_PLACE_TPB 512
+#endif
+#ifndef LR_PLACE_TPB_ROOT
+#define LR_PLACE_TPB_ROOT 1024
 #endif
 #ifndef LR_PLACE_PER
 #define LR_PLACE_PER 8
 #endif
-constexpr uint32_t place_tile_records(bool weighted) {
-    return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * LR_PLACE_TPB;
+constexpr int place_tpb(bool root) { return root ? LR_PLACE_TPB_ROOT : LR_PLACE_TPB; }
+constexpr uint32_t place_tile_records(bool weighted, bool root) {
+    return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * (uint32_t)place_tpb(root);
 }
 
 struct Plan {
