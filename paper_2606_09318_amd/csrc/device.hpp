@@ -36,8 +36,10 @@ struct Ctrl {
     uint32_t dm[MAXL + 1];                  // element count per level when sizes are known only on the
                                             // device (the contracted list of tile-local contraction)
     uint32_t mode;                          // automatic contraction: 0 plain path, 1 tile-local contraction
+    uint32_t multi;                         // plain path with more than one list: predecessor marks needed
+    uint32_t pad[31];
 };
-static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
+static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
 // Device-side choice between two enqueued kernel sequences: a kernel whose
 // gate is set runs only when the word it points to holds `want`, and

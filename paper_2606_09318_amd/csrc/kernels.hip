@@ -164,6 +164,7 @@ __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restric
         ctrl->mode = mode;
         const bool single = mode == 0 && nt == 1 && hs < smp.m;
         ctrl->single = single ? 1u : 0u;
+        ctrl->multi = (mode == 0 && !single) ? 1u : 0u;
         if (single) {
             const uint32_t h = (uint32_t)hs;
             uint32_t H = 0;
@@ -708,10 +709,11 @@ struct PlaceArrays {
 template <bool W, bool ROOT>
 constexpr int place_per() { return (int)place_tile_records(W, ROOT) / place_tpb(ROOT); }
 
-// LDS bytes of one grouping tile over nb ranges (device and host agree).
-__host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, uint32_t nb) {
+// LDS bytes of one grouping tile over nb ranges (device and host agree);
+// without values only the element ids are grouped.
+__host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, uint32_t nb, bool vals = true) {
     const size_t T = place_tile_records(weighted, root);
-    size_t o = 8 * (size_t)nb + (root ? 12 : 8) * T;
+    size_t o = 8 * (size_t)nb + (vals ? (root ? 12 : 8) : 4) * T;
     if (weighted) o = ((o + 7) & ~(size_t)7) + 8 * T;
     return o + 2 * T;
 }
@@ -719,7 +721,7 @@ __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, u
 // LDS counting sort of one tile by range, then coalesced writes of each
 // range's run at [group(lo_bucket + b) + reserved, ...), space reserved with
 // one atomic per range and tile.
-template <bool W, bool ROOT, int PER>
+template <bool W, bool ROOT, int PER, bool VALS = true>
 __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER], const uint32_t (&ts)[PER],
                            const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t shift,
                            uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
@@ -734,7 +736,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     uint32_t* sx = reinterpret_cast<uint32_t*>(lds + o);
     o += 4 * (size_t)T;
     uint32_t* sr = reinterpret_cast<uint32_t*>(lds + o);
-    o += 4 * (size_t)T;
+    if constexpr (VALS) o += 4 * (size_t)T;
     uint32_t* st = nullptr;
     if constexpr (ROOT) {
         st = reinterpret_cast<uint32_t*>(lds + o);
@@ -777,7 +779,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
         if (xs[j] < n) {
             const uint32_t p = hist[bs[j]] + lr[j];
             sx[p] = xs[j];
-            sr[p] = rs[j];
+            if constexpr (VALS) sr[p] = rs[j];
             if constexpr (ROOT) st[p] = ts[j];
             if constexpr (W) sw[p] = ss[j];
             sb[p] = (uint16_t)bs[j];
@@ -792,7 +794,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
         const uint64_t p = lo + gbase[b] + (i - hist[b]);
         if (p < hi) {
             out.x[p] = sx[i];
-            out.r[p] = sr[i];
+            if constexpr (VALS) out.r[p] = sr[i];
             if constexpr (ROOT) out.t[p] = st[i];
             if constexpr (W) out.s[p] = sw[i];
         } else {
@@ -849,10 +851,12 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
     }
 }
 
-template <bool W, bool ROOT>
+// VALS = false groups element ids only; then the coarse ranges need not be
+// full and fill1 (their counts) bounds what is read.
+template <bool W, bool ROOT, bool VALS = true>
 __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
                                                 uint32_t* __restrict__ fill2, PlaceArrays<W> out, const uint32_t* dm,
-                                                Gate gate) {
+                                                const uint32_t* __restrict__ fill1, Gate gate) {
     if (gate.off()) return;
     if (dm) n = dm[0];
     extern __shared__ __align__(16) unsigned char lds[];
@@ -878,24 +882,27 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
             break;
         }
         const uint32_t c = (tile * T) >> s1;  // coarse range of this tile (T divides 2^s1)
+        const uint32_t lim = fill1 ? min(n, (c << s1) + fill1[c]) : n;
         uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
         int64_t ss[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            xs[j] = (i < n) ? in.x[i] : NONE;
+            xs[j] = (i < lim) ? in.x[i] : NONE;
             if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
                 atomicOr(&ctrl->err, 64u);
                 xs[j] = NONE;
             }
             if (xs[j] < n) {
-                rs[j] = in.r[i];
-                if constexpr (ROOT) ts[j] = in.t[i];
-                if constexpr (W) ss[j] = in.s[i];
+                if constexpr (VALS) {
+                    rs[j] = in.r[i];
+                    if constexpr (ROOT) ts[j] = in.t[i];
+                    if constexpr (W) ss[j] = in.s[i];
+                }
                 bs[j] = (xs[j] >> s2) - c * fan;
             }
         }
-        place_tile<W, ROOT, PER>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
+        place_tile<W, ROOT, PER, VALS>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
     }
 }
 
@@ -944,6 +951,68 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, C
                 if constexpr (W) v.s = ls[i];
                 out.store(cur, base + i, v, ROOT ? lt[i] : NONE);
             }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------- predecessor marks ----
+// Level 0 in log mode with more than one list: instead of one random byte
+// store per link, the link targets are grouped by element range with the
+// placement passes (ids only) and each range of 2^s2 ids writes its marks
+// from LDS in order. Every id is the target of at most one link, so no range
+// receives more targets than it has ids.
+template <bool VEC>
+__global__ __launch_bounds__(place_tpb(false)) void k_mark1(const uint32_t* __restrict__ succ, uint32_t n, uint32_t s1,
+                                                            uint32_t nb1, uint32_t* __restrict__ fill1,
+                                                            PlaceArrays<false> out, Ctrl* ctrl, Gate gate) {
+    if (gate.off()) return;
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int PER = place_per<false, false>();
+    constexpr int TPB_ = place_tpb(false);
+    constexpr uint32_t T = PER * TPB_;
+    const uint32_t tiles = (n + T - 1) / T;
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+        int64_t ss[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
+            const uint32_t s = (i < n) ? succ[i] : NONE;
+            xs[j] = (s != i && s < n) ? s : NONE;  // the target of a link
+            bs[j] = xs[j] >> s1;
+        }
+        place_tile<false, false, PER, false>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
+    }
+}
+
+// One workgroup per fine range: the range's targets set bytes in LDS, then
+// the range's marks are written in order (all n bytes get written).
+__global__ __launch_bounds__(place_tpb(false)) void k_mark3(const uint32_t* __restrict__ tx, uint32_t n, uint32_t s2,
+                                                            uint32_t nb2, const uint32_t* __restrict__ fill2,
+                                                            uint8_t* __restrict__ hp, Gate gate) {
+    if (gate.off()) return;
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t* mk = reinterpret_cast<uint32_t*>(lds);
+    constexpr int TPB_ = place_tpb(false);
+    const uint32_t R = 1u << s2;
+    for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
+        const uint32_t base = f << s2;
+        const uint32_t len = min(R, n - base);
+        for (uint32_t i = threadIdx.x; i < R / 4; i += TPB_) mk[i] = 0;
+        __syncthreads();
+        const uint32_t cnt = min(fill2[f], len);
+        uint8_t* mb = reinterpret_cast<uint8_t*>(mk);
+        for (uint32_t i = threadIdx.x; i < cnt; i += TPB_) {
+            const uint32_t k = tx[base + i] - base;
+            if (k < len) mb[k] = 1;
+        }
+        __syncthreads();
+        if ((len & 3) == 0) {
+            uint32_t* hw = reinterpret_cast<uint32_t*>(hp + base);
+            for (uint32_t i = threadIdx.x; i < len / 4; i += TPB_) hw[i] = mk[i];
+        } else {
+            for (uint32_t i = threadIdx.x; i < len; i += TPB_) hp[base + i] = mb[i];
         }
         __syncthreads();
     }
@@ -1483,7 +1552,7 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
     LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
     hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), tpb, l2, st, P, ctrl, n, p.s1, p.s2, fill2,
-                       Q, dm, a.gate);
+                       Q, dm, nullptr, a.gate);
     LR_TRY(hipGetLastError());
     const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
     LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
@@ -1499,6 +1568,43 @@ static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<
     return run_place_t<W, false>(a, p, res, S, ctrl, out0, dm);
 }
 
+
+// Predecessor marks of level 0 in log mode (more than one list): link targets
+// grouped by range in two passes, then written range by range from LDS. The
+// grouping arrays of the placement are free at this point; the marks land on
+// the first of them (hp0), after its grouped targets have been consumed.
+static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl* ctrl) {
+    char* ws = a.ws;
+    hipStream_t st = a.stream;
+    const uint32_t n = (uint32_t)p.m[0];
+    const Gate mg{&ctrl->multi, 1u};  // plain path taken and more than one list
+    uint32_t* fill1 = reinterpret_cast<uint32_t*>(ws + p.off_fill);
+    uint32_t* fill2 = fill1 + p.nb1;
+    LR_TRY(fill(fill1, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, mg));
+    const PlaceArrays<false> P = place_arrays<false>(ws, p.off_p);
+    const PlaceArrays<false> Q = place_arrays<false>(ws, p.off_log);
+    constexpr uint32_t T = place_tile_records(false, false);
+    const dim3 tpb(place_tpb(false));
+    const bool vec = ((uintptr_t)a.succ % 16) == 0;
+    const size_t l1 = place_lds_bytes(false, false, p.nb1, false);
+    if (vec) {
+        LR_TRY(allow_lds(k_mark1<true>, l1));
+        hipLaunchKernelGGL(k_mark1<true>, dim3(grid_for(n, T)), tpb, l1, st, a.succ, n, p.s1, p.nb1, fill1, P, ctrl, mg);
+    } else {
+        LR_TRY(allow_lds(k_mark1<false>, l1));
+        hipLaunchKernelGGL(k_mark1<false>, dim3(grid_for(n, T)), tpb, l1, st, a.succ, n, p.s1, p.nb1, fill1, P, ctrl,
+                           mg);
+    }
+    LR_TRY(hipGetLastError());
+    const size_t l2 = place_lds_bytes(false, false, 1u << (p.s1 - p.s2), false);
+    LR_TRY(allow_lds(k_place2<false, false, false>, l2));
+    hipLaunchKernelGGL((k_place2<false, false, false>), dim3(grid_for(n, T)), tpb, l2, st, P, ctrl, n, p.s1, p.s2,
+                       fill2, Q, nullptr, fill1, mg);
+    LR_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_mark3, dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), tpb, (size_t)1 << p.s2,
+                       st, Q.x, n, p.s2, p.nb2, fill2, hp0, mg);
+    return hipGetLastError();
+}
 
 // Validation of the input (LR_VALIDATE): range and in-degree counts.
 static hipError_t run_validate(const RunArgs& a, const Plan& p, uint32_t n) {
@@ -1553,12 +1659,16 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
     {
         if (a.prologue) LR_TRY(run_headsum(a, p, 0));
-        LR_TRY(fill(hp0, n, 0u, st, ctrl, g));
-        const bool vec = ((uintptr_t)a.succ % 16) == 0;
-        const uint32_t gd = grid_for(n, TPB * 4 * 4);
-        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
-        else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
-        LR_TRY(hipGetLastError());
+        if (p.log0) {
+            LR_TRY(run_marks(a, p, hp0, ctrl));
+        } else {
+            LR_TRY(fill(hp0, n, 0u, st, ctrl, g));
+            const bool vec = ((uintptr_t)a.succ % 16) == 0;
+            const uint32_t gd = grid_for(n, TPB * 4 * 4);
+            if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
+            else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
+            LR_TRY(hipGetLastError());
+        }
     }
     rec_ev(a, EV_DETECT);
     for (uint32_t l = 0; l < p.levels; ++l) {
