@@ -107,6 +107,8 @@ static size_t layout_levels(Plan* p, size_t off) {
             p->off_p[i] = off;
             off += align_up((size_t)n * (i == 3 ? 8 : 4));
         }
+        // weighted: the arrays after the first hold the interleaved (successor,
+        // weight) records during the level-0 chase (16 B per element)
         p->off_fill = off;
         off += align_up((size_t)(p->nb1 + p->nb2) * 4);
     }

@@ -157,6 +157,25 @@ struct SrcIn {
     }
 };
 
+// The input's successor and weight interleaved into one record, so a chase
+// step gathers one line instead of two (int32 weights: 8 B, int64: 16 B).
+template <int WT> struct PairRec;
+template <> struct alignas(8) PairRec<1> { uint32_t s; int32_t w; };
+template <> struct alignas(16) PairRec<2> { uint32_t s, pad; int64_t w; };
+
+template <int WT>
+struct SrcPair {
+    const PairRec<WT>* r;
+    uint32_t m;
+    using L = Lay<true>;
+    __device__ __forceinline__ void load(uint32_t x, uint32_t& nxt, typename L::Val& v) const {
+        const PairRec<WT> p = r[x];
+        const bool t = (p.s == x) | (p.s >= m);
+        nxt = t ? (TERM | x) : p.s;
+        v = t ? L::zero() : L::one_link((int64_t)p.w);
+    }
+};
+
 template <bool W>
 struct SrcLvl {
     const typename Lay<W>::Rec* e;

@@ -956,6 +956,21 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, C
     }
 }
 
+// Interleave successor and weight (weighted level 0 in log mode).
+template <int WT>
+__global__ __launch_bounds__(TPB) void k_pair(const uint32_t* __restrict__ succ, const void* __restrict__ weight,
+                                              uint32_t n, PairRec<WT>* __restrict__ out, Gate gate) {
+    if (gate.off()) return;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        PairRec<WT> r{};
+        r.s = succ[i];
+        if constexpr (WT == 1) r.w = static_cast<const int32_t*>(weight)[i];
+        if constexpr (WT == 2) r.w = static_cast<const int64_t*>(weight)[i];
+        out[i] = r;
+    }
+}
+
 // ------------------------------------------------- predecessor marks ----
 // Level 0 in log mode with more than one list: instead of one random byte
 // store per link, the link targets are grouped by element range with the
@@ -1696,8 +1711,20 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         if (l == 0) {
             if (p.log0) {
                 LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
-                if (p.lane_walks == 2) LR_TRY((launch_chase<W, true, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
-                else LR_TRY((launch_chase<W, true, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                if constexpr (W && WT != 0) {
+                    // weighted input: one record per element, interleaved into the
+                    // grouping arrays after the first (free until the placement)
+                    auto* pr = reinterpret_cast<PairRec<WT>*>(ws + p.off_p[1]);
+                    hipLaunchKernelGGL(k_pair<WT>, dim3(grid_for(n, TPB * 4)), dim3(TPB), 0, st, a.succ, a.weight, n,
+                                       pr, g);
+                    LR_TRY(hipGetLastError());
+                    SrcPair<WT> srcp{pr, n};
+                    LR_TRY((launch_chase<W, true, 1>(p, 0, srcp, smp, ctrl, ws, st, nullptr, g)));
+                } else if (p.lane_walks == 2) {
+                    LR_TRY((launch_chase<W, true, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                } else {
+                    LR_TRY((launch_chase<W, true, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                }
             } else {
                 if (p.lane_walks == 2) LR_TRY((launch_chase<W, false, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
                 else LR_TRY((launch_chase<W, false, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
