@@ -30,8 +30,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
-    ap.add_argument("--list", choices=["random", "block"], default="random",
-                    help="with --only-main: the random list, or the block-local list of the same size")
+    ap.add_argument("--list", choices=["random", "block", "forest"], default="random",
+                    help="with --only-main: the random list, the block-local list of the same size, or the "
+                         "2^27 forest with int64 weights (prefix sums, rank and root)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-weighted", action="store_true")
@@ -79,6 +80,9 @@ def main():
     n = args.n
     if args.list != "random" and not args.only_main:
         raise SystemExit("--list applies to --only-main runs")
+    if args.list == "forest":
+        forest_only(args, stream)
+        return
     t0 = time.time()
     L = workloads.random_list(n, seed=2, stream=0) if args.list == "random" else \
         workloads.block_list(n, block=4096, seed=2, stream=1)
@@ -213,6 +217,42 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
+
+
+def forest_only(args, stream):
+    """Profiling entry: the forest of 2^27 elements with int64 weights (lists of
+    geometric length, mean 64, plus 16 of 2^20), lr_prefix_sum with all outputs."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    n = 1 << 27
+    F = workloads.forest(n, mean=64, n_long=16, long_len=1 << 20, seed=3)
+    succ = torch.from_numpy(F.succ.view(np.int32)).cuda()
+    w = torch.from_numpy(F.weight).cuda()
+    sm = torch.empty(n, dtype=torch.int64, device="cuda")
+    r = torch.empty(n, dtype=torch.int32, device="cuda")
+    t = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_I64))
+
+    def step():
+        st = lr.lr_prefix_sum(succ, w, sm, r, t, ws, None, stream)
+        if st:
+            raise lr.LrError(st, "lr_prefix_sum")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    print(json.dumps({"workload": "forest 2^27 int64 weights", "ms_per_step": round(ms, 4),
+                      "g_elements_per_s": round(n / (ms * 1e-3) / 1e9, 3), "list": "forest"}))
 
 
 def locality_bench(n: int, rank, stream, gammas) -> dict:
