@@ -715,7 +715,7 @@ __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, u
     const size_t T = place_tile_records(weighted, root);
     size_t o = 8 * (size_t)nb + (vals ? (root ? 12 : 8) : 4) * T;
     if (weighted) o = ((o + 7) & ~(size_t)7) + 8 * T;
-    return o + 2 * T;
+    return o;
 }
 
 // LDS counting sort of one tile by range, then coalesced writes of each
@@ -748,7 +748,6 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
         sw = reinterpret_cast<int64_t*>(lds + o);
         o += 8 * (size_t)T;
     }
-    uint16_t* sb = reinterpret_cast<uint16_t*>(lds + o);
     __shared__ uint32_t scan_sh[TPB_ / 64];
     __shared__ uint32_t tile_total;
     const uint32_t t = threadIdx.x;
@@ -782,13 +781,12 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
             if constexpr (VALS) sr[p] = rs[j];
             if constexpr (ROOT) st[p] = ts[j];
             if constexpr (W) sw[p] = ss[j];
-            sb[p] = (uint16_t)bs[j];
         }
     }
     __syncthreads();
     const uint32_t cnt = tile_total;
     for (uint32_t i = t; i < cnt; i += TPB_) {
-        const uint32_t b = sb[i];
+        const uint32_t b = (sx[i] >> shift) - lo_bucket;  // the record's range, from its element id
         const uint64_t lo = (uint64_t)(lo_bucket + b) << shift;
         const uint64_t hi = min(lo + (1ull << shift), (uint64_t)n);
         const uint64_t p = lo + gbase[b] + (i - hist[b]);
