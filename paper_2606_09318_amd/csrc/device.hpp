@@ -193,7 +193,10 @@ struct SrcLvl {
 // Outputs take (element, value, root). A cursor lets an output keep state
 // between consecutive elements of one lane (the batch output walks its
 // request table forward instead of searching it per element).
-template <bool W>
+// The caller's outputs. RK / RT say at compile time whether rank and root are
+// written (the ranking kernels are instantiated per combination, so their
+// store loops carry no branches); DYN checks the pointers at run time instead.
+template <bool W, bool RK = true, bool RT = true, bool DYN = false>
 struct OutUser {
     uint32_t* rank;
     uint32_t* root;
@@ -202,9 +205,15 @@ struct OutUser {
     struct Cur {};
     __device__ __forceinline__ Cur begin(uint32_t) const { return {}; }
     __device__ __forceinline__ void store(Cur&, uint32_t i, typename L::Val v, uint32_t r) const {
-        if (rank) rank[i] = v.c;
-        if (root) root[i] = r;
-        if constexpr (W) { if (sum) sum[i] = v.s; }
+        if constexpr (DYN) {
+            if (rank) rank[i] = v.c;
+            if (root) root[i] = r;
+            if constexpr (W) { if (sum) sum[i] = v.s; }
+        } else {
+            if constexpr (RK) rank[i] = v.c;
+            if constexpr (RT) root[i] = r;
+            if constexpr (W) sum[i] = v.s;
+        }
     }
 };
 

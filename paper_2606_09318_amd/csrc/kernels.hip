@@ -648,6 +648,7 @@ __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __r
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t ntile = (m + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
+    bool bad = false;
     for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
         const uint32_t base = tile * 64 * EXPAND_CH;
         if (base + lane >= m) continue;
@@ -667,20 +668,24 @@ __global__ __launch_bounds__(TPB) void k_expand(const typename Lay<W>::Slot* __r
             const uint32_t i = base + j * 64 + lane;
             if (i < m && sv[j].w < nw) rv[j] = res[sv[j].w];
         }
+        // all values first, then the stores (see k_lc_expand)
+        typename L::Val ov[EXPAND_CH];
+        uint32_t orr[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const typename L::Slot s = sv[j];
+            const bool ok = s.w < nw;
+            bad |= !ok && (base + j * 64 + lane < m);
+            ov[j] = ok ? L::sub(L::val(rv[j]), L::val(s)) : L::junk();
+            orr[j] = ok ? rv[j].root : NONE;
+        }
 #pragma unroll
         for (int j = 0; j < EXPAND_CH; ++j) {
             const uint32_t i = base + j * 64 + lane;
-            if (i < m) {
-                const typename L::Slot s = sv[j];
-                if (s.w < nw) {
-                    out.store(cur, i, L::sub(L::val(rv[j]), L::val(s)), rv[j].root);
-                } else {
-                    atomicOr(&ctrl->err, 4u);
-                    out.store(cur, i, L::junk(), NONE);
-                }
-            }
+            if (i < m) out.store(cur, i, ov[j], orr[j]);
         }
     }
+    if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, 4u);
 }
 
 // ---------------------------------------------------------- placement ----
@@ -1049,7 +1054,7 @@ __global__ __launch_bounds__(TPB) void k_wy_init(Src src, typename Lay<W>::Rec* 
 template <bool W, bool LAST>
 __global__ __launch_bounds__(TPB) void k_wy_round(const typename Lay<W>::Rec* __restrict__ a,
                                                   typename Lay<W>::Rec* __restrict__ b, uint32_t m,
-                                                  OutUser<W> out) {
+                                                  OutUser<W, true, true, true> out) {
     using L = Lay<W>;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
@@ -1057,7 +1062,7 @@ __global__ __launch_bounds__(TPB) void k_wy_round(const typename Lay<W>::Rec* __
         const typename L::Rec q = a[r.nxt];
         const typename L::Val d = L::add(L::val(r), L::val(q));
         if constexpr (LAST) {
-            typename OutUser<W>::Cur c;
+            typename OutUser<W, true, true, true>::Cur c;
             out.store(c, i, d, q.nxt);
         } else {
             b[i] = L::rec(q.nxt, d);
@@ -1067,12 +1072,12 @@ __global__ __launch_bounds__(TPB) void k_wy_round(const typename Lay<W>::Rec* __
 
 template <bool W>
 __global__ __launch_bounds__(TPB) void k_wy_copy(const typename Lay<W>::Rec* __restrict__ a, uint32_t m,
-                                                 OutUser<W> out) {
+                                                 OutUser<W, true, true, true> out) {
     using L = Lay<W>;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
         const typename L::Rec r = a[i];
-        typename OutUser<W>::Cur c;
+        typename OutUser<W, true, true, true>::Cur c;
         out.store(c, i, L::val(r), r.nxt);
     }
 }
@@ -1380,8 +1385,12 @@ __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ 
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t ntile = (n + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
+    static_assert((64 * EXPAND_CH) <= LC_T && LC_T % (64 * EXPAND_CH) == 0, "a wave tile lies in one chain tile");
+    bool bad = false;
     for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
         const uint32_t base = tile * 64 * EXPAND_CH;
+        // one chain tile per wave tile: its first compact id is one load
+        const uint32_t cb = cnt[base >> LOCAL_SHIFT];
         if (base + lane >= n) continue;
         auto cur = out.begin(base + lane);
         uint32_t pv[EXPAND_CH];
@@ -1390,33 +1399,40 @@ __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ 
             const uint32_t i = base + j * 64 + lane;
             pv[j] = (i < n) ? pos[i] : NONE;
         }
-        // every gather before any store (see k_expand)
+        // every gather issued before any store (see k_expand)
         uint32_t cv[EXPAND_CH];
         typename L::Res rv[EXPAND_CH];
         int64_t wv[EXPAND_CH];
 #pragma unroll
         for (int j = 0; j < EXPAND_CH; ++j) {
             const uint32_t i = base + j * 64 + lane;
-            cv[j] = (i >= n || pv[j] == NONE) ? NONE : cnt[i >> LOCAL_SHIFT] + (pv[j] >> 16);
+            cv[j] = (pv[j] == NONE) ? NONE : cb + (pv[j] >> 16);
             if (cv[j] < mc) rv[j] = res[cv[j]];
             wv[j] = 0;
             if constexpr (W) if (i < n) wv[j] = wd[i];
         }
+        // all values first, then the stores: vector-memory counters also count
+        // stores, so a store between two dependent gathers would make every
+        // later gather wait for it
+        typename L::Val ov[EXPAND_CH];
+        uint32_t orr[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const bool ok = cv[j] < mc;
+            bad |= !ok && (base + j * 64 + lane < n);
+            typename L::Val v = L::val(rv[j]);
+            v.c -= pv[j] & 0xffffu;
+            if constexpr (W) v.s -= wv[j];
+            ov[j] = ok ? v : L::junk();
+            orr[j] = ok ? rv[j].root : NONE;
+        }
 #pragma unroll
         for (int j = 0; j < EXPAND_CH; ++j) {
             const uint32_t i = base + j * 64 + lane;
-            if (i >= n) continue;
-            if (cv[j] < mc) {
-                typename L::Val v = L::val(rv[j]);
-                v.c -= pv[j] & 0xffffu;
-                if constexpr (W) v.s -= wv[j];
-                out.store(cur, i, v, rv[j].root);
-            } else {
-                atomicOr(&ctrl->err, 4u);
-                out.store(cur, i, L::junk(), NONE);
-            }
+            if (i < n) out.store(cur, i, ov[j], orr[j]);
         }
     }
+    if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, 4u);
 }
 
 // ============================================================== host side ==
@@ -1901,18 +1917,28 @@ static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
     return run_srs_t<W, WT>(pa, out0);
 }
 
+template <int WT>
+static hipError_t run_weighted(const RunArgs& a) {
+    if (a.rank && a.root) return run_any_t<true, WT>(a, OutUser<true, true, true>{a.rank, a.root, a.sum});
+    if (a.rank) return run_any_t<true, WT>(a, OutUser<true, true, false>{a.rank, nullptr, a.sum});
+    if (a.root) return run_any_t<true, WT>(a, OutUser<true, false, true>{nullptr, a.root, a.sum});
+    return run_any_t<true, WT>(a, OutUser<true, false, false>{nullptr, nullptr, a.sum});
+}
+
 hipError_t run_srs(const RunArgs& a) {
     const Plan& p = *a.plan;
     if (a.desc) {
         OutBatch out{a.desc, a.bases, a.count};
         return run_any_t<false, 0>(a, out);
     }
-    if (!p.weighted) return run_any_t<false, 0>(a, OutUser<false>{a.rank, a.root, nullptr});
-    OutUser<true> out{a.rank, a.root, a.sum};
-    switch (a.wt) {
-        case 1: return run_any_t<true, 1>(a, out);
-        case 2: return run_any_t<true, 2>(a, out);
-        default: return run_any_t<true, 0>(a, out);
+    if (!p.weighted) {  // rank is required
+        if (a.root) return run_any_t<false, 0>(a, OutUser<false, true, true>{a.rank, a.root, nullptr});
+        return run_any_t<false, 0>(a, OutUser<false, true, false>{a.rank, nullptr, nullptr});
+    }
+    switch (a.wt) {  // the sum is required; rank and root are optional
+        case 1: return run_weighted<1>(a);
+        case 2: return run_weighted<2>(a);
+        default: return run_weighted<0>(a);
     }
 }
 
@@ -1922,7 +1948,7 @@ static hipError_t run_wyllie_t(const RunArgs& a, uint64_t n64) {
     const uint32_t n = (uint32_t)n64;
     auto* A = reinterpret_cast<typename L::Rec*>(a.ws);
     auto* B = reinterpret_cast<typename L::Rec*>(a.ws + ((n64 * sizeof(typename L::Rec) + ALIGN - 1) / ALIGN) * ALIGN);
-    OutUser<W> out{a.rank, a.root, W ? a.sum : nullptr};
+    OutUser<W, true, true, true> out{a.rank, a.root, W ? a.sum : nullptr};
     const uint32_t g = grid_for(n, TPB * 4);
     SrcIn<W, WT> src{a.succ, a.weight, n};
     rec_ev(a, EV_START);
