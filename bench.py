@@ -448,6 +448,16 @@ def serve_bench(count: int) -> dict:
                      "throughput_g_elements_per_s": round(total / mk / 1e9, 3), "makespan_s": round(mk, 3),
                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
                      "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    # offered-load sweep for the batched server (same trace, arrival times scaled)
+    res["load_sweep"] = []
+    for load in (0.5, 0.7, 0.9, 1.1):
+        scale = 0.8 / load
+        st, lat, sts, mk = lr.lr_server_replay(cfg(2, count), reqs, [a * scale for a in arr], count)
+        lat = np.array(lat) * 1e3
+        res["load_sweep"].append({"load": load, "status_ok": bool(st == 0 and all(s == 0 for s in sts)),
+                                  "throughput_g_elements_per_s": round(total / mk / 1e9, 3),
+                                  "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                  "p99_ms": round(float(np.percentile(lat, 99)), 3)})
     # spot check: a few requests against their closed form
     for i in range(0, count, max(1, count // 16)):
         Lq = workloads.request_input(tr[i])
