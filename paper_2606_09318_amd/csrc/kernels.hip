@@ -18,6 +18,19 @@
 //            root (ruler propagation).
 // Walks run forward along succ, so ranks toward the terminal come out
 // directly and no list reversal is needed.
+//
+// Level 0 of large inputs (n >= 2^22) logs the chase's visits and places the
+// results by element range (place1/2/3) instead of storing at random
+// addresses; with more than one list its predecessor marks are grouped by
+// range the same way (mark1, place2 on ids, mark3), and weighted inputs are
+// interleaved into one record per element first (pair).
+//
+// Tile-local contraction (Section 2.3): chains of links inside 4096-id tiles
+// are contracted first (lc_chain, lc_scan, lc_compact), the levels above rank
+// the contracted list with sizes read from the device, and lc_expand restores
+// every element. By default the head-sum pass chooses on the device between
+// this path and the plain one; both are enqueued and the kernels of the path
+// not taken return at once (Gate).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
