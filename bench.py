@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--serve-count", type=int, default=4096)
     ap.add_argument("--gamma", type=float, nargs="*", default=[0.0, 0.01, 0.1, 0.3],
                     help="List(n, gamma) locality sweep (empty: none)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only the device access-rate calibration (lr_calibrate), one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -67,6 +69,10 @@ def main():
     torch.cuda.set_device(0)
     dev = "cuda:0"
     stream = torch.cuda.current_stream()
+
+    if args.calibrate:
+        print(json.dumps({"calibration": lr.calibrate(dev)}))
+        return
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
@@ -197,6 +203,9 @@ def main():
     extra["locality"] = locality_bench(n, rank, stream, args.gamma)
     extra["block_local_4096"] = extra["locality"]["block_local_4096"]
     del rank, root, L
+    torch.cuda.empty_cache()
+
+    extra["calibration"] = lr.calibrate(dev)
     torch.cuda.empty_cache()
 
     if not args.no_weighted:

@@ -231,6 +231,19 @@ lr_status lr_autotune(const uint32_t* succ, const void* weight, lr_wtype w, uint
  * written. */
 int lr_profile_last(double* ms, int cap);
 
+/* Device calibration (diagnostic, not part of any ranking call): on the
+ * current device, with `ws` as scratch (at least lr_calibrate_workspace_bytes,
+ * about 3 GiB, contents destroyed), times 2^28 accesses of each kind and
+ * writes up to `cap` rates to `out`: [0] streaming copy of 1 GiB (GB/s, read +
+ * written bytes), [1] 4 B gathers at hashed positions of a 1 GiB array, [2] 8 B
+ * stores into 1 GiB, [3] 8 B stores into 256 MiB, [4] 1 B stores into 256 MiB,
+ * [5] bit sets (atomic OR) in a 32 MiB bitmap (G accesses/s). These are the
+ * ceilings the ranking kernels' random accesses are measured against.
+ * Synchronises `stream`. Returns the number of rates written, or a negative
+ * lr_status. */
+size_t lr_calibrate_workspace_bytes(void);
+int lr_calibrate(void* ws, size_t ws_bytes, double* out, int cap, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* lr_status_string(lr_status s);
 

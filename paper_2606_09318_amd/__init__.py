@@ -78,6 +78,8 @@ def load():
         "lr_profile_last": (st, [P(ctypes.c_double), st]),
         "lr_autotune": (st, [vp, vp, st, u64, vp, sz, P(lr_opts), P(lr_opts), P(ctypes.c_double), st, P(st), vp]),
         "lr_euler_tree_workspace_bytes": (sz, [u64, P(lr_opts)]),
+        "lr_calibrate_workspace_bytes": (sz, []),
+        "lr_calibrate": (st, [vp, sz, P(ctypes.c_double), st, vp]),
         "lr_euler_tree": (st, [vp, vp, vp, u64, u32, vp, vp, vp, vp, sz, P(lr_opts), vp]),
         "lr_server_create": (st, [P(lr_server_config), P(vp)]),
         "lr_server_submit": (st, [vp, P(lr_request), P(u64)]),
@@ -277,3 +279,16 @@ def euler_tree(succ, down, up, root: int = 0, opts=None, stream=None):
     if s:
         raise LrError(s, "lr_euler_tree")
     return d, p, z
+
+
+def calibrate(device="cuda", stream=None) -> dict:
+    """Device access rates (lr_calibrate): streaming copy GB/s and random
+    gather / store / bit-set rates in G accesses/s."""
+    ws = workspace(load().lr_calibrate_workspace_bytes(), device)
+    out = (ctypes.c_double * 6)()
+    k = load().lr_calibrate(_ptr(ws), ws.numel(), out, 6, _stream(stream))
+    if k < 0:
+        raise LrError(-k, "lr_calibrate")
+    names = ["copy_gb_s", "gather4_1gib_g_s", "store8_1gib_g_s", "store8_256mib_g_s", "store1_256mib_g_s",
+             "bitset_32mib_g_s"]
+    return {nm: round(out[i], 2) for i, nm in enumerate(names[:k])}
