@@ -1149,8 +1149,9 @@ constexpr uint32_t LC_T = LOCAL_TILE;
 constexpr int LC_PER = LC_T / LC_TPB;   // elements per lane
 constexpr int LC_ROUNDS = 14;           // > log2(LC_T): chains of a tile converge within this many rounds
 constexpr int LC_CHUNKS = LC_T / 64;    // 64-id chunks of a tile (one wave ballot each)
+constexpr uint32_t LC_TGT = 0xffffu;    // jump entry: target (tile-relative id); link count in bits 16-31
 
-static_assert(LC_T == (1u << LOCAL_SHIFT) && LC_T <= 65536 && LC_CHUNKS <= 64, "local tile");
+static_assert(LC_T == (1u << LOCAL_SHIFT) && LC_T <= LC_TGT + 1 && LC_CHUNKS <= 64, "local tile");
 
 // start ids are compact: tile base (scanned start counts) + starts before the
 // element in its tile (word prefix + bits below it in its 32-id word)
@@ -1247,10 +1248,10 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
 #pragma unroll
                 for (int j = 0; j < LC_PER; ++j) {
                     const uint32_t i = j * LC_TPB + threadIdx.x;
-                    const uint32_t p = v[j] & 0xffffu;
+                    const uint32_t p = v[j] & LC_TGT;
                     if (i < len && p != i) {
                         const uint32_t u = PD[p];
-                        const uint32_t q = u & 0xffffu;
+                        const uint32_t q = u & LC_TGT;
                         if (q != p) {
                             v[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
                             PD[i] = v[j];
@@ -1265,12 +1266,12 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
 #pragma unroll
                 for (int j = 0; j < LC_PER; ++j) {
                     const uint32_t i = j * LC_TPB + threadIdx.x;
-                    const uint32_t p = v[j] & 0xffffu;
+                    const uint32_t p = v[j] & LC_TGT;
                     nv[j] = v[j];
                     nw[j] = ws[j];
                     if (i < len && p != i) {
                         const uint32_t u = PD[p];
-                        const uint32_t q = u & 0xffffu;
+                        const uint32_t q = u & LC_TGT;
                         if (q != p) {
                             nv[j] = q | (((v[j] >> 16) + (u >> 16)) << 16);
                             nw[j] = ws[j] + WS[p];
@@ -1298,9 +1299,11 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
             const uint32_t i = j * LC_TPB + threadIdx.x;
             if (i >= len) continue;
             const uint32_t x = b + i;
-            const uint32_t p = v[j] & 0xffffu;
+            const uint32_t p = v[j] & LC_TGT;
             const uint32_t dist = v[j] >> 16;
-            if ((PD[p] & 0xffffu) != p) {  // never reached a start: x is on a cycle inside the tile
+            // a start has no predecessor in the tile (its start bit); on a cycle inside
+            // the tile the jumps never reach one, even where a target comes back to itself
+            if (!((DIR[p >> 5].x >> (p & 31)) & 1u)) {
                 pos[x] = NONE;
                 atomicOr(&ctrl->err, 8u);
                 continue;

@@ -289,3 +289,22 @@ def test_automatic_choice_batch():
         assert np.array_equal(host_u32(r), er)
         if t is not None:
             assert np.array_equal(host_u32(t), et)
+
+
+@pytest.mark.parametrize("cycle_len", [1, 2, 3, 4, 7, 16, 100, 4096])
+def test_validate_cycles_inside_a_tile(cycle_len):
+    """A cycle of any length inside one tile beside a valid list: the jumps of
+    a cycle element can come back to the element itself, which must still be
+    reported (the element is not a chain start)."""
+    o = local_opts(flags=lr.LR_VALIDATE | LOCAL)
+    n = 3 * 4096
+    succ = np.minimum(np.arange(n) + 1, n - 1).astype(np.uint32)
+    c0 = 4096 + 17 if cycle_len < 4000 else 4096
+    succ[c0 - 1] = c0 - 1                                   # the list before the cycle ends here
+    idx = np.arange(c0, c0 + cycle_len)
+    succ[idx] = np.roll(idx, -1)                            # close the cycle
+    if cycle_len == 1:
+        succ[c0] = c0 + 1 if c0 + 1 < n else c0            # a self-loop is a terminal: use a 2-cycle instead
+        succ[c0 + 1] = c0
+    assert gpu_rank(succ, o)[0] == lr.LR_ERR_BAD_LIST, cycle_len
+    assert gpu_rank(succ, local_opts())[0] == lr.LR_OK     # without validation: no fault
