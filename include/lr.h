@@ -77,12 +77,14 @@ enum {
  * its rank from its chain's first element. It pays off when most links are
  * local (a list stored mostly in list order) and costs extra passes when few
  * are. By default (neither flag) inputs of 2^21 elements or more choose on
- * the device: the pass that looks for the head of a single list also counts
- * the local links, and the contracted path runs when the contracted list
- * keeps at most 5/16 of the elements (at least about 69% of the links are
- * local); nothing is synchronised, both paths are enqueued
- * and the one not taken returns at once. Results are identical in every
- * mode. Applies to lr_rank, lr_prefix_sum and lr_rank_batch. */
+ * the device: the local links of every 16th tile are counted, and the
+ * contracted path runs when they extrapolate to a contracted list of at most
+ * 4/16 of the elements (at least 75% of the links local). The contracted path
+ * counts its list exactly and, if it holds more than 5/16 of the elements
+ * (the most its workspace takes), hands over to the plain path on the
+ * device. Nothing is synchronised: both paths are enqueued and the one not
+ * taken returns at once. Results are identical in every mode. Applies to
+ * lr_rank, lr_prefix_sum and lr_rank_batch. */
 
 #define LR_MAX_LEVELS 8
 

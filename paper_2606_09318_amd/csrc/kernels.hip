@@ -28,9 +28,10 @@
 // Tile-local contraction (Section 2.3): chains of links inside 4096-id tiles
 // are contracted first (lc_chain, lc_scan, lc_compact), the levels above rank
 // the contracted list with sizes read from the device, and lc_expand restores
-// every element. By default the head-sum pass chooses on the device between
-// this path and the plain one; both are enqueued and the kernels of the path
-// not taken return at once (Gate).
+// every element. By default a sample of the tiles chooses on the device
+// between this path and the plain one (lsample, ldecide; the exact count in
+// lc_scan can still hand over to the plain path); both are enqueued and the
+// kernels of the path not taken return at once (Gate).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -104,14 +105,15 @@ __global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ suc
 // store per element; the marking passes then do nothing.
 template <bool VEC>
 __global__ __launch_bounds__(TPB) void k_headsum(const uint32_t* __restrict__ succ, uint32_t m,
-                                                 uint32_t* __restrict__ partial) {
+                                                 uint32_t* __restrict__ partial, Gate gate) {
+    if (gate.off()) return;
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t hs = 0;
-    uint32_t nt = 0, loc = 0;
+    uint32_t nt = 0;
     auto one = [&](uint32_t x, uint32_t s) {
         if (s == x || s >= m) { ++nt; hs += x; }
-        else { hs += (uint64_t)x - s; loc += (s >> LOCAL_SHIFT) == (x >> LOCAL_SHIFT); }
+        else hs += (uint64_t)x - s;
     };
     uint32_t done = 0;
     if constexpr (VEC) {
@@ -127,57 +129,109 @@ __global__ __launch_bounds__(TPB) void k_headsum(const uint32_t* __restrict__ su
     }
     for (uint32_t i = done + g; i < m; i += stride) one(i, succ[i]);
     __shared__ uint64_t shs[TPB / 64];
-    __shared__ uint32_t snt[TPB / 64], sloc[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         hs += __shfl_xor(hs, o);
         nt += __shfl_xor(nt, o);
-        loc += __shfl_xor(loc, o);
     }
-    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; sloc[threadIdx.x >> 6] = loc; }
+    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; loc += sloc[i]; }
+        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
         partial[4 * blockIdx.x] = nt;
-        partial[4 * blockIdx.x + 1] = loc;
+        partial[4 * blockIdx.x + 1] = 0;
         reinterpret_cast<uint64_t*>(partial)[2 * blockIdx.x + 1] = hs;
     }
 }
 
-// Sums the partials. Automatic contraction (auto_cap > 0): the contracted
-// list has one element per element without a predecessor in its tile, i.e.
-// m minus the local links; the tile-local path is taken (mode 1) when that is
-// at most auto_cap. Otherwise, with exactly one terminal (and a head inside
-// the range), it publishes the head as the level's only initial-element walk.
+// Automatic contraction, the guess: local links counted on every
+// LOCAL_SAMPLE_STRIDE-th tile (one workgroup per sampled tile at a time);
+// partial[4b] = local links, partial[4b + 1] = elements looked at.
+template <bool VEC>
+__global__ __launch_bounds__(TPB) void k_lsample(const uint32_t* __restrict__ succ, uint32_t m,
+                                                 uint32_t* __restrict__ partial) {
+    const uint32_t ntiles = (m + LOCAL_TILE - 1) / LOCAL_TILE;
+    const uint32_t nsamp = (ntiles + LOCAL_SAMPLE_STRIDE - 1) / LOCAL_SAMPLE_STRIDE;
+    uint32_t loc = 0, seen = 0;
+    for (uint32_t q = blockIdx.x; q < nsamp; q += gridDim.x) {
+        const uint32_t b = q * LOCAL_SAMPLE_STRIDE * LOCAL_TILE;
+        const uint32_t len = min(LOCAL_TILE, m - b);
+        for (uint32_t i = threadIdx.x; i < len; i += TPB) {
+            const uint32_t s = succ[b + i];
+            loc += s != b + i && s < m && (s >> LOCAL_SHIFT) == (b >> LOCAL_SHIFT);
+        }
+        seen += len;
+    }
+    __shared__ uint32_t sl[TPB / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) loc += __shfl_xor(loc, o);
+    if ((threadIdx.x & 63) == 0) sl[threadIdx.x >> 6] = loc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < TPB / 64; ++i) loc += sl[i];
+        partial[4 * blockIdx.x] = loc;
+        partial[4 * blockIdx.x + 1] = seen;
+    }
+}
+
+// The guess: contract when the sampled tiles extrapolate to a contracted
+// list of at most thr elements. The contracted path's scan checks the exact
+// size against its capacity and falls back to the plain path if it is larger.
+__global__ __launch_bounds__(TPB) void k_ldecide(const uint32_t* __restrict__ partial, uint32_t nparts, uint32_t m,
+                                                 uint32_t thr, Ctrl* ctrl) {
+    uint64_t loc = 0, seen = 0;
+    for (uint32_t i = threadIdx.x; i < nparts; i += TPB) {
+        loc += partial[4 * i];
+        seen += partial[4 * i + 1];
+    }
+    __shared__ uint64_t sl[TPB / 64], ss[TPB / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        loc += __shfl_xor(loc, o);
+        seen += __shfl_xor(seen, o);
+    }
+    if ((threadIdx.x & 63) == 0) { sl[threadIdx.x >> 6] = loc; ss[threadIdx.x >> 6] = seen; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < TPB / 64; ++i) { loc += sl[i]; seen += ss[i]; }
+        const uint64_t est_local = seen ? loc * (uint64_t)m / seen : 0;
+        ctrl->mode = (seen && (uint64_t)m - est_local <= thr) ? 1u : 0u;
+        ctrl->single = 0;  // set by the plain path's head sum if that path runs
+        ctrl->multi = 0;
+    }
+}
+
+// Sums the partials (plain path). With exactly one terminal (and a head
+// inside the range) it publishes the head as the level's only
+// initial-element walk; multi says whether predecessor marks are needed.
 __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restrict__ partial, uint32_t nparts,
                                                        Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
-                                                       uint32_t rec_bytes, uint32_t auto_cap) {
+                                                       uint32_t rec_bytes, Gate gate) {
+    if (gate.off()) return;
     uint64_t hs = 0;
-    uint32_t nt = 0, loc = 0;
+    uint32_t nt = 0;
     for (uint32_t i = threadIdx.x; i < nparts; i += TPB) {
         nt += partial[4 * i];
-        loc += partial[4 * i + 1];
         hs += reinterpret_cast<const uint64_t*>(partial)[2 * i + 1];
     }
     __shared__ uint64_t shs[TPB / 64];
-    __shared__ uint32_t snt[TPB / 64], sloc[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         hs += __shfl_xor(hs, o);
         nt += __shfl_xor(nt, o);
-        loc += __shfl_xor(loc, o);
     }
-    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; sloc[threadIdx.x >> 6] = loc; }
+    if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; loc += sloc[i]; }
+        for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
         ctrl->nterm = nt;
         ctrl->hsum = hs;
-        const uint32_t mode = (auto_cap && smp.m - loc <= auto_cap) ? 1u : 0u;
-        ctrl->mode = mode;
-        const bool single = mode == 0 && nt == 1 && hs < smp.m;
+        ctrl->mode = 0;
+        const bool single = nt == 1 && hs < smp.m;
         ctrl->single = single ? 1u : 0u;
-        ctrl->multi = (mode == 0 && !single) ? 1u : 0u;
+        ctrl->multi = single ? 0u : 1u;
         if (single) {
             const uint32_t h = (uint32_t)hs;
             uint32_t H = 0;
@@ -1336,11 +1390,15 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
 struct LevelShifts { uint8_t lg[MAXL]; };
 
 __global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, uint32_t ntiles, Ctrl* ctrl,
-                                                  uint32_t levels, LevelShifts ks, Gate gate) {
+                                                  uint32_t levels, LevelShifts ks, uint32_t cap, Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
     const uint32_t total = wg_exscan_inplace(cnt, ntiles, sh);
     if (threadIdx.x == 0) {
+        if (total > cap) {  // the guess was wrong: more than the contracted levels hold
+            ctrl->mode = 0;  // every later kernel of this path returns; the plain path runs
+            return;
+        }
         cnt[ntiles] = total;
         uint32_t m = total;
         ctrl->dm[0] = m;
@@ -1662,19 +1720,34 @@ static hipError_t run_validate(const RunArgs& a, const Plan& p, uint32_t n) {
 
 // One streaming pass over the input: terminal count, head sum (the one-list
 // shortcut) and local links; with auto_cap > 0 it also picks the path.
-static hipError_t run_headsum(const RunArgs& a, const Plan& p, uint32_t auto_cap) {
+static hipError_t run_headsum(const RunArgs& a, const Plan& p, Gate g) {
     const uint32_t n = (uint32_t)p.m[0];
     hipStream_t st = a.stream;
     const bool vec = ((uintptr_t)a.succ % 16) == 0;
     const uint32_t gs = std::min<uint32_t>(grid_for(n, TPB * 16), HEADSUM_BLOCKS);
     uint32_t* part = reinterpret_cast<uint32_t*>(a.ws + p.off_hsum);
-    if (vec) hipLaunchKernelGGL(k_headsum<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
-    else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
+    if (vec) hipLaunchKernelGGL(k_headsum<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part, g);
+    else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part, g);
     LR_TRY(hipGetLastError());
     const Sampler smp0{n, p.log2k[0], p.lseed[0]};
     hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs,
                        reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl), smp0, a.ws + p.off_eb[0], (uint32_t)p.m[1],
-                       (uint32_t)p.rec_bytes, auto_cap);
+                       (uint32_t)p.rec_bytes, g);
+    return hipGetLastError();
+}
+
+// Automatic contraction, the device-side guess (sets Ctrl.mode).
+static hipError_t run_guess(const RunArgs& a, const Plan& p, uint32_t thr) {
+    const uint32_t n = (uint32_t)p.m[0];
+    hipStream_t st = a.stream;
+    const uint32_t ntiles = (n + LOCAL_TILE - 1) / LOCAL_TILE;
+    const uint32_t nsamp = (ntiles + LOCAL_SAMPLE_STRIDE - 1) / LOCAL_SAMPLE_STRIDE;
+    const uint32_t gs = std::max(1u, std::min<uint32_t>(nsamp, HEADSUM_BLOCKS));
+    uint32_t* part = reinterpret_cast<uint32_t*>(a.ws + p.off_hsum);
+    hipLaunchKernelGGL(k_lsample<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part);
+    LR_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_ldecide, dim3(1), dim3(TPB), 0, st, part, gs, n, thr,
+                       reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl));
     return hipGetLastError();
 }
 
@@ -1703,7 +1776,7 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     // Otherwise: predecessor marks (the one-list case skips these kernels).
     uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
     {
-        if (a.prologue) LR_TRY(run_headsum(a, p, 0));
+        if (a.prologue) LR_TRY(run_headsum(a, p, Gate{}));
         if (p.log0) {
             LR_TRY(run_marks(a, p, hp0, ctrl));
         } else {
@@ -1834,7 +1907,7 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
     LR_TRY(hipGetLastError());
     LevelShifts ks{};
     for (uint32_t l = 0; l < Lv; ++l) ks.lg[l] = (uint8_t)p.log2k[l];
-    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks, g);
+    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks, (uint32_t)p.m[0], g);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_DETECT);
     if (hp0) {
@@ -1911,9 +1984,11 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
     return hipSuccess;
 }
 
-// Forced paths run alone. Automatic contraction: the head-sum pass decides on
-// the device; both paths are enqueued and the one not chosen returns from
-// every kernel at once (no host synchronisation, so the call stays capturable).
+// Forced paths run alone. Automatic contraction: a sample of the tiles
+// decides on the device, the contracted path's scan may still hand over to the
+// plain path, and the plain path's head-sum pass runs only if that path is
+// taken. Both paths are enqueued and the one not chosen returns from every
+// kernel at once (no host synchronisation, so the call stays capturable).
 template <bool W, int WT, class Out0>
 static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
     if (!a.lplan) return a.plan->local ? run_local_t<W, WT>(a, out0) : run_srs_t<W, WT>(a, out0);
@@ -1921,15 +1996,16 @@ static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);
     rec_ev(a, EV_START);
     if (a.validate) LR_TRY(run_validate(a, p, (uint32_t)p.m[0]));
-    LR_TRY(run_headsum(a, p, (uint32_t)a.lplan->m[0]));
+    LR_TRY(run_guess(a, p, (uint32_t)local_guess_cap(p.m[0])));
     RunArgs la = a;
     la.plan = a.lplan;
     la.prologue = false;
     la.gate = Gate{&ctrl->mode, 1u};
-    LR_TRY((run_local_t<W, WT>(la, out0)));
+    LR_TRY((run_local_t<W, WT>(la, out0)));  // its scan falls back to mode 0 if the list is too long
     RunArgs pa = a;
     pa.prologue = false;
     pa.gate = Gate{&ctrl->mode, 0u};
+    LR_TRY(run_headsum(pa, p, pa.gate));
     return run_srs_t<W, WT>(pa, out0);
 }
 

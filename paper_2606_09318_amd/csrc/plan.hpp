@@ -22,13 +22,22 @@ constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the v
 constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
 constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
 constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
-// automatic contraction: considered from this size on, taken when the
-// contracted list has at most LR_LOCAL_AUTO_16THS / 16 of the elements
+// automatic contraction: considered from this size on; the contracted levels
+// hold at most LR_LOCAL_AUTO_16THS / 16 of the elements
 constexpr uint64_t LOCAL_AUTO_MIN_N = 1ull << 21;
 #ifndef LR_LOCAL_AUTO_16THS
 #define LR_LOCAL_AUTO_16THS 5
 #endif
 constexpr uint64_t local_auto_cap(uint64_t n) { return (n * LR_LOCAL_AUTO_16THS + 15) / 16; }
+// the choice is a guess from every LOCAL_SAMPLE_STRIDE-th tile, taken when the
+// extrapolated contracted list is at most LR_LOCAL_GUESS_16THS / 16 of the
+// elements (below the capacity, so a wrong guess is rare; the contracted
+// path checks the exact size and falls back to the plain path)
+constexpr uint32_t LOCAL_SAMPLE_STRIDE = 16;
+#ifndef LR_LOCAL_GUESS_16THS
+#define LR_LOCAL_GUESS_16THS 4
+#endif
+constexpr uint64_t local_guess_cap(uint64_t n) { return n * LR_LOCAL_GUESS_16THS / 16; }
 // grouping tiles: lanes x LR_PLACE_PER records (half as many weighted); the
 // passes that also carry roots use wider workgroups (measured faster there,
 // slower without roots)

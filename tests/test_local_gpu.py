@@ -291,6 +291,30 @@ def test_automatic_choice_batch():
             assert np.array_equal(host_u32(t), et)
 
 
+def test_automatic_choice_wrong_guess():
+    """The choice is guessed from every 16th tile of 4096 ids. Here exactly
+    those tiles are local and the rest is random, so the guess picks
+    contraction, the contracted list is far larger than its levels hold, and
+    the contracted path must hand over to the plain path on the device."""
+    L = workloads.striped_list(AUTO_N, 4096, 16, seed=21)
+    print(f"case: striped n={AUTO_N}", flush=True)
+    exp = np.empty(AUTO_N, np.uint32)
+    exp[L.order] = np.arange(AUTO_N - 1, -1, -1, dtype=np.uint32)
+    for flags in (0, lr.LR_VALIDATE):
+        st, r, t = gpu_rank(L.succ, lr.make_opts(flags=flags))
+        assert st == lr.LR_OK
+        assert np.array_equal(r, exp), f"flags={flags}"
+        assert np.all(t == L.order[-1])
+    w = workloads.weights(AUTO_N, 21, 3, -1000, 1000, np.int64)
+    st, s, r, t = gpu_prefix(L.succ, w, lr.make_opts())
+    assert st == lr.LR_OK
+    _, er, et, es = oracle.rank(L.succ, w)
+    assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+    bad = L.succ.copy()
+    bad[L.order[5]] = L.order[5]            # a second terminal: two lists
+    check_rank(bad, lr.make_opts())
+
+
 @pytest.mark.parametrize("cycle_len", [1, 2, 3, 4, 7, 16, 100, 4096])
 def test_validate_cycles_inside_a_tile(cycle_len):
     """A cycle of any length inside one tile beside a valid list: the jumps of

@@ -73,3 +73,16 @@ def test_gamma_order(gamma):
     assert np.array_equal(L.succ[L.order[:-1]], L.order[1:])
     with pytest.raises(ValueError):
         workloads.gamma_order(10, 1.5, seed=1)
+
+
+@pytest.mark.parametrize("n", [1, 4096, 4097, 300001])
+def test_striped_list(n):
+    """Kept tiles are single stretches in id order; the list covers every id."""
+    L = workloads.striped_list(n, 4096, 16, seed=5)
+    assert np.array_equal(np.sort(L.order), np.arange(n, dtype=np.uint32))
+    assert np.array_equal(L.succ[L.order[:-1]], L.order[1:])
+    pos = np.empty(n, np.int64)
+    pos[L.order] = np.arange(n)
+    for t in range(0, (n + 4095) // 4096, 16):
+        ids = np.arange(t * 4096, min(n, (t + 1) * 4096))
+        assert np.all(np.diff(pos[ids]) == 1)

@@ -134,6 +134,33 @@ def gamma_list(n: int, gamma: float, seed: int = 6, stream: int = 0) -> ListInpu
     return ListInput(link_order(order), order)
 
 
+def striped_list(n: int, tile: int, stride: int, seed: int = 7, stream: int = 2) -> ListInput:
+    """One list whose tiles t = 0, stride, 2*stride, ... (of `tile` ids each)
+    are walked in id order as one stretch, while every other element sits at
+    a random place between the stretches: local where a strided sample looks,
+    random almost everywhere else."""
+    ntiles = (n + tile - 1) // tile
+    kept = np.arange(0, ntiles, stride, dtype=np.int64)
+    is_kept = np.zeros(ntiles, bool)
+    is_kept[kept] = True
+    tile_of = np.arange(n, dtype=np.int64) // tile
+    loose = np.flatnonzero(~is_kept[tile_of]).astype(np.int64)
+    # units: one per kept tile (ids 0..len(kept)-1), one per loose element
+    nu = kept.size + loose.size
+    units = perm(nu, seed, stream).astype(np.int64)
+    is_tile = units < kept.size
+    tile_first = kept[units[is_tile]] * tile
+    lens = np.ones(nu, np.int64)
+    lens[is_tile] = np.minimum(tile, n - tile_first)
+    first = np.empty(nu, np.int64)
+    first[is_tile] = tile_first
+    first[~is_tile] = loose[units[~is_tile] - kept.size]
+    starts = np.concatenate(([0], np.cumsum(lens)))
+    order = np.repeat(first, lens) + (np.arange(n, dtype=np.int64) - np.repeat(starts[:-1], lens))
+    order = order.astype(np.uint32)
+    return ListInput(link_order(order), order)
+
+
 def identity_list(n: int) -> ListInput:
     """succ[i] = i + 1: the paper's List(n, 0.0) on one PE."""
     order = np.arange(n, dtype=np.uint32)
