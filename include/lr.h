@@ -69,8 +69,21 @@ enum {
     LR_VALIDATE = 1u,  /* check input and result; synchronises the stream */
     LR_PROFILE = 2u,   /* record per-phase times, read with lr_profile_last */
     LR_LOCAL = 4u,     /* always contract tile-local chains first (Section 2.3) */
-    LR_NO_LOCAL = 8u   /* never contract tile-local chains */
+    LR_NO_LOCAL = 8u,  /* never contract tile-local chains */
+    LR_SPAWN = 16u     /* first level with ruler spawning (Section 2.2); not with LR_LOCAL */
 };
+/* Ruler spawning (Section 2.2): the first level's chase keeps its lanes busy.
+ * A lane whose walk reached a ruler, once its wavefront has handed out all the
+ * sampled rulers' and heads' walks, claims an element that no walk has
+ * reached yet as a new ruler and walks from there, so long stretches between
+ * sampled rulers are cut by walks started inside them. Elements are claimed
+ * with an atomic compare-and-swap on their slot (a walk stops where it finds
+ * a spawned ruler). The walks are numbered on the device and their list is
+ * ranked by the ruling-set levels, with sizes read on the device; spacing[0]
+ * is then the first level's sampling spacing and spacing[1..] the spacings of
+ * the levels above (0 = defaults). Results are identical to the default path.
+ * It shortens the longest walk of small, cache-resident inputs; on inputs
+ * far beyond the caches the per-step atomic costs more than it saves. */
 /* Tile-local contraction (Section 2.3): chains of links that stay inside a
  * tile of 4096 consecutive ids are contracted to their first element, the
  * ruling-set levels rank the contracted list, and every element then takes
@@ -91,7 +104,8 @@ enum {
 /* Options; a NULL lr_opts* means all defaults. */
 typedef struct lr_opts {
     uint64_t seed;                     /* seed of the ruler sampling hash */
-    uint32_t flags;                    /* LR_VALIDATE | LR_PROFILE */
+    uint32_t flags;                    /* LR_VALIDATE | LR_PROFILE | LR_LOCAL |
+                                          LR_NO_LOCAL | LR_SPAWN */
     uint32_t base_max;                 /* largest level solved by the one-workgroup
                                           base case; 0 = default (8192 unweighted,
                                           4096 weighted) */

@@ -156,22 +156,56 @@ static size_t layout_local(Plan* p, uint64_t n, size_t off) {
     return off;
 }
 
+// Ruler spawning over an n-element input: slots, predecessor bytes and head
+// tile counts of the input level, and the records of its walks (at most n).
+static size_t layout_spawn(Plan* p, uint64_t n, size_t off) {
+    p->spawn = true;
+    p->sp_n = n;
+    p->sp_ntiles = (uint32_t)((n + TILE - 1) / TILE);
+    p->off_sp_slot = off;
+    off += align_up(std::max<size_t>((size_t)n * p->rec_bytes, 16));
+    p->off_sp_hp = off;
+    off += align_up((size_t)n + 16);
+    p->off_sp_tile = off;
+    off += align_up((size_t)(p->sp_ntiles + 1) * 4);
+    p->off_lrec = off;
+    off += align_up(std::max<size_t>((size_t)n * p->rec_bytes, 16));
+    return off;
+}
+
 lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, PlanSet* ps) {
     *ps = PlanSet{};
     if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
     const bool force = o && (o->flags & LR_LOCAL);
     const bool never = o && (o->flags & LR_NO_LOCAL);
+    const bool spawn = o && (o->flags & LR_SPAWN);
     if (force && never) return LR_ERR_INVALID_ARG;
+    if (force && spawn) return LR_ERR_INVALID_ARG;
     Plan* p = &ps->p;
-    lr_status s = plan_levels(n, weighted, o, true, p);
+    lr_opts upper = o ? *o : lr_opts{};  // spawning: spacing[0] samples the input, the rest the levels above
+    if (spawn) {
+        for (int l = 0; l + 1 < LR_MAX_LEVELS; ++l) upper.spacing[l] = o->spacing[l + 1];
+        upper.spacing[LR_MAX_LEVELS - 1] = 0;
+        if (o->spacing[0] && !pow2_in(o->spacing[0], 2, 4096)) return LR_ERR_INVALID_ARG;
+    }
+    lr_status s = plan_levels(n, weighted, spawn ? &upper : o, true, p);
     if (s != LR_OK) return s;
+    // the input level of the spawning chase keeps its head count in the last
+    // Ctrl level entry
+    if (spawn && p->levels >= (uint32_t)MAXL - 1) return LR_ERR_UNSUPPORTED;
     size_t off = 0;
     p->off_ctrl = off;
     off += align_up(sizeof(Ctrl));
     p->off_hsum = off;
     off += align_up((size_t)HEADSUM_BLOCKS * 16);
     const size_t body = off;
-    if (force) {
+    if (spawn) {
+        const uint32_t k0 = o->spacing[0] ? o->spacing[0] : SPAWN_K0;
+        p->sp_log2k = ilog2(k0);
+        p->sp_seed = (uint32_t)mix64(o->seed * 0x2545f4914f6cdd1dULL + 0x2000);
+        p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
+        off = layout_levels(p, layout_spawn(p, n, body));
+    } else if (force) {
         p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
         off = layout_levels(p, layout_local(p, n, body));
     } else {
@@ -180,7 +214,7 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
     }
     // Automatic contraction: the contracted path's arrays share the workspace
     // with the plain path's (only one of them runs), after the common header.
-    ps->autol = !force && !never && p->levels >= 1 && n >= LOCAL_AUTO_MIN_N;
+    ps->autol = !force && !never && !spawn && p->levels >= 1 && n >= LOCAL_AUTO_MIN_N;
     if (ps->autol) {
         Plan* q = &ps->lp;
         lr_opts lo = o ? *o : lr_opts{};

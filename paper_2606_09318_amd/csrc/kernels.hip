@@ -1509,6 +1509,276 @@ __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ 
     if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, 4u);
 }
 
+// ------------------------------------------------------- ruler spawning --
+// Section 2.2, on one GPU. The chase's lanes play the paper's active waves:
+// a wavefront first hands out the walks of its range of sampled rulers and
+// heads, and from then on a lane whose walk ended claims an element of the
+// wavefront's id range that no walk has reached as a new ruler and walks on
+// from it. Every element's slot starts all ones (unreached); a walk claims
+// its next element with a 64-bit compare-and-swap that writes (walk, offset),
+// and a spawned ruler's slot holds SPAWN | its walk id, so a walk whose swap
+// finds a spawned ruler ends there. In a forest every element has one
+// predecessor, so the only competitor for an element is the spawner: the
+// swap decides, and the walk ids are handed out by one counter per spawning
+// round of a wavefront.
+//
+// Walk ids: [0, S0) sampled rulers (block b's ruler is walk b), [S0, T0)
+// heads that are not sampled (their start parked in the record), then spawned
+// rulers. A spawner that loses the swap leaves its id unused; the record is
+// written as an isolated terminal so the walks' list stays a forest.
+constexpr uint32_t SPAWN = TERM;      // slot flag: the element is a spawned ruler
+constexpr int SP_TPB = 256;
+constexpr int SPL = MAXL - 1;         // Ctrl level entry holding the input level's head walks
+
+// Position of the k-th (from 0) set bit of m; m has more than k set bits.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k) {
+    uint32_t pos = 0;
+    uint32_t c = __popc((uint32_t)m);
+    if (k >= c) { k -= c; pos = 32; m >>= 32; }
+    uint32_t v = (uint32_t)m;
+    c = __popc(v & 0xffffu); if (k >= c) { k -= c; pos += 16; v >>= 16; }
+    c = __popc(v & 0xffu);   if (k >= c) { k -= c; pos += 8;  v >>= 8; }
+    c = __popc(v & 0xfu);    if (k >= c) { k -= c; pos += 4;  v >>= 4; }
+    c = __popc(v & 0x3u);    if (k >= c) { k -= c; pos += 2;  v >>= 2; }
+    if (k >= (v & 1u)) pos += 1;
+    return pos;
+}
+
+__device__ __forceinline__ unsigned long long* slot_word(void* slot, uint32_t x, uint32_t bytes) {
+    return reinterpret_cast<unsigned long long*>(static_cast<char*>(slot) + (size_t)x * bytes);
+}
+
+__global__ void k_sp_init(Ctrl* ctrl, Gate gate) {
+    if (gate.off()) return;
+    if (threadIdx.x == 0) {
+        ctrl->spn = 0;
+        ctrl->single = 0;
+        ctrl->multi = 0;
+    }
+}
+
+template <bool W, int WT>
+__global__ __launch_bounds__(SP_TPB) void k_sp_chase(SrcIn<W, WT> src, Sampler smp, Ctrl* ctrl,
+                                                     typename Lay<W>::Slot* __restrict__ slot,
+                                                     const uint8_t* __restrict__ hp_in,
+                                                     typename Lay<W>::Rec* __restrict__ lrec,
+                                                     uint8_t* __restrict__ hp_c, uint32_t cap, Gate gate) {
+    if (gate.off()) return;
+    using L = Lay<W>;
+    using Val = typename L::Val;
+    constexpr uint32_t SB = sizeof(typename L::Slot);
+    constexpr unsigned long long FREE = ~0ull;
+    const uint32_t lane = lane_id();
+    const uint32_t m = smp.m;
+    const uint32_t S0 = (m + (1u << smp.log2k) - 1u) >> smp.log2k;
+    const uint32_t T0 = S0 + ctrl->lv[SPL].H;
+    const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t per = T0 / nwave + 1;
+    uint32_t wcur = (uint32_t)min<uint64_t>((uint64_t)gwave * per, T0);
+    const uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, T0);
+    const uint32_t span = m / nwave + 1;
+    uint32_t scur = (uint32_t)min<uint64_t>((uint64_t)gwave * span, m);
+    const uint32_t shi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * span, m);
+    bool can_spawn = true;  // cleared if the walk ids run out (not a forest)
+    uint32_t w = NONE, x = 0, nxt = 0;
+    Val v = L::zero(), off = L::zero();
+    bool fresh = false;     // walk just started: the record of x is not loaded yet
+    for (;;) {
+        uint64_t idle = __ballot(w == NONE);
+        // the walks of the wavefront's sampled rulers and heads
+        if (idle && wcur < whi) {
+            const uint32_t my = wcur + mbcnt(idle);
+            wcur = min(wcur + (uint32_t)__popcll(idle), whi);
+            if (w == NONE && my < whi) {
+                const uint32_t s0 = (my < S0) ? smp.start(my) : lrec[my].nxt;
+                if (s0 < m) {
+                    w = my;
+                    x = s0;
+                    off = L::zero();
+                    fresh = true;
+                    slot[s0] = L::slot(my, L::zero());
+                } else {  // corrupt parked start (cannot happen for valid input)
+                    lrec[my] = L::rec(TERM | IDX, L::zero());
+                    atomicOr(&ctrl->err, 8u);
+                }
+            }
+            idle = __ballot(w == NONE);
+        }
+        // spawning: idle lanes take unreached elements of the wavefront's id range
+        if (idle && wcur >= whi && scur < shi && can_spawn) {
+            const uint32_t z = scur + lane;
+            bool cand = false;
+            if (z < shi && hp_in[z] && !smp.sampled(z))
+                cand = *reinterpret_cast<const uint32_t*>(slot_word(slot, z, SB)) == NONE;
+            const uint64_t avail = __ballot(cand);
+            const uint32_t ni = (uint32_t)__popcll(idle), na = (uint32_t)__popcll(avail);
+            uint64_t take = avail;
+            if (na > ni) {  // the first ni candidates; the scan resumes after the last one taken
+                const uint32_t last = select_bit(avail, ni - 1u);
+                take = avail & ((2ull << last) - 1ull);
+                scur += last + 1u;
+            } else {
+                scur += 64u;
+            }
+            if (scur > shi) scur = shi;
+            const uint32_t nt = (uint32_t)__popcll(take);
+            if (nt) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&ctrl->spn, nt);
+                base = __shfl(base, 0);
+                if ((uint64_t)T0 + base + nt > cap) {  // more walks than elements: not a forest
+                    can_spawn = false;
+                    if (lane == 0) atomicOr(&ctrl->err, 16u);
+                } else {
+                    const bool mine = (take >> lane) & 1ull;
+                    const uint32_t cid = T0 + base + mbcnt(take);
+                    uint32_t got = 0;
+                    if (mine) {
+                        const unsigned long long want = (unsigned long long)(SPAWN | cid);  // offset 0
+                        got = atomicCAS(slot_word(slot, z, SB), FREE, want) == FREE;
+                        if (got) {
+                            if constexpr (W) slot[z].s = 0;
+                        } else {
+                            lrec[cid] = L::rec(TERM | z, L::zero());  // lost to a walk: an unused id
+                        }
+                    }
+                    // hand the new rulers to the idle lanes in order
+                    const uint32_t k = mbcnt(idle);
+                    const bool recv = (w == NONE) && k < nt;
+                    const uint32_t from = recv ? select_bit(take, k) : lane;
+                    const uint32_t rz = __shfl(z, (int)from);
+                    const uint32_t rc = __shfl(cid, (int)from);
+                    const uint32_t rg = __shfl(got, (int)from);
+                    if (recv && rg) {
+                        w = rc;
+                        x = rz;
+                        off = L::zero();
+                        fresh = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(w != NONE) == 0 && wcur >= whi && (scur >= shi || !can_spawn)) break;
+        // one step: a lane tests the successor it loaded; if that is neither a
+        // terminal nor a ruler it claims it and loads its record in the same
+        // round trip (a fresh walk only loads its start's record)
+        bool adv = false;
+        Val o2 = off;
+        if (w != NONE && !fresh) {
+            o2 = L::add(off, v);
+            if (nxt & TERM) {                       // x is a terminal: the walk ends on it
+                lrec[w] = L::rec(nxt, o2);
+                w = NONE;
+            } else if (smp.sampled(nxt)) {          // reached a sampled ruler
+                const uint32_t c = nxt >> smp.log2k;
+                lrec[w] = L::rec(c, o2);
+                hp_c[c] = 1;
+                if (c == w) atomicOr(&ctrl->err, 8u);  // back at its own start: a cycle
+                w = NONE;
+            } else {
+                adv = true;
+            }
+        }
+        const uint32_t q = fresh ? x : nxt;
+        unsigned long long old = FREE;
+        uint32_t ln = 0;
+        Val lv = L::zero();
+        if (adv) old = atomicCAS(slot_word(slot, q, SB), FREE, ((unsigned long long)o2.c << 32) | w);
+        if (fresh || adv) src.load(q, ln, lv);
+        if (fresh) {
+            nxt = ln;
+            v = lv;
+            fresh = false;
+        } else if (adv) {
+            if (old == FREE) {
+                if constexpr (W) slot[q].s = o2.s;
+                x = q;
+                off = o2;
+                nxt = ln;
+                v = lv;
+            } else {
+                const uint32_t ow = (uint32_t)old;
+                if (ow & SPAWN) {                   // reached a spawned ruler
+                    const uint32_t c = ow & IDX;
+                    lrec[w] = L::rec(c, o2);
+                    hp_c[c] = 1;
+                    if (c == w) atomicOr(&ctrl->err, 8u);
+                } else {                            // reached by two walks: two predecessors
+                    lrec[w] = L::rec(TERM | IDX, o2);
+                    atomicOr(&ctrl->err, 2u);
+                }
+                w = NONE;
+            }
+        }
+    }
+}
+
+// The walks' list: its size and the sizes of the levels above.
+__global__ void k_sp_publish(Ctrl* ctrl, uint32_t S0, uint32_t cap, uint32_t levels, LevelShifts ks, Gate gate) {
+    if (gate.off()) return;
+    if (threadIdx.x == 0) {
+        uint64_t t = (uint64_t)S0 + ctrl->lv[SPL].H + ctrl->spn;
+        uint32_t m = (uint32_t)min<uint64_t>(t, cap);
+        ctrl->dm[0] = m;
+        for (uint32_t l = 0; l < levels; ++l) {
+            m = (m + (1u << ks.lg[l]) - 1u) >> ks.lg[l];
+            ctrl->dm[l + 1] = m;
+        }
+        ctrl->single = 0;
+    }
+}
+
+// rank(x) = result(walk(x)) - offset(x), as k_expand, with the walk id taken
+// from the slot without its spawned-ruler flag.
+template <bool W, class Out>
+__global__ __launch_bounds__(TPB) void k_sp_expand(const typename Lay<W>::Slot* __restrict__ slot, uint32_t n,
+                                                   const typename Lay<W>::Res* __restrict__ res, Ctrl* ctrl,
+                                                   Out out, Gate gate) {
+    if (gate.off()) return;
+    using L = Lay<W>;
+    const uint32_t mc = ctrl->dm[0];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t ntile = (n + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
+    bool bad = false;
+    for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
+        const uint32_t base = tile * 64 * EXPAND_CH;
+        if (base + lane >= n) continue;
+        auto cur = out.begin(base + lane);
+        typename L::Slot sv[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            if (i < n) sv[j] = slot[i];
+        }
+        typename L::Res rv[EXPAND_CH];
+        uint32_t wv[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            wv[j] = (i < n) ? (sv[j].w & IDX) : NONE;
+            if (wv[j] < mc) rv[j] = res[wv[j]];
+        }
+        typename L::Val ov[EXPAND_CH];
+        uint32_t orr[EXPAND_CH];
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const bool ok = wv[j] < mc;
+            bad |= !ok && (base + j * 64 + lane < n);
+            ov[j] = ok ? L::sub(L::val(rv[j]), L::val(sv[j])) : L::junk();
+            orr[j] = ok ? rv[j].root : NONE;
+        }
+#pragma unroll
+        for (int j = 0; j < EXPAND_CH; ++j) {
+            const uint32_t i = base + j * 64 + lane;
+            if (i < n) out.store(cur, i, ov[j], orr[j]);
+        }
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, 4u);
+}
+
 // ============================================================== host side ==
 
 static int g_cus = 0;
@@ -1875,6 +2145,74 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     return hipSuccess;
 }
 
+// The ruling-set levels over a contracted list (records at lrec, sizes in
+// Ctrl.dm): on return lrec holds every contracted element's result.
+template <bool W>
+static hipError_t run_clevels(const RunArgs& a, const Plan& p, typename Lay<W>::Rec* lrec, Ctrl* ctrl, Gate g,
+                              bool ev_chase0) {
+    using L = Lay<W>;
+    char* ws = a.ws;
+    hipStream_t st = a.stream;
+    const uint32_t Lv = p.levels;
+    for (uint32_t l = 0; l < Lv; ++l) {
+        const uint32_t* dm = &ctrl->dm[l];
+        const Sampler smp{(uint32_t)p.m[l], p.log2k[l], p.lseed[l]};
+        const uint32_t S = (uint32_t)p.m[l + 1];
+        const uint8_t* hp = reinterpret_cast<const uint8_t*>(ws + p.off_slot[l]);
+        uint32_t* tile = reinterpret_cast<uint32_t*>(ws + p.off_tile[l]);
+        const bool more = l + 1 < Lv;
+        uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
+        const uint32_t zw = more ? (S + 3) / 4 : 0;
+        const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
+        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, nullptr, dm,
+                           g);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
+                           S, (uint32_t)p.rec_bytes, nullptr, dm, g);
+        LR_TRY(hipGetLastError());
+        if (a.validate && !(l == 0 && p.log0))
+            LR_TRY(fill(ws + p.off_slot[l], (uint64_t)p.m[l] * p.rec_bytes, 0xffffffffu, st, nullptr, g));
+        const auto* rec = (l == 0) ? lrec : reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]);
+        SrcLvl<W> src{rec, (uint32_t)p.m[l]};
+        if (l == 0 && p.log0) {  // a long contracted list: visit log and grouped placement, as the plain path
+            LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
+            LR_TRY((launch_chase<W, true, 1>(p, 0, src, smp, ctrl, ws, st, dm, g)));
+        } else {
+            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
+        }
+        if (l == 0 && ev_chase0) rec_ev(a, EV_CHASE0);
+    }
+    {
+        auto* top = Lv ? reinterpret_cast<typename L::Rec*>(ws + p.off_eb[Lv - 1]) : lrec;
+        SrcLvl<W> src{top, (uint32_t)p.m[Lv]};
+        OutLvl<W> out{reinterpret_cast<typename L::Res*>(top)};
+        LR_TRY((launch_base<W>(src, out, (uint32_t)p.m[Lv], ctrl, st, &ctrl->dm[Lv], g)));
+    }
+    for (int l = (int)Lv - 1; l >= 0; --l) {
+        const uint32_t m = (uint32_t)p.m[l];
+        const uint32_t S = (uint32_t)p.m[l + 1];
+        const uint32_t* dm = &ctrl->dm[l];
+        hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
+                           ctrl, l, dm, g);
+        LR_TRY(hipGetLastError());
+        const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
+        const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
+        auto* below = (l == 0) ? reinterpret_cast<typename L::Res*>(lrec)
+                               : reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1]);
+        OutLvl<W> out{below};
+        if (l == 0 && p.log0) {
+            LR_TRY((run_place<W, OutLvl<W>>(a, p, res, S, ctrl, out, true, dm)));
+        } else {
+            hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(grid_for(m, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot,
+                               m, res, S, ctrl, l, out, dm, g);
+        }
+        LR_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
 // Tile-local contraction, then the ruling-set levels on the contracted list
 // (sizes from the device), then every element from its chain start. The plan
 // sizes the levels for a contracted list of at most m[0] elements; lc_n is
@@ -1919,66 +2257,83 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
                        cnt, dir, p.lc_ntiles, n, lrec, hp0, g);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_HEADS);
-    for (uint32_t l = 0; l < Lv; ++l) {
-        const uint32_t* dm = &ctrl->dm[l];
-        const Sampler smp{(uint32_t)p.m[l], p.log2k[l], p.lseed[l]};
-        const uint32_t S = (uint32_t)p.m[l + 1];
-        const uint8_t* hp = reinterpret_cast<const uint8_t*>(ws + p.off_slot[l]);
-        uint32_t* tile = reinterpret_cast<uint32_t*>(ws + p.off_tile[l]);
-        const bool more = l + 1 < Lv;
-        uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
-        const uint32_t zw = more ? (S + 3) / 4 : 0;
-        const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
-        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, nullptr, dm,
-                           g);
-        LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
-        LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
-                           S, (uint32_t)p.rec_bytes, nullptr, dm, g);
-        LR_TRY(hipGetLastError());
-        if (a.validate && !(l == 0 && p.log0))
-            LR_TRY(fill(ws + p.off_slot[l], (uint64_t)p.m[l] * p.rec_bytes, 0xffffffffu, st, nullptr, g));
-        const auto* rec = (l == 0) ? lrec : reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]);
-        SrcLvl<W> src{rec, (uint32_t)p.m[l]};
-        if (l == 0 && p.log0) {  // a long contracted list: visit log and grouped placement, as the plain path
-            LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
-            LR_TRY((launch_chase<W, true, 1>(p, 0, src, smp, ctrl, ws, st, dm, g)));
-        } else {
-            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
-        }
-        if (l == 0) rec_ev(a, EV_CHASE0);
-    }
-    {
-        auto* top = Lv ? reinterpret_cast<typename L::Rec*>(ws + p.off_eb[Lv - 1]) : lrec;
-        SrcLvl<W> src{top, (uint32_t)p.m[Lv]};
-        OutLvl<W> out{reinterpret_cast<typename L::Res*>(top)};
-        LR_TRY((launch_base<W>(src, out, (uint32_t)p.m[Lv], ctrl, st, &ctrl->dm[Lv], g)));
-    }
-    for (int l = (int)Lv - 1; l >= 0; --l) {
-        const uint32_t m = (uint32_t)p.m[l];
-        const uint32_t S = (uint32_t)p.m[l + 1];
-        const uint32_t* dm = &ctrl->dm[l];
-        hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
-                           ctrl, l, dm, g);
-        LR_TRY(hipGetLastError());
-        const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
-        const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
-        auto* below = (l == 0) ? reinterpret_cast<typename L::Res*>(lrec)
-                               : reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1]);
-        OutLvl<W> out{below};
-        if (l == 0 && p.log0) {
-            LR_TRY((run_place<W, OutLvl<W>>(a, p, res, S, ctrl, out, true, dm)));
-        } else {
-            hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(grid_for(m, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot,
-                               m, res, S, ctrl, l, out, dm, g);
-        }
-        LR_TRY(hipGetLastError());
-    }
+    LR_TRY(run_clevels<W>(a, p, lrec, ctrl, g, true));
     rec_ev(a, EV_UPPER);
     rec_ev(a, EV_PART);
     hipLaunchKernelGGL((k_lc_expand<W, Out0>), dim3(grid_for(n, TPB * EXPAND_CH)), dim3(TPB), 0, st, pos, wd, cnt,
                        reinterpret_cast<const typename L::Res*>(lrec), n, ctrl, out0, g);
+    LR_TRY(hipGetLastError());
+    rec_ev(a, EV_EXPAND);
+    return hipSuccess;
+}
+
+// Ruler spawning: predecessor bytes and heads of the input, the spawning
+// chase (its walks form the contracted list, sized on the device), the
+// ruling-set levels on that list, then every element from its walk.
+template <bool W, int WT, class Out0>
+static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
+    using L = Lay<W>;
+    const Plan& p = *a.plan;
+    char* ws = a.ws;
+    hipStream_t st = a.stream;
+    const Gate g = a.gate;
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
+    const uint32_t n = (uint32_t)p.sp_n;
+    const uint32_t Lv = p.levels;
+    if (a.prologue) {
+        rec_ev(a, EV_START);
+        if (a.validate) LR_TRY(run_validate(a, p, n));
+    }
+    auto* slot = reinterpret_cast<typename L::Slot*>(ws + p.off_sp_slot);
+    uint8_t* hp_in = reinterpret_cast<uint8_t*>(ws + p.off_sp_hp);
+    uint32_t* tile = reinterpret_cast<uint32_t*>(ws + p.off_sp_tile);
+    auto* lrec = reinterpret_cast<typename L::Rec*>(ws + p.off_lrec);
+    uint8_t* hp_c = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);  // the walks' predecessor bytes
+    const Sampler smp{n, p.sp_log2k, p.sp_seed};
+    const uint32_t S0 = (n + (1u << p.sp_log2k) - 1u) >> p.sp_log2k;
+    hipLaunchKernelGGL(k_sp_init, dim3(1), dim3(64), 0, st, ctrl, g);
+    LR_TRY(hipGetLastError());
+    LR_TRY(fill(hp_in, n, 0u, st, nullptr, g));
+    LR_TRY(fill(slot, (uint64_t)n * p.rec_bytes, 0xffffffffu, st, nullptr, g));
+    {
+        const bool vec = ((uintptr_t)a.succ % 16) == 0;
+        const uint32_t gd = grid_for(n, TPB * 4 * 4);
+        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp_in, ctrl, g);
+        else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp_in, ctrl, g);
+        LR_TRY(hipGetLastError());
+    }
+    rec_ev(a, EV_DETECT);
+    const uint32_t gt = std::min<uint32_t>(p.sp_ntiles, (uint32_t)device_cus() * 8);
+    hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp_in, smp, tile, p.sp_ntiles,
+                       reinterpret_cast<uint32_t*>(hp_c), (n + 3) / 4, nullptr, nullptr, g);
+    LR_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.sp_ntiles, ctrl, SPL, g);
+    LR_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp_in, smp, tile, p.sp_ntiles,
+                       reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, nullptr, nullptr, g);
+    LR_TRY(hipGetLastError());
+    rec_ev(a, EV_HEADS);
+    {
+        auto kern = k_sp_chase<W, WT>;
+        static uint32_t resident = 0;  // one per template instance
+        if (!resident) resident = persistent_grid(kern, SP_TPB);
+        const uint64_t lanes = std::max<uint64_t>((uint64_t)n / LR_SPAWN_PER_LANE, 4 * 64);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((lanes + SP_TPB - 1) / SP_TPB, resident);
+        SrcIn<W, WT> src{a.succ, a.weight, n};
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(SP_TPB), 0, st, src, smp, ctrl, slot, hp_in, lrec, hp_c,
+                           (uint32_t)p.m[0], g);
+        LR_TRY(hipGetLastError());
+    }
+    LevelShifts ks{};
+    for (uint32_t l = 0; l < Lv; ++l) ks.lg[l] = (uint8_t)p.log2k[l];
+    hipLaunchKernelGGL(k_sp_publish, dim3(1), dim3(64), 0, st, ctrl, S0, (uint32_t)p.m[0], Lv, ks, g);
+    LR_TRY(hipGetLastError());
+    rec_ev(a, EV_CHASE0);
+    LR_TRY(run_clevels<W>(a, p, lrec, ctrl, g, false));
+    rec_ev(a, EV_UPPER);
+    rec_ev(a, EV_PART);
+    hipLaunchKernelGGL((k_sp_expand<W, Out0>), dim3(grid_for(n, TPB * EXPAND_CH)), dim3(TPB), 0, st, slot, n,
+                       reinterpret_cast<const typename L::Res*>(lrec), ctrl, out0, g);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_EXPAND);
     return hipSuccess;
@@ -1991,6 +2346,7 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
 // kernel at once (no host synchronisation, so the call stays capturable).
 template <bool W, int WT, class Out0>
 static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
+    if (a.plan->spawn) return run_spawn_t<W, WT>(a, out0);
     if (!a.lplan) return a.plan->local ? run_local_t<W, WT>(a, out0) : run_srs_t<W, WT>(a, out0);
     const Plan& p = *a.plan;
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);

@@ -38,6 +38,15 @@ constexpr uint32_t LOCAL_SAMPLE_STRIDE = 16;
 #define LR_LOCAL_GUESS_16THS 4
 #endif
 constexpr uint64_t local_guess_cap(uint64_t n) { return n * LR_LOCAL_GUESS_16THS / 16; }
+// ruler spawning: default sampling spacing of the input level, and input
+// elements per chase lane (the lanes are the walks kept active)
+#ifndef LR_SPAWN_K0
+#define LR_SPAWN_K0 64
+#endif
+constexpr uint32_t SPAWN_K0 = LR_SPAWN_K0;
+#ifndef LR_SPAWN_PER_LANE
+#define LR_SPAWN_PER_LANE 64
+#endif
 // grouping tiles: lanes x LR_PLACE_PER records (half as many weighted); the
 // passes that also carry roots use wider workgroups (measured faster there,
 // slower without roots)
@@ -94,6 +103,16 @@ struct Plan {
     size_t off_lc_wd = 0;    // per element: weight from its chain start (weighted only)
     size_t off_lc_stage = 0; // contracted records at their tile's offset, before compaction
     size_t off_lrec = 0;     // contracted records, then their results
+    // ruler spawning (LR_SPAWN): the input level is a chase whose lanes spawn
+    // rulers; its walks form the contracted list (records at off_lrec, at
+    // most n of them: m[0] = n), which the levels above rank
+    bool spawn = false;
+    uint64_t sp_n = 0;       // input elements
+    uint32_t sp_log2k = 0, sp_seed = 0;  // input level sampling
+    uint32_t sp_ntiles = 0;  // head-compaction tiles of the input
+    size_t off_sp_slot = 0;  // per element: walk id (flagged for spawned rulers) and offset
+    size_t off_sp_hp = 0;    // per element: has-a-predecessor byte
+    size_t off_sp_tile = 0;  // head counts per tile, scanned in place
     size_t total = 0;
 };
 
