@@ -70,8 +70,16 @@ enum {
     LR_PROFILE = 2u,   /* record per-phase times, read with lr_profile_last */
     LR_LOCAL = 4u,     /* always contract tile-local chains first (Section 2.3) */
     LR_NO_LOCAL = 8u,  /* never contract tile-local chains */
-    LR_SPAWN = 16u     /* first level with ruler spawning (Section 2.2); not with LR_LOCAL */
+    LR_SPAWN = 16u,    /* first level with ruler spawning (Section 2.2); not with LR_LOCAL */
+    LR_VISIT_LOG = 32u /* first level through the visit log even below 2^25 elements
+                          (inputs of at least 2^16); a tuning and testing option */
 };
+/* Visit log: on inputs of 2^25 elements or more the first level's chase does
+ * not store each element's walk and offset at the element (one random store
+ * per element) but appends them to per-wavefront logs written in whole lines;
+ * two grouping passes then bring every record to its element's range, and
+ * the outputs are written range by range. Below 2^25 the random stores are
+ * cheaper (the arrays are small enough for the caches to absorb them). */
 /* Ruler spawning (Section 2.2): the first level's chase keeps its lanes busy.
  * A lane whose walk reached a ruler, once its wavefront has handed out all the
  * sampled rulers' and heads' walks, claims an element that no walk has
@@ -105,7 +113,7 @@ enum {
 typedef struct lr_opts {
     uint64_t seed;                     /* seed of the ruler sampling hash */
     uint32_t flags;                    /* LR_VALIDATE | LR_PROFILE | LR_LOCAL |
-                                          LR_NO_LOCAL | LR_SPAWN */
+                                          LR_NO_LOCAL | LR_SPAWN | LR_VISIT_LOG */
     uint32_t base_max;                 /* largest level solved by the one-workgroup
                                           base case; 0 = default (8192 unweighted,
                                           4096 weighted) */
@@ -242,7 +250,7 @@ lr_status lr_autotune(const uint32_t* succ, const void* weight, lr_wtype w, uint
  * LR_PROFILE on this thread: [0] predecessor marks, [1] head compaction,
  * [2] level-0 chase, [3] upper levels, base case and their propagation,
  * [4] level-0 record resolution and first grouping pass (0 for inputs
- * below 2^22), [5] level-0 propagation to the outputs, [6] total.
+ * without the visit log), [5] level-0 propagation to the outputs, [6] total.
  * Synchronises on the recorded events. Returns the number of values
  * written. */
 int lr_profile_last(double* ms, int cap);

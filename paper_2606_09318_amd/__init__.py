@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("LR_LIBRARY") or os.path.join(HERE, "liblr.so")
 LR_OK, LR_ERR_INVALID_ARG, LR_ERR_UNSUPPORTED, LR_ERR_WORKSPACE = 0, 1, 2, 3
 LR_ERR_OUT_OF_MEMORY, LR_ERR_BAD_LIST, LR_ERR_HIP = 4, 5, 6
 LR_W_NONE, LR_W_I32, LR_W_I64 = 0, 1, 2
-LR_VALIDATE, LR_PROFILE, LR_LOCAL, LR_NO_LOCAL, LR_SPAWN = 1, 2, 4, 8, 16
+LR_VALIDATE, LR_PROFILE, LR_LOCAL, LR_NO_LOCAL, LR_SPAWN, LR_VISIT_LOG = 1, 2, 4, 8, 16, 32
 LR_MAX_LEVELS = 8
 
 

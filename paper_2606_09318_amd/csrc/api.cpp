@@ -173,6 +173,12 @@ static size_t layout_spawn(Plan* p, uint64_t n, size_t off) {
     return off;
 }
 
+// Level 0 through the visit log: from LOG_MIN_N elements on, or on request.
+static bool use_log(uint64_t m0, uint32_t levels, const lr_opts* o) {
+    if (levels < 1) return false;
+    return m0 >= LOG_MIN_N || (o && (o->flags & LR_VISIT_LOG) && m0 >= LOG_FORCE_MIN_N);
+}
+
 lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, PlanSet* ps) {
     *ps = PlanSet{};
     if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
@@ -203,13 +209,13 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         const uint32_t k0 = o->spacing[0] ? o->spacing[0] : SPAWN_K0;
         p->sp_log2k = ilog2(k0);
         p->sp_seed = (uint32_t)mix64(o->seed * 0x2545f4914f6cdd1dULL + 0x2000);
-        p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
+        p->log0 = false;  // the walks' list is a small fraction of n on the inputs spawning is for
         off = layout_levels(p, layout_spawn(p, n, body));
     } else if (force) {
-        p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
+        p->log0 = use_log(n, p->levels, o);
         off = layout_levels(p, layout_local(p, n, body));
     } else {
-        p->log0 = p->levels >= 1 && n >= LOG_MIN_N;
+        p->log0 = use_log(n, p->levels, o);
         off = layout_levels(p, body);
     }
     // Automatic contraction: the contracted path's arrays share the workspace
@@ -223,7 +229,7 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         if (s != LR_OK) return s;
         q->off_ctrl = p->off_ctrl;
         q->off_hsum = p->off_hsum;
-        q->log0 = q->levels >= 1 && q->m[0] >= LOG_MIN_N;
+        q->log0 = use_log(q->m[0], q->levels, o);
         off = std::max(off, layout_levels(q, layout_local(q, n, body)));
     }
     if (batch_count) {

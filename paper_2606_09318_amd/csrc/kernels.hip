@@ -19,7 +19,7 @@
 // Walks run forward along succ, so ranks toward the terminal come out
 // directly and no list reversal is needed.
 //
-// Level 0 of large inputs (n >= 2^22) logs the chase's visits and places the
+// Level 0 of large inputs (n >= 2^25) logs the chase's visits and places the
 // results by element range (place1/2/3) instead of storing at random
 // addresses; with more than one list its predecessor marks are grouped by
 // range the same way (mark1, place2 on ids, mark3), and weighted inputs are
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(TPB) void k_ldecide(const uint32_t* __restrict__ pa
 // initial-element walk; multi says whether predecessor marks are needed.
 __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restrict__ partial, uint32_t nparts,
                                                        Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
-                                                       uint32_t rec_bytes, Gate gate) {
+                                                       uint32_t rec_bytes, int lvl, Gate gate) {
     if (gate.off()) return;
     uint64_t hs = 0;
     uint32_t nt = 0;
@@ -239,8 +239,8 @@ __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restric
                 *reinterpret_cast<uint32_t*>(eb + (size_t)S * rec_bytes) = h;
                 H = 1;
             }
-            ctrl->lv[0].H = H;
-            ctrl->lv[0].q = 0;
+            ctrl->lv[lvl].H = H;
+            ctrl->lv[lvl].q = 0;
             ctrl->chunks = 0;
         }
     }
@@ -376,13 +376,15 @@ __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__
     }
 }
 
+constexpr int SPL = MAXL - 1;  // Ctrl level entry of the spawning path's input level
+
 // One workgroup: exclusive scan of the tile counts in place; publishes the
 // walk count and resets the chase queue of this level.
 __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles,
                                                      Ctrl* ctrl, int lvl, Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
-    if (lvl == 0 && ctrl->single) return;
+    if ((lvl == 0 || lvl == SPL) && ctrl->single) return;
     const uint32_t total = wg_exscan_inplace(tilecnt, ntiles, sh);
     if (threadIdx.x == 0) {
         ctrl->lv[lvl].H = total;
@@ -1510,206 +1512,278 @@ __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ 
 }
 
 // ------------------------------------------------------- ruler spawning --
-// Section 2.2, on one GPU. The chase's lanes play the paper's active waves:
-// a wavefront first hands out the walks of its range of sampled rulers and
-// heads, and from then on a lane whose walk ended claims an element of the
-// wavefront's id range that no walk has reached as a new ruler and walks on
-// from it. Every element's slot starts all ones (unreached); a walk claims
-// its next element with a 64-bit compare-and-swap that writes (walk, offset),
-// and a spawned ruler's slot holds SPAWN | its walk id, so a walk whose swap
-// finds a spawned ruler ends there. In a forest every element has one
-// predecessor, so the only competitor for an element is the spawner: the
-// swap decides, and the walk ids are handed out by one counter per spawning
-// round of a wavefront.
+// Section 2.2 on one GPU, in two chases with no atomics on the elements.
+// Spawning exists to cut the long stretches between sampled rulers, whose
+// walks decide how long a chase runs. Phase 1 is the ordinary chase from the
+// sampled rulers and the heads, except that a walk stops after `cap` steps:
+// it marks the next element, which no walk has reached, as its cap target
+// (slot = SPF | walk, offset) and ends there. Between the phases every
+// element whose slot is still free (reached by no walk) is known, and new
+// rulers are spawned among exactly those: each cap target, and each free
+// element that a hash picks at rate 1/k2. Phase 2 walks from the spawned
+// rulers; its lanes tell a spawned ruler from a free element by one plain
+// load of the slot, so every step is one round trip of plain loads. With
+// phase 1 capped at c k steps only a fraction of about exp(-c) of the
+// elements is left for phase 2, where walks are k2 long on average.
 //
 // Walk ids: [0, S0) sampled rulers (block b's ruler is walk b), [S0, T0)
-// heads that are not sampled (their start parked in the record), then spawned
-// rulers. A spawner that loses the swap leaves its id unused; the record is
-// written as an isolated terminal so the walks' list stays a forest.
-constexpr uint32_t SPAWN = TERM;      // slot flag: the element is a spawned ruler
+// heads that are not sampled (start parked in the record), [T0, T0 + R2)
+// spawned rulers (start parked in the record), numbered in tile order.
+// Slots: all ones = free; (walk, offset) = reached; SPF | walk = a phase-1
+// cap target (before the spawn pass) or a spawned ruler (after it).
+constexpr uint32_t SPF = TERM;        // slot flag: cap target / spawned ruler
 constexpr int SP_TPB = 256;
-constexpr int SPL = MAXL - 1;         // Ctrl level entry holding the input level's head walks
 
-// Position of the k-th (from 0) set bit of m; m has more than k set bits.
-__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k) {
-    uint32_t pos = 0;
-    uint32_t c = __popc((uint32_t)m);
-    if (k >= c) { k -= c; pos = 32; m >>= 32; }
-    uint32_t v = (uint32_t)m;
-    c = __popc(v & 0xffffu); if (k >= c) { k -= c; pos += 16; v >>= 16; }
-    c = __popc(v & 0xffu);   if (k >= c) { k -= c; pos += 8;  v >>= 8; }
-    c = __popc(v & 0xfu);    if (k >= c) { k -= c; pos += 4;  v >>= 4; }
-    c = __popc(v & 0x3u);    if (k >= c) { k -= c; pos += 2;  v >>= 2; }
-    if (k >= (v & 1u)) pos += 1;
-    return pos;
-}
-
-__device__ __forceinline__ unsigned long long* slot_word(void* slot, uint32_t x, uint32_t bytes) {
-    return reinterpret_cast<unsigned long long*>(static_cast<char*>(slot) + (size_t)x * bytes);
-}
-
-__global__ void k_sp_init(Ctrl* ctrl, Gate gate) {
+// Every slot free (all ones), and the control words of the path reset.
+__global__ __launch_bounds__(TPB) void k_sp_prep(uint32_t* __restrict__ slotw, uint64_t words, Ctrl* ctrl,
+                                                 Gate gate) {
     if (gate.off()) return;
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->spn = 0;
         ctrl->single = 0;
         ctrl->multi = 0;
     }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n4 = words / 4;
+    const uint4 v = make_uint4(NONE, NONE, NONE, NONE);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        reinterpret_cast<uint4*>(slotw)[i] = v;
+    for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+        slotw[i] = NONE;
 }
 
+// Phase 1: the chase of the sampled rulers' and heads' walks (one walk per
+// lane, wavefront walk ranges as in k_chase), capped at `cap` steps. Unlike
+// the levels' chase every walk is an element of the next list, so every walk
+// that ends on a ruler marks that ruler as having a predecessor.
 template <bool W, int WT>
-__global__ __launch_bounds__(SP_TPB) void k_sp_chase(SrcIn<W, WT> src, Sampler smp, Ctrl* ctrl,
-                                                     typename Lay<W>::Slot* __restrict__ slot,
-                                                     const uint8_t* __restrict__ hp_in,
-                                                     typename Lay<W>::Rec* __restrict__ lrec,
-                                                     uint8_t* __restrict__ hp_c, uint32_t cap, Gate gate) {
+__global__ __launch_bounds__(SP_TPB) void k_sp_chase1(SrcIn<W, WT> src, Sampler smp, Ctrl* ctrl,
+                                                      typename Lay<W>::Slot* __restrict__ slot,
+                                                      typename Lay<W>::Rec* __restrict__ lrec,
+                                                      uint8_t* __restrict__ hp_c, uint32_t cap, Gate gate) {
     if (gate.off()) return;
     using L = Lay<W>;
     using Val = typename L::Val;
-    constexpr uint32_t SB = sizeof(typename L::Slot);
-    constexpr unsigned long long FREE = ~0ull;
-    const uint32_t lane = lane_id();
     const uint32_t m = smp.m;
     const uint32_t S0 = (m + (1u << smp.log2k) - 1u) >> smp.log2k;
     const uint32_t T0 = S0 + ctrl->lv[SPL].H;
     const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
     const uint32_t per = T0 / nwave + 1;
-    uint32_t wcur = (uint32_t)min<uint64_t>((uint64_t)gwave * per, T0);
+    uint32_t cursor = (uint32_t)min<uint64_t>((uint64_t)gwave * per, T0);
     const uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, T0);
-    const uint32_t span = m / nwave + 1;
-    uint32_t scur = (uint32_t)min<uint64_t>((uint64_t)gwave * span, m);
-    const uint32_t shi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * span, m);
-    bool can_spawn = true;  // cleared if the walk ids run out (not a forest)
-    uint32_t w = NONE, x = 0, nxt = 0;
-    Val v = L::zero(), off = L::zero();
-    bool fresh = false;     // walk just started: the record of x is not loaded yet
+    uint32_t w = NONE, x = 0, steps = 0;
+    Val off = L::zero();
     for (;;) {
-        uint64_t idle = __ballot(w == NONE);
-        // the walks of the wavefront's sampled rulers and heads
-        if (idle && wcur < whi) {
-            const uint32_t my = wcur + mbcnt(idle);
-            wcur = min(wcur + (uint32_t)__popcll(idle), whi);
+        const uint64_t idle = __ballot(w == NONE);
+        if (idle == ~0ull && cursor >= whi) break;
+        if (idle && cursor < whi) {
+            const uint32_t my = cursor + mbcnt(idle);
+            cursor = min(cursor + (uint32_t)__popcll(idle), whi);
             if (w == NONE && my < whi) {
                 const uint32_t s0 = (my < S0) ? smp.start(my) : lrec[my].nxt;
                 if (s0 < m) {
                     w = my;
                     x = s0;
                     off = L::zero();
-                    fresh = true;
-                    slot[s0] = L::slot(my, L::zero());
+                    steps = 0;
                 } else {  // corrupt parked start (cannot happen for valid input)
                     lrec[my] = L::rec(TERM | IDX, L::zero());
                     atomicOr(&ctrl->err, 8u);
                 }
             }
-            idle = __ballot(w == NONE);
         }
-        // spawning: idle lanes take unreached elements of the wavefront's id range
-        if (idle && wcur >= whi && scur < shi && can_spawn) {
-            const uint32_t z = scur + lane;
-            bool cand = false;
-            if (z < shi && hp_in[z] && !smp.sampled(z))
-                cand = *reinterpret_cast<const uint32_t*>(slot_word(slot, z, SB)) == NONE;
-            const uint64_t avail = __ballot(cand);
-            const uint32_t ni = (uint32_t)__popcll(idle), na = (uint32_t)__popcll(avail);
-            uint64_t take = avail;
-            if (na > ni) {  // the first ni candidates; the scan resumes after the last one taken
-                const uint32_t last = select_bit(avail, ni - 1u);
-                take = avail & ((2ull << last) - 1ull);
-                scur += last + 1u;
-            } else {
-                scur += 64u;
+        if (w == NONE) continue;
+        uint32_t nxt;
+        Val v;
+        src.load(x, nxt, v);
+        slot[x] = L::slot(w, off);
+        if (nxt & TERM) {                           // x is a terminal: the walk ends on it
+            lrec[w] = L::rec(nxt, L::add(off, v));
+            w = NONE;
+            continue;
+        }
+        off = L::add(off, v);
+        if (smp.sampled(nxt)) {                     // reached the next sampled ruler
+            const uint32_t c = nxt >> smp.log2k;
+            lrec[w] = L::rec(c, off);
+            hp_c[c] = 1;
+            if (c == w) atomicOr(&ctrl->err, 8u);   // back at its own start: a cycle
+            w = NONE;
+        } else if (++steps >= cap) {                // capped: nxt becomes a spawned ruler
+            slot[nxt] = L::slot(SPF | w, off);
+            w = NONE;
+        } else {
+            x = nxt;
+        }
+    }
+}
+
+// Spawned rulers: per tile of TILE ids, lane j looks at ids tile*TILE + i*TPB
+// + j (i < TILE / TPB), coalesced. A ruler is a cap target or a free element
+// picked by the hash.
+constexpr int SP_PER = TILE / TPB;
+
+template <bool W>
+__device__ __forceinline__ bool sp_ruler(const typename Lay<W>::Slot* slot, uint32_t z, uint32_t seed,
+                                         uint32_t k2mask) {
+    const uint32_t w = slot[z].w;
+    if (w == NONE) return (hash32(seed, z) & k2mask) == 0u;
+    return (w & SPF) != 0u;
+}
+
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_sp_count(const typename Lay<W>::Slot* __restrict__ slot, uint32_t n,
+                                                  uint32_t seed, uint32_t k2mask, uint32_t* __restrict__ tilecnt,
+                                                  uint32_t ntiles, Gate gate) {
+    if (gate.off()) return;
+    __shared__ uint32_t sh[TPB / 64];
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < SP_PER; ++i) {
+            const uint32_t z = t * TILE + i * TPB + threadIdx.x;
+            if (z < n) c += sp_ruler<W>(slot, z, seed, k2mask);
+        }
+        const uint32_t tot = block_sum(c, sh);
+        if (threadIdx.x == 0) tilecnt[t] = tot;
+        __syncthreads();
+    }
+}
+
+// One workgroup: scan of the spawned-ruler counts; publishes their number.
+__global__ __launch_bounds__(1024) void k_sp_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles, Ctrl* ctrl,
+                                                  Gate gate) {
+    if (gate.off()) return;
+    __shared__ uint32_t sh[1024 / 64];
+    const uint32_t total = wg_exscan_inplace(tilecnt, ntiles, sh);
+    if (threadIdx.x == 0) ctrl->spn = total;
+}
+
+// Numbers the spawned rulers, parks each one's start in its record, flags its
+// slot, and ends the capped walk whose target it is on it.
+template <bool W>
+__global__ __launch_bounds__(TPB) void k_sp_write(typename Lay<W>::Slot* __restrict__ slot, uint32_t n,
+                                                  uint32_t seed, uint32_t k2mask,
+                                                  const uint32_t* __restrict__ tileoff, uint32_t ntiles,
+                                                  const Ctrl* ctrl, uint32_t S0, typename Lay<W>::Rec* __restrict__ lrec,
+                                                  uint8_t* __restrict__ hp_c, Gate gate) {
+    if (gate.off()) return;
+    using L = Lay<W>;
+    __shared__ uint32_t sh[TPB / 64];
+    const uint32_t T0 = S0 + ctrl->lv[SPL].H;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int i = 0; i < SP_PER; ++i) {
+            const uint32_t z = t * TILE + i * TPB + threadIdx.x;
+            if (z < n && sp_ruler<W>(slot, z, seed, k2mask)) bits |= 1u << i;
+        }
+        uint32_t total;
+        uint32_t pos = T0 + tileoff[t] + block_exscan((uint32_t)__popc(bits), sh, &total);
+        while (bits) {
+            const int i = __ffs(bits) - 1;
+            bits &= bits - 1;
+            const uint32_t z = t * TILE + i * TPB + threadIdx.x;
+            const typename L::Slot sv = slot[z];
+            if (sv.w != NONE) {  // a cap target: its walk ends on this ruler
+                lrec[sv.w & IDX] = L::rec(pos, L::val(sv));
+                hp_c[pos] = 1;
             }
-            if (scur > shi) scur = shi;
-            const uint32_t nt = (uint32_t)__popcll(take);
-            if (nt) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&ctrl->spn, nt);
-                base = __shfl(base, 0);
-                if ((uint64_t)T0 + base + nt > cap) {  // more walks than elements: not a forest
-                    can_spawn = false;
-                    if (lane == 0) atomicOr(&ctrl->err, 16u);
+            slot[z] = L::slot(SPF | pos, L::zero());
+            *reinterpret_cast<uint32_t*>(&lrec[pos]) = z;  // parked start
+            ++pos;
+        }
+        __syncthreads();
+    }
+}
+
+// Phase 2: the walks of the spawned rulers. A lane holds the record of x and
+// the pending successor; each step loads the successor's slot and record
+// together and then decides: a spawned ruler ends the walk, a free element is
+// taken.
+template <bool W, int WT>
+__global__ __launch_bounds__(SP_TPB) void k_sp_chase2(SrcIn<W, WT> src, Sampler smp, Ctrl* ctrl,
+                                                      typename Lay<W>::Slot* __restrict__ slot,
+                                                      typename Lay<W>::Rec* __restrict__ lrec,
+                                                      uint8_t* __restrict__ hp_c, Gate gate) {
+    if (gate.off()) return;
+    using L = Lay<W>;
+    using Val = typename L::Val;
+    const uint32_t m = smp.m;
+    const uint32_t S0 = (m + (1u << smp.log2k) - 1u) >> smp.log2k;
+    const uint32_t T0 = S0 + ctrl->lv[SPL].H;
+    const uint32_t R2 = ctrl->spn;
+    const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t per = R2 / nwave + 1;
+    uint32_t cursor = T0 + (uint32_t)min<uint64_t>((uint64_t)gwave * per, R2);
+    const uint32_t whi = T0 + (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, R2);
+    uint32_t w = NONE, x = 0, nxt = 0;
+    Val v = L::zero(), off = L::zero();
+    bool fresh = false;  // walk just started: the record of x is not loaded yet
+    for (;;) {
+        const uint64_t idle = __ballot(w == NONE);
+        if (idle == ~0ull && cursor >= whi) break;
+        if (idle && cursor < whi) {
+            const uint32_t my = cursor + mbcnt(idle);
+            cursor = min(cursor + (uint32_t)__popcll(idle), whi);
+            if (w == NONE && my < whi) {
+                const uint32_t s0 = lrec[my].nxt;
+                if (s0 < m) {
+                    w = my;
+                    x = s0;
+                    off = L::zero();
+                    fresh = true;
                 } else {
-                    const bool mine = (take >> lane) & 1ull;
-                    const uint32_t cid = T0 + base + mbcnt(take);
-                    uint32_t got = 0;
-                    if (mine) {
-                        const unsigned long long want = (unsigned long long)(SPAWN | cid);  // offset 0
-                        got = atomicCAS(slot_word(slot, z, SB), FREE, want) == FREE;
-                        if (got) {
-                            if constexpr (W) slot[z].s = 0;
-                        } else {
-                            lrec[cid] = L::rec(TERM | z, L::zero());  // lost to a walk: an unused id
-                        }
-                    }
-                    // hand the new rulers to the idle lanes in order
-                    const uint32_t k = mbcnt(idle);
-                    const bool recv = (w == NONE) && k < nt;
-                    const uint32_t from = recv ? select_bit(take, k) : lane;
-                    const uint32_t rz = __shfl(z, (int)from);
-                    const uint32_t rc = __shfl(cid, (int)from);
-                    const uint32_t rg = __shfl(got, (int)from);
-                    if (recv && rg) {
-                        w = rc;
-                        x = rz;
-                        off = L::zero();
-                        fresh = true;
-                    }
+                    lrec[my] = L::rec(TERM | IDX, L::zero());
+                    atomicOr(&ctrl->err, 8u);
                 }
             }
         }
-        if (__ballot(w != NONE) == 0 && wcur >= whi && (scur >= shi || !can_spawn)) break;
-        // one step: a lane tests the successor it loaded; if that is neither a
-        // terminal nor a ruler it claims it and loads its record in the same
-        // round trip (a fresh walk only loads its start's record)
+        if (w == NONE) continue;
         bool adv = false;
         Val o2 = off;
-        if (w != NONE && !fresh) {
+        if (!fresh) {
             o2 = L::add(off, v);
-            if (nxt & TERM) {                       // x is a terminal: the walk ends on it
+            if (nxt & TERM) {
                 lrec[w] = L::rec(nxt, o2);
                 w = NONE;
-            } else if (smp.sampled(nxt)) {          // reached a sampled ruler
+            } else if (smp.sampled(nxt)) {
                 const uint32_t c = nxt >> smp.log2k;
                 lrec[w] = L::rec(c, o2);
                 hp_c[c] = 1;
-                if (c == w) atomicOr(&ctrl->err, 8u);  // back at its own start: a cycle
                 w = NONE;
             } else {
                 adv = true;
             }
         }
+        if (w == NONE) continue;
         const uint32_t q = fresh ? x : nxt;
-        unsigned long long old = FREE;
-        uint32_t ln = 0;
-        Val lv = L::zero();
-        if (adv) old = atomicCAS(slot_word(slot, q, SB), FREE, ((unsigned long long)o2.c << 32) | w);
-        if (fresh || adv) src.load(q, ln, lv);
+        uint32_t sw = NONE, ln;
+        Val lv;
+        if (adv) sw = slot[q].w;
+        src.load(q, ln, lv);
         if (fresh) {
             nxt = ln;
             v = lv;
             fresh = false;
-        } else if (adv) {
-            if (old == FREE) {
-                if constexpr (W) slot[q].s = o2.s;
-                x = q;
-                off = o2;
-                nxt = ln;
-                v = lv;
-            } else {
-                const uint32_t ow = (uint32_t)old;
-                if (ow & SPAWN) {                   // reached a spawned ruler
-                    const uint32_t c = ow & IDX;
-                    lrec[w] = L::rec(c, o2);
-                    hp_c[c] = 1;
-                    if (c == w) atomicOr(&ctrl->err, 8u);
-                } else {                            // reached by two walks: two predecessors
-                    lrec[w] = L::rec(TERM | IDX, o2);
-                    atomicOr(&ctrl->err, 2u);
-                }
-                w = NONE;
-            }
+        } else if (sw == NONE) {                    // a free element: the walk takes it
+            slot[q] = L::slot(w, o2);
+            x = q;
+            off = o2;
+            nxt = ln;
+            v = lv;
+        } else if (sw & SPF) {                      // a spawned ruler: the walk ends on it
+            const uint32_t c = sw & IDX;
+            lrec[w] = L::rec(c, o2);
+            hp_c[c] = 1;
+            if (c == w) atomicOr(&ctrl->err, 8u);
+            w = NONE;
+        } else {                                    // reached twice: two predecessors
+            lrec[w] = L::rec(TERM | IDX, o2);
+            atomicOr(&ctrl->err, 2u);
+            w = NONE;
         }
     }
 }
@@ -2002,7 +2076,7 @@ static hipError_t run_headsum(const RunArgs& a, const Plan& p, Gate g) {
     const Sampler smp0{n, p.log2k[0], p.lseed[0]};
     hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs,
                        reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl), smp0, a.ws + p.off_eb[0], (uint32_t)p.m[1],
-                       (uint32_t)p.rec_bytes, g);
+                       (uint32_t)p.rec_bytes, 0, g);
     return hipGetLastError();
 }
 
@@ -2267,9 +2341,10 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
     return hipSuccess;
 }
 
-// Ruler spawning: predecessor bytes and heads of the input, the spawning
-// chase (its walks form the contracted list, sized on the device), the
-// ruling-set levels on that list, then every element from its walk.
+// Ruler spawning: predecessor bytes and heads of the input, the capped chase,
+// the spawned rulers, their chase (all walks form the contracted list, sized
+// on the device), the ruling-set levels on that list, then every element
+// from its walk.
 template <bool W, int WT, class Out0>
 static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
     using L = Lay<W>;
@@ -2291,10 +2366,24 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
     uint8_t* hp_c = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);  // the walks' predecessor bytes
     const Sampler smp{n, p.sp_log2k, p.sp_seed};
     const uint32_t S0 = (n + (1u << p.sp_log2k) - 1u) >> p.sp_log2k;
-    hipLaunchKernelGGL(k_sp_init, dim3(1), dim3(64), 0, st, ctrl, g);
-    LR_TRY(hipGetLastError());
-    LR_TRY(fill(hp_in, n, 0u, st, nullptr, g));
-    LR_TRY(fill(slot, (uint64_t)n * p.rec_bytes, 0xffffffffu, st, nullptr, g));
+    {
+        const uint64_t words = (uint64_t)n * p.rec_bytes / 4;
+        hipLaunchKernelGGL(k_sp_prep, dim3(grid_for(words, TPB * 4)), dim3(TPB), 0, st,
+                           reinterpret_cast<uint32_t*>(slot), words, ctrl, g);
+        LR_TRY(hipGetLastError());
+    }
+    {  // one list: its head from the streaming sum, and no predecessor marks
+        const bool vec = ((uintptr_t)a.succ % 16) == 0;
+        const uint32_t gs = std::min<uint32_t>(grid_for(n, TPB * 16), HEADSUM_BLOCKS);
+        uint32_t* part = reinterpret_cast<uint32_t*>(ws + p.off_hsum);
+        if (vec) hipLaunchKernelGGL(k_headsum<true>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part, g);
+        else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part, g);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs, ctrl, smp,
+                           reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, SPL, g);
+        LR_TRY(hipGetLastError());
+    }
+    LR_TRY(fill(hp_in, n, 0u, st, ctrl, g));
     {
         const bool vec = ((uintptr_t)a.succ % 16) == 0;
         const uint32_t gd = grid_for(n, TPB * 4 * 4);
@@ -2305,23 +2394,33 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
     rec_ev(a, EV_DETECT);
     const uint32_t gt = std::min<uint32_t>(p.sp_ntiles, (uint32_t)device_cus() * 8);
     hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp_in, smp, tile, p.sp_ntiles,
-                       reinterpret_cast<uint32_t*>(hp_c), (n + 3) / 4, nullptr, nullptr, g);
+                       reinterpret_cast<uint32_t*>(hp_c), (n + 3) / 4, ctrl, nullptr, g);
     LR_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.sp_ntiles, ctrl, SPL, g);
     LR_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp_in, smp, tile, p.sp_ntiles,
-                       reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, nullptr, nullptr, g);
+                       reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, ctrl, nullptr, g);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_HEADS);
     {
-        auto kern = k_sp_chase<W, WT>;
-        static uint32_t resident = 0;  // one per template instance
-        if (!resident) resident = persistent_grid(kern, SP_TPB);
-        const uint64_t lanes = std::max<uint64_t>((uint64_t)n / LR_SPAWN_PER_LANE, 4 * 64);
-        const uint32_t grid = (uint32_t)std::min<uint64_t>((lanes + SP_TPB - 1) / SP_TPB, resident);
         SrcIn<W, WT> src{a.succ, a.weight, n};
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(SP_TPB), 0, st, src, smp, ctrl, slot, hp_in, lrec, hp_c,
-                           (uint32_t)p.m[0], g);
+        auto k1 = k_sp_chase1<W, WT>;
+        auto k2 = k_sp_chase2<W, WT>;
+        static uint32_t g1 = 0, g2 = 0;  // one per template instance
+        if (!g1) g1 = persistent_grid(k1, SP_TPB);
+        if (!g2) g2 = persistent_grid(k2, SP_TPB);
+        const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)LR_SPAWN_CAP << p.sp_log2k, n);
+        hipLaunchKernelGGL(k1, dim3(g1), dim3(SP_TPB), 0, st, src, smp, ctrl, slot, lrec, hp_c, cap, g);
+        LR_TRY(hipGetLastError());
+        const uint32_t seed2 = p.sp_seed ^ 0x5bd1e995u, k2mask = LR_SPAWN_K2 - 1u;
+        hipLaunchKernelGGL(k_sp_count<W>, dim3(gt), dim3(TPB), 0, st, slot, n, seed2, k2mask, tile, p.sp_ntiles, g);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(1024), 0, st, tile, p.sp_ntiles, ctrl, g);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_sp_write<W>, dim3(gt), dim3(TPB), 0, st, slot, n, seed2, k2mask, tile, p.sp_ntiles, ctrl,
+                           S0, lrec, hp_c, g);
+        LR_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k2, dim3(g2), dim3(SP_TPB), 0, st, src, smp, ctrl, slot, lrec, hp_c, g);
         LR_TRY(hipGetLastError());
     }
     LevelShifts ks{};

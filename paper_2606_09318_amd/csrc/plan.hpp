@@ -18,7 +18,11 @@ constexpr uint32_t HEADSUM_BLOCKS = 2048;      // partial sums of the one-list h
 #endif
 constexpr uint32_t LOG_CHUNK = LR_LOG_CHUNK;  // records per visit-log chunk
 constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps the log slack)
-constexpr uint64_t LOG_MIN_N = 1ull << 22;   // smallest level 0 that uses the visit log
+#ifndef LR_LOG_MIN_LOG2
+#define LR_LOG_MIN_LOG2 25
+#endif
+constexpr uint64_t LOG_MIN_N = 1ull << LR_LOG_MIN_LOG2;  // smallest level 0 that uses the visit log
+constexpr uint64_t LOG_FORCE_MIN_N = 1ull << 16;          // smallest level 0 LR_VISIT_LOG applies to
 constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
 constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
 constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
@@ -38,15 +42,20 @@ constexpr uint32_t LOCAL_SAMPLE_STRIDE = 16;
 #define LR_LOCAL_GUESS_16THS 4
 #endif
 constexpr uint64_t local_guess_cap(uint64_t n) { return n * LR_LOCAL_GUESS_16THS / 16; }
-// ruler spawning: default sampling spacing of the input level, and input
-// elements per chase lane (the lanes are the walks kept active)
+// ruler spawning: default sampling spacing k of the input level, the cap of
+// its walks in multiples of k, and the spacing k2 (a power of two) at which
+// rulers are spawned among the elements the capped walks left
 #ifndef LR_SPAWN_K0
-#define LR_SPAWN_K0 64
+#define LR_SPAWN_K0 32
 #endif
 constexpr uint32_t SPAWN_K0 = LR_SPAWN_K0;
-#ifndef LR_SPAWN_PER_LANE
-#define LR_SPAWN_PER_LANE 64
+#ifndef LR_SPAWN_CAP
+#define LR_SPAWN_CAP 2
 #endif
+#ifndef LR_SPAWN_K2
+#define LR_SPAWN_K2 4
+#endif
+static_assert((LR_SPAWN_K2 & (LR_SPAWN_K2 - 1)) == 0, "k2 is a power of two");
 // grouping tiles: lanes x LR_PLACE_PER records (half as many weighted); the
 // passes that also carry roots use wider workgroups (measured faster there,
 // slower without roots)

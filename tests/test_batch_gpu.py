@@ -75,8 +75,9 @@ def test_batch_log_mode_without_roots():
         inputs.append(L)
     reqs = lr.requests(items)
     assert sum(sizes) >= 1 << 22
-    ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items)))
-    assert lr.lr_rank_batch(reqs, len(items), ws) == lr.LR_OK
+    o = lr.make_opts(flags=lr.LR_VISIT_LOG)
+    ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items), o))
+    assert lr.lr_rank_batch(reqs, len(items), ws, o) == lr.LR_OK
     torch.cuda.synchronize()
     for (s, r, t), L in zip(items, inputs):
         assert np.array_equal(host_u32(r), oracle.rank(L.succ)[1])

@@ -13,23 +13,24 @@ from gpu_util import dev, host_u32
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n", [1 << 16, (1 << 22) + 5])
-def test_graph_capture_and_replays(n):
-    print(f"case: graph capture n={n}", flush=True)
+@pytest.mark.parametrize("n,flags", [(1 << 16, 0), ((1 << 22) + 5, 0), ((1 << 22) + 5, lr.LR_VISIT_LOG)])
+def test_graph_capture_and_replays(n, flags):
+    print(f"case: graph capture n={n} flags={flags}", flush=True)
+    o = lr.make_opts(flags=flags)
     lists = [workloads.random_list(n, seed=60 + i) if i % 2 == 0 else workloads.block_list(n, 4096, seed=60 + i)
              for i in range(4)]
     succ = dev(lists[0].succ)
     rank = torch.empty(n, dtype=torch.int32, device="cuda")
     root = torch.empty(n, dtype=torch.int32, device="cuda")
-    ws = lr.workspace(lr.lr_workspace_bytes(n))
+    ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_NONE, o))
     s = torch.cuda.Stream()
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
-        assert lr.lr_rank(succ, rank, root, ws, None, s) == lr.LR_OK  # warm-up outside the capture
+        assert lr.lr_rank(succ, rank, root, ws, o, s) == lr.LR_OK  # warm-up outside the capture
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
-        st = lr.lr_rank(succ, rank, root, ws, None, s)
+        st = lr.lr_rank(succ, rank, root, ws, o, s)
     assert st == lr.LR_OK
     for i, L in enumerate(lists * 2):
         succ.copy_(torch.from_numpy(L.succ.view(np.int32)))

@@ -215,11 +215,13 @@ def test_invalid_input_is_memory_safe():
 
 
 def test_large_random_takes_capacity_levels():
-    """A contracted list as long as the input (no locality) at a size whose
-    plain path would use the visit log."""
+    """A contracted list as long as the input (no locality), with and without
+    the visit log for its first level."""
     n = (1 << 22) + 12345
     print(f"case: local random list n={n}", flush=True)
-    check_rank(workloads.random_list(n, seed=17).succ, want_root=False)
+    succ = workloads.random_list(n, seed=17).succ
+    check_rank(succ, want_root=False)
+    check_rank(succ, local_opts(flags=lr.LR_VISIT_LOG), want_root=False)
 
 
 # ------------------------------------------------------------------------

@@ -7,7 +7,7 @@ import torch
 import oracle
 import paper_2606_09318_amd as lr
 import workloads
-from gpu_util import gpu_prefix, gpu_rank, gpu_wyllie
+from gpu_util import dev, gpu_prefix, gpu_rank, gpu_wyllie
 
 pytestmark = pytest.mark.gpu
 
@@ -204,7 +204,32 @@ def test_profile_phases():
 
 
 # ------------------------------------------------------------------------
-# Inputs of 2^22 elements and more take the visit-log path at level 0.
+# Inputs of 2^25 elements and more take the visit-log path at level 0 by
+# default; LR_VISIT_LOG takes it from 2^16 on, so these cases stay small.
+
+LOG = lr.LR_VISIT_LOG
+
+
+def test_visit_log_threshold():
+    """The default switches to the visit log at 2^25; the result is the closed
+    form of the generator either way (checked on the device: the oracle would
+    take seconds per call at this size)."""
+    n = (1 << 25) + 3
+    print(f"case: default visit log n={n}", flush=True)
+    L = workloads.random_list(n, seed=25)
+    succ = dev(L.succ)
+    r = torch.empty(n, dtype=torch.int32, device="cuda")
+    t = torch.empty(n, dtype=torch.int32, device="cuda")
+    exp = torch.empty(n, dtype=torch.int32, device="cuda")
+    exp[dev(L.order).long()] = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+    for flags in (0, lr.LR_NO_LOCAL):
+        ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(flags=flags)))
+        assert lr.lr_rank(succ, r, t, ws, lr.make_opts(flags=flags)) == lr.LR_OK
+        torch.cuda.synchronize()
+        assert torch.equal(r, exp)
+        assert bool((t == int(L.order[-1])).all())
+        del ws
+
 
 @pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 12345, 5000011])
 @pytest.mark.parametrize("lane_walks", [1, 2])
@@ -213,23 +238,24 @@ def test_log_mode_random_lists(n, lane_walks):
     p = lr.lr_plan_query(n)
     assert p.levels >= 1
     L = workloads.random_list(n, seed=n % 1000)
-    check_rank(L.succ, lr.make_opts(lane_walks=lane_walks))
-    st, r, _ = gpu_rank(L.succ, lr.make_opts(lane_walks=lane_walks), want_root=False)
+    check_rank(L.succ, lr.make_opts(flags=LOG, lane_walks=lane_walks))
+    st, r, _ = gpu_rank(L.succ, lr.make_opts(flags=LOG, lane_walks=lane_walks), want_root=False)
     assert st == lr.LR_OK and np.array_equal(r, oracle.rank(L.succ)[1])
 
 
 def test_log_mode_block_list_and_forest():
     n = (1 << 22) + 77
     print("case: log mode block list / forest", flush=True)
-    check_rank(workloads.block_list(n, block=4096, seed=8).succ)
+    o = lr.make_opts(flags=LOG)
+    check_rank(workloads.block_list(n, block=4096, seed=8).succ, o)
     F = workloads.forest(n, mean=64, n_long=4, long_len=100000, seed=9)
-    check_rank(F.succ)
-    st, s, r, t = gpu_prefix(F.succ, F.weight)
+    check_rank(F.succ, o)
+    st, s, r, t = gpu_prefix(F.succ, F.weight, o)
     assert st == lr.LR_OK
     ost, er, et, es = oracle.rank(F.succ, F.weight)
     assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
     F32 = workloads.forest(n, mean=8, n_long=1, long_len=300000, seed=10, wdtype=np.int32)
-    st, s, r, t = gpu_prefix(F32.succ, F32.weight)
+    st, s, r, t = gpu_prefix(F32.succ, F32.weight, o)
     ost, er, et, es = oracle.rank(F32.succ, F32.weight)
     assert st == lr.LR_OK and np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
 
@@ -237,15 +263,16 @@ def test_log_mode_block_list_and_forest():
 def test_log_mode_all_singletons_and_pairs():
     n = (1 << 22) + 3
     print("case: log mode singletons / pairs", flush=True)
-    check_rank(np.arange(n, dtype=np.uint32))
+    o = lr.make_opts(flags=LOG)
+    check_rank(np.arange(n, dtype=np.uint32), o)
     pairs = np.arange(n, dtype=np.uint32)
     pairs[0:n - 1:2] = np.arange(1, n, 2, dtype=np.uint32)
-    check_rank(pairs)
+    check_rank(pairs, o)
 
 
 def test_log_mode_validate():
     n = 1 << 22
-    o = lr.make_opts(flags=lr.LR_VALIDATE)
+    o = lr.make_opts(flags=lr.LR_VALIDATE | LOG)
     L = workloads.random_list(n, seed=4)
     assert gpu_rank(L.succ, o)[0] == lr.LR_OK
     cyc = L.succ.copy()
@@ -261,4 +288,5 @@ def test_log_mode_invalid_input_is_memory_safe():
     n = 1 << 22
     rng = np.random.default_rng(11)
     bad = rng.integers(0, n, size=n).astype(np.uint32)
+    assert gpu_rank(bad, lr.make_opts(flags=LOG))[0] == lr.LR_OK
     assert gpu_rank(bad)[0] == lr.LR_OK

@@ -120,7 +120,7 @@ def test_repeated_calls_same_result():
 
 
 def test_large_random_certificate():
-    """2^22 + 5 elements: the walks' list takes the visit-log levels."""
+    """2^22 + 5 elements, checked on the device."""
     n = (1 << 22) + 5
     print(f"case: spawn n={n}", flush=True)
     L = workloads.random_list(n, seed=50)
