@@ -43,6 +43,9 @@ def parse():
                     help="only the device access-rate calibration (lr_calibrate), one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--sweep", choices=["spawn", "visit-log"],
+                    help="only a size sweep, one JSON line: ruler spawning (LR_SPAWN, first-level spacing 16/32/64) "
+                         "against the default path, or the first level with and without the visit log")
     return ap.parse_args()
 
 
@@ -81,6 +84,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4, "reps": 5}))
+        return
+
+    if args.sweep:
+        print(json.dumps({"sweep": args.sweep, "unit": "ms per lr_rank call (median of 15), rank output",
+                          "rows": size_sweep(args.sweep, stream)}))
         return
 
     n = args.n
@@ -262,6 +270,73 @@ def forest_only(args, stream):
     ms = ev0.elapsed_time(ev1) / args.steps
     print(json.dumps({"workload": "forest 2^27 int64 weights", "ms_per_step": round(ms, 4),
                       "g_elements_per_s": round(n / (ms * 1e-3) / 1e9, 3), "list": "forest"}))
+
+
+def size_sweep(kind: str, stream) -> list:
+    """Ruler spawning or the visit-log threshold across input sizes. Every
+    timed configuration is checked against the closed form of the generator
+    (random lists) or the local certificate (forests)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import certificate_gpu
+
+    def median_ms(fn, reps=15):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return round(sorted(ts)[len(ts) // 2], 4)
+
+    rows = []
+    if kind == "spawn":
+        sizes, inputs = [14, 16, 18, 20, 22, 23, 24, 25], ["random"]
+        modes = [("default", 0, ())] + [(f"spawn_k{k}", lr.LR_SPAWN, (k,)) for k in (16, 32, 64)]
+    else:
+        sizes, inputs = [21, 22, 23, 24, 25, 26], ["random", "forest"]
+        modes = [("default", lr.LR_NO_LOCAL, ()), ("visit_log", lr.LR_NO_LOCAL | lr.LR_VISIT_LOG, ())]
+    for logn in sizes:
+        n = 1 << logn
+        for kind_in in inputs:
+            if kind_in == "random":
+                L = workloads.random_list(n, seed=2)
+                succ_np, order = L.succ, L.order
+            else:
+                F = workloads.forest(n, mean=64, n_long=4, long_len=n // 64, seed=3)
+                succ_np, order = F.succ, None
+            succ = torch.from_numpy(succ_np.view(np.int32)).cuda()
+            r = torch.empty(n, dtype=torch.int32, device="cuda")
+            t = torch.empty(n, dtype=torch.int32, device="cuda")
+            exp = None
+            if order is not None:
+                exp = torch.empty(n, dtype=torch.int32, device="cuda")
+                exp[torch.from_numpy(order.view(np.int32)).cuda().long()] = torch.arange(
+                    n - 1, -1, -1, dtype=torch.int32, device="cuda")
+            row = {"n": n, "input": kind_in}
+            for name, flags, sp in modes:
+                o = lr.make_opts(flags=flags, spacing=sp)
+                ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_NONE, o))
+                row[name] = median_ms(lambda: lr.lr_rank(succ, r, t, ws, o, stream))
+                ok = torch.equal(r, exp) if exp is not None else certificate_gpu(succ, r, t)
+                if not ok:
+                    raise SystemExit(f"sweep: wrong result, n={n} {kind_in} {name}")
+                del ws
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            del succ, r, t, exp
+            torch.cuda.empty_cache()
+    return rows
 
 
 def locality_bench(n: int, rank, stream, gammas) -> dict:
