@@ -117,3 +117,32 @@ def test_local_contraction_workspace():
         assert p.workspace_bytes == b
         plain = lr.lr_plan_query(n, w)
         assert p.levels == plain.levels and list(p.m) == list(plain.m)
+
+
+def test_spawn_workspace_and_flags():
+    """LR_SPAWN sizes the input level's slots, predecessor bytes and head
+    counts plus the walks' records (at most n) on top of the walks' levels;
+    it excludes LR_LOCAL; spacing[0] is the input level's spacing and
+    spacing[1..] the levels above."""
+    for n, w in [(1, lr.LR_W_NONE), (5000, lr.LR_W_NONE), (1 << 20, lr.LR_W_NONE), (1 << 20, lr.LR_W_I64)]:
+        o = lr.make_opts(flags=lr.LR_SPAWN)
+        b = lr.lr_workspace_bytes(n, w, o)
+        rec = 16 if w != lr.LR_W_NONE else 8
+        assert b >= n * (2 * rec + 1)
+        assert lr.lr_plan_query(n, w, o).workspace_bytes == b
+    assert lr.lr_workspace_bytes(1000, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_SPAWN | lr.LR_LOCAL)) == 0
+    assert lr.lr_workspace_bytes(1000, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_SPAWN, spacing=(3,))) == 0
+    p = lr.lr_plan_query(1 << 20, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_SPAWN, spacing=(64, 8, 4)))
+    assert [p.spacing[i] for i in range(2)] == [8, 4]
+
+
+def test_visit_log_flag_sizes_the_log():
+    """LR_VISIT_LOG adds the visit log below 2^25 (from 2^16 on) and changes
+    nothing for smaller inputs."""
+    n = 1 << 20
+    plain = lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_NO_LOCAL))
+    logged = lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_NO_LOCAL | lr.LR_VISIT_LOG))
+    assert logged > plain + 12 * n
+    small = 1 << 15
+    assert lr.lr_workspace_bytes(small, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_VISIT_LOG)) == \
+        lr.lr_workspace_bytes(small, lr.LR_W_NONE)
