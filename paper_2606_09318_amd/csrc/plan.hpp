@@ -23,7 +23,10 @@ constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps th
 #endif
 constexpr uint64_t LOG_MIN_N = 1ull << LR_LOG_MIN_LOG2;  // smallest level 0 that uses the visit log
 constexpr uint64_t LOG_FORCE_MIN_N = 1ull << 16;          // smallest level 0 LR_VISIT_LOG applies to
-constexpr uint32_t PLACE_FINE_SHIFT = 13;    // fine placement ranges of 8192 elements (LDS of one workgroup)
+#ifndef LR_PLACE_FINE_SHIFT
+#define LR_PLACE_FINE_SHIFT 13
+#endif
+constexpr uint32_t PLACE_FINE_SHIFT = LR_PLACE_FINE_SHIFT;  // fine placement ranges of 8192 elements (LDS of one workgroup)
 constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
 constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
 // automatic contraction: considered from this size on; the contracted levels
