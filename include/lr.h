@@ -80,18 +80,19 @@ enum {
  * two grouping passes then bring every record to its element's range, and
  * the outputs are written range by range. Below 2^25 the random stores are
  * cheaper (the arrays are small enough for the caches to absorb them). */
-/* Ruler spawning (Section 2.2): the first level's chase keeps its lanes busy.
- * A lane whose walk reached a ruler, once its wavefront has handed out all the
- * sampled rulers' and heads' walks, claims an element that no walk has
- * reached yet as a new ruler and walks from there, so long stretches between
- * sampled rulers are cut by walks started inside them. Elements are claimed
- * with an atomic compare-and-swap on their slot (a walk stops where it finds
- * a spawned ruler). The walks are numbered on the device and their list is
- * ranked by the ruling-set levels, with sizes read on the device; spacing[0]
- * is then the first level's sampling spacing and spacing[1..] the spacings of
- * the levels above (0 = defaults). Results are identical to the default path.
- * It shortens the longest walk of small, cache-resident inputs; on inputs
- * far beyond the caches the per-step atomic costs more than it saves. */
+/* Ruler spawning (Section 2.2): the first level is chased in two rounds. The
+ * walks of the sampled rulers and heads stop after 2k steps, each marking the
+ * element it would have taken next; then new rulers are spawned at every such
+ * element and, at a rate of 1/4, at the elements no walk has reached, and
+ * their walks finish the list. This cuts the long stretches between sampled
+ * rulers that decide how long a chase runs. The walks of both rounds form a
+ * list, numbered and sized on the device, which the ruling-set levels rank;
+ * spacing[0] is then the first level's sampling spacing k and spacing[1..]
+ * the spacings of the levels above (0 = defaults). No element is claimed
+ * atomically and the walks do not depend on timing; results are identical to
+ * the default path. On MI355X the extra passes cost about what the shorter
+ * chase saves (slower below 2^22 elements, within a few percent from 2^22 to
+ * 2^25), so it is an option, not a default. */
 /* Tile-local contraction (Section 2.3): chains of links that stay inside a
  * tile of 4096 consecutive ids are contracted to their first element, the
  * ruling-set levels rank the contracted list, and every element then takes

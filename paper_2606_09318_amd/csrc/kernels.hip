@@ -32,6 +32,12 @@
 // between this path and the plain one (lsample, ldecide; the exact count in
 // lc_scan can still hand over to the plain path); both are enqueued and the
 // kernels of the path not taken return at once (Gate).
+//
+// Ruler spawning (Section 2.2, LR_SPAWN): the input level is chased in two
+// rounds (sp_chase1 capped at 2k steps; sp_count/scan/write spawn rulers at
+// the cap targets and among the unreached elements; sp_chase2 walks from
+// them), and all walks form the list the levels above rank (run_clevels, as
+// for the contracted list); sp_expand restores every element.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
