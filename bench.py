@@ -49,11 +49,24 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
+def code_only(text: str) -> str:
+    """Source text without comments and with whitespace collapsed, so that a
+    comment edit does not mark recorded counters as stale (string literals in
+    these files contain no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(root: str = ROOT) -> str:
+    """Hash of the code (not the comments) of the kernels and their device
+    structures: the traffic recorded in profiles/chase_traffic.json is used
+    only while it matches."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "device.hpp"):
-        with open(os.path.join(ROOT, "paper_2606_09318_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, "paper_2606_09318_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
