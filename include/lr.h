@@ -210,7 +210,8 @@ lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtyp
  * weight +1 on down arcs and -1 on up arcs gives, for every arc a, the number
  * of arcs (rank) and #down - #up (sum) from a to the end of the tour; depth,
  * preorder number and subtree size of every vertex follow from the values at
- * the tour's first arc and at the vertex's two arcs.
+ * the vertex's two arcs (those of the tour's first arc are fixed by V: rank
+ * 2V - 3, sum 1).
  *   succ  [m] uint32, m = 2(V-1): the tour as a successor array over its arcs
  *         (one list; its last arc is the terminal). Ignored when V == 1.
  *   down  [V] uint32: down[v] = id of the arc parent(v) -> v.
@@ -222,9 +223,10 @@ lr_status lr_prefix_sum_wyllie(const uint32_t* succ, const void* weight, lr_wtyp
  *         tour follows (root 0). May be NULL.
  *   size     [V] uint32 output: vertices in v's subtree (root V). May be NULL.
  * V <= 2^30. Workspace from lr_euler_tree_workspace_bytes (it holds the
- * weights, the prefix sums, the ranks and an lr_prefix_sum workspace). With
+ * weights, a (rank, sum) record per arc and an lr_prefix_sum workspace). With
  * LR_VALIDATE the call also checks that down/up name every arc exactly once
- * and that the tour is one list (LR_ERR_BAD_LIST otherwise); without it such
+ * and that the tour is one list starting with rank 2V - 3 and sum 1
+ * (LR_ERR_BAD_LIST otherwise); without it such
  * input gives unspecified outputs, never an out-of-bounds access. opts apply
  * to the inner lr_prefix_sum. */
 size_t lr_euler_tree_workspace_bytes(uint64_t V, const lr_opts* opts);

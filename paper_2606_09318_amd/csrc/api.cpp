@@ -294,7 +294,7 @@ static lr_status check_base_lds(const Plan& p) {
 
 static lr_status rank_common(const uint32_t* succ, const void* weight, int wt, bool weighted, int64_t* sum,
                              uint32_t* rank, uint32_t* root, uint64_t n, void* ws, size_t ws_bytes,
-                             const lr_opts* opts, void* stream) {
+                             const lr_opts* opts, void* stream, void* rec = nullptr) {
     PlanSet ps;
     lr_status s = make_plans(n, weighted, opts, 0, &ps);
     if (s != LR_OK) return s;
@@ -311,11 +311,21 @@ static lr_status rank_common(const uint32_t* succ, const void* weight, int wt, b
     a.rank = rank;
     a.root = root;
     a.sum = sum;
+    a.rec = rec;
     a.ws = carve(ws);
     a.stream = static_cast<hipStream_t>(stream);
     a.validate = opts && (opts->flags & LR_VALIDATE);
     a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
     return finish(run_srs(a), a, p);
+}
+
+lr_status prefix_sum_records(const uint32_t* succ, const void* weight, int wt, void* rec, uint64_t n, void* ws,
+                             size_t ws_bytes, const lr_opts* opts, void* stream) {
+    if (wt < 0 || wt > 3) return LR_ERR_INVALID_ARG;
+    if (n == 0) return LR_OK;
+    if (!succ || !rec || (wt == 0) != (weight == nullptr)) return LR_ERR_INVALID_ARG;
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    return rank_common(succ, weight, wt, true, nullptr, nullptr, nullptr, n, ws, ws_bytes, opts, stream, rec);
 }
 
 }  // namespace lr

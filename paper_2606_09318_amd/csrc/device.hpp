@@ -141,7 +141,7 @@ struct Sampler {
 // id when x is a terminal) and its value: the link weight for a non-terminal,
 // the terminal's own weight for a terminal (0 on the input level).
 // Out-of-range successors are read as terminals, so no walk leaves the array.
-template <bool W, int WT>  // WT: 0 = every link weighs 1, 1 = int32 weights, 2 = int64 weights
+template <bool W, int WT>  // WT: 0 = every link weighs 1, 1 = int32, 2 = int64, 3 = int8 weights (internal)
 struct SrcIn {
     const uint32_t* succ;
     const void* weight;
@@ -151,6 +151,7 @@ struct SrcIn {
         const uint32_t s = succ[x];
         int64_t w = 1;
         if constexpr (WT == 1) w = static_cast<const int32_t*>(weight)[x];
+        if constexpr (WT == 3) w = static_cast<const int8_t*>(weight)[x];
         if constexpr (WT == 2) w = static_cast<const int64_t*>(weight)[x];
         const bool t = (s == x) | (s >= m);
         nxt = t ? (TERM | x) : s;
@@ -163,6 +164,7 @@ struct SrcIn {
 template <int WT> struct PairRec;
 template <> struct alignas(8) PairRec<1> { uint32_t s; int32_t w; };
 template <> struct alignas(16) PairRec<2> { uint32_t s, pad; int64_t w; };
+template <> struct alignas(8) PairRec<3> { uint32_t s; int32_t w; };  // int8 weights, widened
 
 template <int WT>
 struct SrcPair {

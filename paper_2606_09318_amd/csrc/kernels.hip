@@ -1044,6 +1044,7 @@ __global__ __launch_bounds__(TPB) void k_pair(const uint32_t* __restrict__ succ,
         PairRec<WT> r{};
         r.s = succ[i];
         if constexpr (WT == 1) r.w = static_cast<const int32_t*>(weight)[i];
+        if constexpr (WT == 3) r.w = static_cast<const int8_t*>(weight)[i];
         if constexpr (WT == 2) r.w = static_cast<const int64_t*>(weight)[i];
         out[i] = r;
     }
@@ -1256,6 +1257,7 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
             if (i < len) {
                 sv[j] = succ[b + i];
                 if constexpr (WT == 1) wv[j] = static_cast<const int32_t*>(weight)[b + i];
+                if constexpr (WT == 3) wv[j] = static_cast<const int8_t*>(weight)[b + i];
                 if constexpr (WT == 2) wv[j] = static_cast<const int64_t*>(weight)[b + i];
                 PD[i] = i;
                 if constexpr (W) WS[i] = 0;
@@ -2487,6 +2489,15 @@ hipError_t run_srs(const RunArgs& a) {
     if (!p.weighted) {  // rank is required
         if (a.root) return run_any_t<false, 0>(a, OutUser<false, true, true>{a.rank, a.root, nullptr});
         return run_any_t<false, 0>(a, OutUser<false, true, false>{a.rank, nullptr, nullptr});
+    }
+    if (a.rec) {  // records for an internal caller
+        OutLvl<true> out{reinterpret_cast<typename Lay<true>::Res*>(a.rec)};
+        switch (a.wt) {
+            case 1: return run_any_t<true, 1>(a, out);
+            case 2: return run_any_t<true, 2>(a, out);
+            case 3: return run_any_t<true, 3>(a, out);
+            default: return run_any_t<true, 0>(a, out);
+        }
     }
     switch (a.wt) {  // the sum is required; rank and root are optional
         case 1: return run_weighted<1>(a);

@@ -30,12 +30,21 @@ struct RunArgs {
     hipStream_t stream = nullptr;
     bool validate = false;
     hipEvent_t* ev = nullptr;         // EV_COUNT events to record, or null
+    void* rec = nullptr;              // weighted, internal callers: one (rank, root, sum) record per
+                                      // element (Lay<true>::Res) instead of the separate arrays
     bool prologue = true;             // run validation and the head-sum pass (false: the caller did)
     Gate gate{};                      // device-side path selection (null: always run)
 };
 
 // Sparse ruling-set ranking over the whole plan. Enqueues only.
 hipError_t run_srs(const RunArgs& a);
+
+// Weighted ranking whose results land as one 16-byte (rank, root, sum)
+// record per element at `rec` (the root field is not filled: NONE). Same
+// arguments, workspace and checks as lr_prefix_sum otherwise, and one more
+// weight type: wt = 3 for int8 weights.
+lr_status prefix_sum_records(const uint32_t* succ, const void* weight, int wt, void* rec, uint64_t n, void* ws,
+                             size_t ws_bytes, const lr_opts* opts, void* stream);
 
 // Wyllie pointer doubling baseline; ws holds two ping-pong record arrays.
 hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted);

@@ -7,17 +7,23 @@
 // and -1 on up arcs, one weighted ranking of the tour gives for every arc a
 //   rank(a) = #down + #up  and  sum(a) = #down - #up
 // over the arcs from a to the end of the tour (the last arc, the terminal,
-// excluded). With h the tour's first arc (rank m - 1) and d, u the down and up
-// arcs of a non-root vertex v:
+// excluded). With h the tour's first arc and d, u the down and up arcs of a
+// non-root vertex v:
 //   depth(v)    = sum(h) - sum(d) + 1            (down arcs minus up arcs before v, plus its own)
 //   preorder(v) = #down arcs before d + 1 = (rank(h) + sum(h)) / 2 - (rank(d) + sum(d)) / 2 + 1
 //   size(v)     = (rank(d) - rank(u) + 1) / 2    (the arcs from d to u enter and leave the subtree)
-// and the root has depth 0, preorder 0, size V.
+// and the root has depth 0, preorder 0, size V. The tour of a tree with V
+// vertices has m = 2(V - 1) arcs and ends on an up arc into the root, so
+// rank(h) = m - 1 and sum(h) = (V - 1) - (V - 2) = 1 are known in advance:
+//   depth(v) = 2 - sum(d),  preorder(v) = V - (rank(d) + sum(d)) / 2.
+// The prefix sum writes rank and sum of an arc as one 16-byte record, so a
+// vertex costs two random record gathers (d and u).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
 
+#include "device.hpp"
 #include "lr.h"
 #include "runner.hpp"
 
@@ -30,10 +36,11 @@ static inline size_t tree_align(size_t v) { return (v + 255) / 256 * 256; }
 
 // w[down(v)] = +1 and w[up(v)] = -1 for every non-root vertex (w cleared to 0
 // before, so an arc that no vertex names keeps weight 0); arc ids out of
-// range set the error word instead.
+// range set the error word instead. One byte per arc: the random stores land
+// in an array a quarter the size of an int32 one.
 __global__ __launch_bounds__(TREE_TPB) void k_tree_weights(const uint32_t* __restrict__ down,
                                                            const uint32_t* __restrict__ up, uint32_t V,
-                                                           uint32_t root, uint32_t m, int32_t* __restrict__ w,
+                                                           uint32_t root, uint32_t m, int8_t* __restrict__ w,
                                                            uint32_t* err) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
@@ -47,7 +54,7 @@ __global__ __launch_bounds__(TREE_TPB) void k_tree_weights(const uint32_t* __res
 
 // Clears the weights, the head arc and the error word (a kernel, not a
 // memset, so the sequence can be captured into a graph).
-__global__ __launch_bounds__(TREE_TPB) void k_tree_clear(int32_t* __restrict__ w, uint32_t m,
+__global__ __launch_bounds__(TREE_TPB) void k_tree_clear(int8_t* __restrict__ w, uint32_t m,
                                                          uint32_t* __restrict__ ctl) {
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,44 +62,50 @@ __global__ __launch_bounds__(TREE_TPB) void k_tree_clear(int32_t* __restrict__ w
         ctl[0] = TREE_NONE;  // head arc
         ctl[1] = 0;          // error bits
     }
-    for (uint32_t a = g; a < m; a += stride) w[a] = 0;
+    const uint32_t words = (m + 3) / 4;  // w is 256-byte aligned with room for whole words
+    for (uint32_t i = g; i < words; i += stride) reinterpret_cast<uint32_t*>(w)[i] = 0;
 }
 
 // Validation: every arc must carry +1 or -1 (each named by exactly one vertex).
-__global__ __launch_bounds__(TREE_TPB) void k_tree_cover(const int32_t* __restrict__ w, uint32_t m, uint32_t* err) {
+__global__ __launch_bounds__(TREE_TPB) void k_tree_cover(const int8_t* __restrict__ w, uint32_t m, uint32_t* err) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride)
         if (w[a] == 0) atomicOr(err, 2u);
 }
 
-// The tour's first arc: the only one with rank m - 1.
-__global__ __launch_bounds__(TREE_TPB) void k_tree_head(const uint32_t* __restrict__ rank, uint32_t m,
-                                                        uint32_t* head) {
+using TRes = Lay<true>::Res;  // (rank, root, sum) of one arc
+
+// Validation: the tour is one list whose first arc has rank m - 1 and sum 1.
+__global__ __launch_bounds__(TREE_TPB) void k_tree_head(const TRes* __restrict__ rec, uint32_t m, uint32_t* head,
+                                                        uint32_t* err) {
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride)
-        if (rank[a] == m - 1) *head = a;
+    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < m; a += stride) {
+        const TRes r = rec[a];
+        if (r.c == m - 1) {
+            *head = a;
+            if (r.s != 1) atomicOr(err, 4u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(TREE_TPB) void k_tree_headless(const uint32_t* head, uint32_t* err) {
+    if (threadIdx.x == 0 && *head == TREE_NONE) atomicOr(err, 4u);  // no arc has rank m - 1
 }
 
 __global__ __launch_bounds__(TREE_TPB) void k_tree_vertex(const uint32_t* __restrict__ down,
                                                           const uint32_t* __restrict__ up, uint32_t V, uint32_t root,
-                                                          uint32_t m, const uint32_t* __restrict__ rank,
-                                                          const int64_t* __restrict__ sum,
-                                                          const uint32_t* __restrict__ head, uint32_t* depth,
-                                                          uint32_t* preorder, uint32_t* size, uint32_t* err) {
-    const uint32_t h = *head;
-    const bool ok_h = h < m;
-    const int64_t rh = ok_h ? (int64_t)rank[h] : 0, sh = ok_h ? sum[h] : 0;
-    if (!ok_h && blockIdx.x == 0 && threadIdx.x == 0 && m) atomicOr(err, 4u);  // the tour is not one list
+                                                          uint32_t m, const TRes* __restrict__ rec, uint32_t* depth,
+                                                          uint32_t* preorder, uint32_t* size) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
         uint32_t dep = 0, pre = 0, sz = V;
         if (v != root) {
             const uint32_t d = down[v], u = up[v];
-            if (ok_h && d < m && u < m) {
-                const int64_t rd = rank[d], sd = sum[d], ru = rank[u];
-                dep = (uint32_t)(sh - sd + 1);
-                pre = (uint32_t)((rh + sh) / 2 - (rd + sd) / 2 + 1);
-                sz = (uint32_t)((rd - ru + 1) / 2);
+            if (d < m && u < m) {
+                const TRes rd = rec[d], ru = rec[u];
+                dep = (uint32_t)(2 - rd.s);
+                pre = (uint32_t)((int64_t)V - ((int64_t)rd.c + rd.s) / 2);
+                sz = (uint32_t)(((int64_t)rd.c - (int64_t)ru.c + 1) / 2);
             } else {
                 dep = pre = sz = TREE_NONE;
             }
@@ -110,18 +123,16 @@ static uint32_t tree_grid(uint64_t work) {
 }
 
 struct TreeLayout {
-    size_t w = 0, sum = 0, rank = 0, ctl = 0, inner = 0, inner_bytes = 0, total = 0;
+    size_t w = 0, rec = 0, ctl = 0, inner = 0, inner_bytes = 0, total = 0;
 };
 
 static bool tree_layout(uint64_t V, const lr_opts* opts, TreeLayout* t) {
     const uint64_t m = V >= 2 ? 2 * (V - 1) : 0;
     size_t off = 0;
     t->w = off;
-    off += tree_align(m * 4 + 4);
-    t->sum = off;
-    off += tree_align(m * 8 + 8);
-    t->rank = off;
-    off += tree_align(m * 4 + 4);
+    off += tree_align(m + 4);
+    t->rec = off;
+    off += tree_align(m * sizeof(TRes) + sizeof(TRes));
     t->ctl = off;  // head arc, error word
     off += 256;
     t->inner = off;
@@ -155,15 +166,14 @@ extern "C" lr_status lr_euler_tree(const uint32_t* succ, const uint32_t* down, c
     if (!ws || ws_bytes < t.total) return LR_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* w0 = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) / 256 * 256);
-    int32_t* w = reinterpret_cast<int32_t*>(w0 + t.w);
-    int64_t* sum = reinterpret_cast<int64_t*>(w0 + t.sum);
-    uint32_t* rank = reinterpret_cast<uint32_t*>(w0 + t.rank);
+    int8_t* w = reinterpret_cast<int8_t*>(w0 + t.w);
+    TRes* rec = reinterpret_cast<TRes*>(w0 + t.rec);
     uint32_t* head = reinterpret_cast<uint32_t*>(w0 + t.ctl);
     uint32_t* err = head + 1;
     const bool validate = opts && (opts->flags & LR_VALIDATE);
     lr_opts inner = opts ? *opts : lr_opts{};
     inner.flags &= ~(uint32_t)LR_PROFILE;
-    hipLaunchKernelGGL(k_tree_clear, dim3(tree_grid(m)), dim3(TREE_TPB), 0, st, w, (uint32_t)m, head);
+    hipLaunchKernelGGL(k_tree_clear, dim3(tree_grid(m / 4 + 1)), dim3(TREE_TPB), 0, st, w, (uint32_t)m, head);
     if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
     if (m) {
         hipLaunchKernelGGL(k_tree_weights, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up, (uint32_t)V, root,
@@ -171,14 +181,16 @@ extern "C" lr_status lr_euler_tree(const uint32_t* succ, const uint32_t* down, c
         if (validate)
             hipLaunchKernelGGL(k_tree_cover, dim3(tree_grid(m)), dim3(TREE_TPB), 0, st, w, (uint32_t)m, err);
         if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
-        const lr_status s = lr_prefix_sum(succ, w, LR_W_I32, sum, rank, nullptr, m, w0 + t.inner, t.inner_bytes,
-                                          &inner, stream);
+        const lr_status s = prefix_sum_records(succ, w, 3, rec, m, w0 + t.inner, t.inner_bytes, &inner, stream);
         if (s != LR_OK) return s;
-        hipLaunchKernelGGL(k_tree_head, dim3(tree_grid(m)), dim3(TREE_TPB), 0, st, rank, (uint32_t)m, head);
-        if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
+        if (validate) {
+            hipLaunchKernelGGL(k_tree_head, dim3(tree_grid(m)), dim3(TREE_TPB), 0, st, rec, (uint32_t)m, head, err);
+            hipLaunchKernelGGL(k_tree_headless, dim3(1), dim3(64), 0, st, head, err);
+            if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
+        }
     }
     hipLaunchKernelGGL(k_tree_vertex, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up, (uint32_t)V, root,
-                       (uint32_t)m, rank, sum, head, depth, preorder, size, err);
+                       (uint32_t)m, rec, depth, preorder, size);
     if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
     if (validate) {
         uint32_t e = 0;
