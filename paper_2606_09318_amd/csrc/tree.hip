@@ -34,10 +34,13 @@ constexpr uint32_t TREE_NONE = 0xffffffffu;
 
 static inline size_t tree_align(size_t v) { return (v + 255) / 256 * 256; }
 
-// w[down(v)] = +1 and w[up(v)] = -1 for every non-root vertex (w cleared to 0
-// before, so an arc that no vertex names keeps weight 0); arc ids out of
-// range set the error word instead. One byte per arc: the random stores land
-// in an array a quarter the size of an int32 one.
+// w[down(v)] = +1 for every non-root vertex. Validating (BOTH): w was
+// cleared to 0 and w[up(v)] = -1 is stored too, so an arc that no vertex
+// names keeps weight 0 and arc ids out of range set the error word.
+// Otherwise w was cleared to -1, every arc not named as a down arc is an up
+// arc, and half the random stores are saved. One byte per arc: the stores
+// land in an array a quarter the size of an int32 one.
+template <bool BOTH>
 __global__ __launch_bounds__(TREE_TPB) void k_tree_weights(const uint32_t* __restrict__ down,
                                                            const uint32_t* __restrict__ up, uint32_t V,
                                                            uint32_t root, uint32_t m, int8_t* __restrict__ w,
@@ -45,16 +48,19 @@ __global__ __launch_bounds__(TREE_TPB) void k_tree_weights(const uint32_t* __res
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
         if (v == root) continue;
-        const uint32_t d = down[v], u = up[v];
+        const uint32_t d = down[v];
         if (d < m) w[d] = 1;
-        if (u < m) w[u] = -1;
-        if (d >= m || u >= m || d == u) atomicOr(err, 1u);
+        if constexpr (BOTH) {
+            const uint32_t u = up[v];
+            if (u < m) w[u] = -1;
+            if (d >= m || u >= m || d == u) atomicOr(err, 1u);
+        }
     }
 }
 
-// Clears the weights, the head arc and the error word (a kernel, not a
-// memset, so the sequence can be captured into a graph).
-__global__ __launch_bounds__(TREE_TPB) void k_tree_clear(int8_t* __restrict__ w, uint32_t m,
+// Sets every weight byte (0 or -1), the head arc and the error word (a
+// kernel, not a memset, so the sequence can be captured into a graph).
+__global__ __launch_bounds__(TREE_TPB) void k_tree_clear(int8_t* __restrict__ w, uint32_t m, uint32_t fill,
                                                          uint32_t* __restrict__ ctl) {
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(TREE_TPB) void k_tree_clear(int8_t* __restrict__ w,
         ctl[1] = 0;          // error bits
     }
     const uint32_t words = (m + 3) / 4;  // w is 256-byte aligned with room for whole words
-    for (uint32_t i = g; i < words; i += stride) reinterpret_cast<uint32_t*>(w)[i] = 0;
+    for (uint32_t i = g; i < words; i += stride) reinterpret_cast<uint32_t*>(w)[i] = fill;
 }
 
 // Validation: every arc must carry +1 or -1 (each named by exactly one vertex).
@@ -173,11 +179,16 @@ extern "C" lr_status lr_euler_tree(const uint32_t* succ, const uint32_t* down, c
     const bool validate = opts && (opts->flags & LR_VALIDATE);
     lr_opts inner = opts ? *opts : lr_opts{};
     inner.flags &= ~(uint32_t)LR_PROFILE;
-    hipLaunchKernelGGL(k_tree_clear, dim3(tree_grid(m / 4 + 1)), dim3(TREE_TPB), 0, st, w, (uint32_t)m, head);
+    hipLaunchKernelGGL(k_tree_clear, dim3(tree_grid(m / 4 + 1)), dim3(TREE_TPB), 0, st, w, (uint32_t)m,
+                       validate ? 0u : 0xffffffffu, head);
     if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
     if (m) {
-        hipLaunchKernelGGL(k_tree_weights, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up, (uint32_t)V, root,
-                           (uint32_t)m, w, err);
+        if (validate)
+            hipLaunchKernelGGL(k_tree_weights<true>, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up,
+                               (uint32_t)V, root, (uint32_t)m, w, err);
+        else
+            hipLaunchKernelGGL(k_tree_weights<false>, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up,
+                               (uint32_t)V, root, (uint32_t)m, w, err);
         if (validate)
             hipLaunchKernelGGL(k_tree_cover, dim3(tree_grid(m)), dim3(TREE_TPB), 0, st, w, (uint32_t)m, err);
         if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;

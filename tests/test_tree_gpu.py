@@ -95,7 +95,11 @@ def test_validate():
     o = lr.make_opts(flags=lr.LR_VALIDATE)
     parent = workloads.recursive_tree(20000, seed=10)
     E = workloads.tour_of(parent, seed=10)
-    assert gpu_tree(E, 0, o)[0] == lr.LR_OK
+    st, outs = gpu_tree(E, 0, o)               # validating: both weights stored, values as without
+    assert st == lr.LR_OK
+    _, ed, ep, ez = oracle.tree(parent, 0)
+    for got, exp in zip(outs, (ed, ep, ez)):
+        assert np.array_equal(got, exp)
     bad = workloads.EulerInput(E.succ, E.weight, parent, E.down_arc.copy(), E.up_arc, None)
     bad.down_arc[5] = E.down_arc[6]                       # one arc named twice, one arc by nobody
     assert gpu_tree(bad, 0, o)[0] == lr.LR_ERR_BAD_LIST
