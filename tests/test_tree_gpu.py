@@ -58,7 +58,7 @@ def test_path_star_caterpillar():
     check(cat)
 
 
-@pytest.mark.parametrize("flags", [lr.LR_LOCAL, lr.LR_NO_LOCAL])
+@pytest.mark.parametrize("flags", [lr.LR_LOCAL, lr.LR_NO_LOCAL, lr.LR_SPAWN, lr.LR_NO_LOCAL | lr.LR_VISIT_LOG])
 def test_modes_and_forced_levels(flags):
     parent = workloads.recursive_tree(300000, seed=8)
     check(parent, opts=lr.make_opts(flags=flags))
