@@ -899,19 +899,36 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
     const uint32_t nw = S + ctrl->lv[0].H;
     const uint32_t tiles = (used + T - 1) / T;
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+        uint32_t xs[PER], rs[PER], ts[PER], bs[PER], wl[PER];
         int64_t ss[PER];
+        typename L::Val offs[PER];
+        // the three (four) fields of every record in one round of loads: a
+        // padding record (x = NONE) is read like the others, it shares their lines
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            xs[j] = (i < used) ? lg.x[i] : NONE;
+            xs[j] = NONE;
+            wl[j] = NONE;
+            if (i < used) {
+                xs[j] = lg.x[i];
+                wl[j] = lg.w[i];
+                offs[j].c = lg.c[i];
+                if constexpr (W) offs[j].s = lg.s[i];
+            }
+        }
+        // then every walk result (the records of a walk sit together, so these
+        // mostly hit the caches), all issued before any is used
+        typename L::Res bres[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (xs[j] < n && wl[j] < nw) bres[j] = res[wl[j]];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
             if (xs[j] < n) {
-                const uint32_t w = lg.w[i];
-                typename L::Val off;
-                off.c = lg.c[i];
-                if constexpr (W) off.s = lg.s[i];
+                const uint32_t w = wl[j];
+                const typename L::Val off = offs[j];
                 if (w < nw) {
-                    const typename L::Res b = res[w];
+                    const typename L::Res b = bres[j];
                     const typename L::Val v = L::sub(L::val(b), off);
                     rs[j] = v.c;
                     ts[j] = b.root;
@@ -963,22 +980,28 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
         const uint32_t lim = fill1 ? min(n, (c << s1) + fill1[c]) : n;
         uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
         int64_t ss[PER];
+        // every field of the tile's records in one round of loads (the value
+        // loads do not wait for the element id)
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            xs[j] = (i < lim) ? in.x[i] : NONE;
-            if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
-                atomicOr(&ctrl->err, 64u);
-                xs[j] = NONE;
-            }
-            if (xs[j] < n) {
+            xs[j] = NONE;
+            if (i < lim) {
+                xs[j] = in.x[i];
                 if constexpr (VALS) {
                     rs[j] = in.r[i];
                     if constexpr (ROOT) ts[j] = in.t[i];
                     if constexpr (W) ss[j] = in.s[i];
                 }
-                bs[j] = (xs[j] >> s2) - c * fan;
             }
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
+                atomicOr(&ctrl->err, 64u);
+                xs[j] = NONE;
+            }
+            if (xs[j] < n) bs[j] = (xs[j] >> s2) - c * fan;
         }
         place_tile<W, ROOT, PER, VALS>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
     }
@@ -1012,12 +1035,30 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, C
         }
         if (check && t == 0 && fill2[f] != len) atomicOr(&ctrl->err, 128u);
         __syncthreads();
-        for (uint32_t i = t; i < len; i += place_tpb(ROOT)) {
-            const uint32_t k = in.x[base + i] - base;
-            if (k < len) {
-                lr[k] = in.r[base + i];
-                if constexpr (ROOT) lt[k] = in.t[base + i];
-                if constexpr (W) ls[k] = in.s[base + i];
+        // four records per lane per round, every field loaded before any LDS
+        // store (the value loads do not wait for the element id)
+        constexpr int U = 4;
+        for (uint32_t i0 = t; i0 < len; i0 += U * place_tpb(ROOT)) {
+            uint32_t kk[U], rv[U], tv[U];
+            int64_t sv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t i = i0 + u * place_tpb(ROOT);
+                kk[u] = NONE;
+                if (i < len) {
+                    kk[u] = in.x[base + i] - base;
+                    rv[u] = in.r[base + i];
+                    if constexpr (ROOT) tv[u] = in.t[base + i];
+                    if constexpr (W) sv[u] = in.s[base + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (kk[u] < len) {
+                    lr[kk[u]] = rv[u];
+                    if constexpr (ROOT) lt[kk[u]] = tv[u];
+                    if constexpr (W) ls[kk[u]] = sv[u];
+                }
             }
         }
         __syncthreads();
@@ -1097,9 +1138,16 @@ __global__ __launch_bounds__(place_tpb(false)) void k_mark3(const uint32_t* __re
         __syncthreads();
         const uint32_t cnt = min(fill2[f], len);
         uint8_t* mb = reinterpret_cast<uint8_t*>(mk);
-        for (uint32_t i = threadIdx.x; i < cnt; i += TPB_) {
-            const uint32_t k = tx[base + i] - base;
-            if (k < len) mb[k] = 1;
+        for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += 4 * TPB_) {  // four loads in flight per lane
+            uint32_t kk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = i0 + u * TPB_;
+                kk[u] = (i < cnt) ? tx[base + i] - base : NONE;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (kk[u] < len) mb[kk[u]] = 1;
         }
         __syncthreads();
         if ((len & 3) == 0) {
