@@ -898,30 +898,44 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
     const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
     const uint32_t nw = S + ctrl->lv[0].H;
     const uint32_t tiles = (used + T - 1) / T;
+    // The fields of every record of a tile in one round of loads (a padding
+    // record, x = NONE, is read like the others: it shares their lines). The
+    // next tile's round is issued before this tile is grouped: the grouping's
+    // barriers wait for LDS only, so those loads stay in flight meanwhile.
+    uint32_t nx[PER], nwl[PER];
+    typename L::Val noff[PER];
+    auto load_tile = [&](uint32_t tile) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
+            nx[j] = NONE;
+            nwl[j] = NONE;
+            if (i < used) {
+                nx[j] = lg.x[i];
+                nwl[j] = lg.w[i];
+                noff[j].c = lg.c[i];
+                if constexpr (W) noff[j].s = lg.s[i];
+            }
+        }
+    };
+    if (blockIdx.x < tiles) load_tile(blockIdx.x);
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         uint32_t xs[PER], rs[PER], ts[PER], bs[PER], wl[PER];
         int64_t ss[PER];
         typename L::Val offs[PER];
-        // the three (four) fields of every record in one round of loads: a
-        // padding record (x = NONE) is read like the others, it shares their lines
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            xs[j] = NONE;
-            wl[j] = NONE;
-            if (i < used) {
-                xs[j] = lg.x[i];
-                wl[j] = lg.w[i];
-                offs[j].c = lg.c[i];
-                if constexpr (W) offs[j].s = lg.s[i];
-            }
+            xs[j] = nx[j];
+            wl[j] = nwl[j];
+            offs[j] = noff[j];
         }
-        // then every walk result (the records of a walk sit together, so these
+        // every walk result (the records of a walk sit together, so these
         // mostly hit the caches), all issued before any is used
         typename L::Res bres[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j)
             if (xs[j] < n && wl[j] < nw) bres[j] = res[wl[j]];
+        if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             if (xs[j] < n) {
