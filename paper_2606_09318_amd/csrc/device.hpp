@@ -37,7 +37,7 @@ struct Ctrl {
                                             // device (the contracted list of tile-local contraction)
     uint32_t mode;                          // automatic contraction: 0 plain path, 1 tile-local contraction
     uint32_t multi;                         // plain path with more than one list: predecessor marks needed
-    uint32_t spn;                           // ruler spawning: walk ids handed to spawned rulers
+    uint32_t spn;                           // ruler spawning: number of spawned rulers
     uint32_t pad[30];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");

@@ -2133,7 +2133,7 @@ static hipError_t run_validate(const RunArgs& a, const Plan& p, uint32_t n) {
 }
 
 // One streaming pass over the input: terminal count, head sum (the one-list
-// shortcut) and local links; with auto_cap > 0 it also picks the path.
+// shortcut); the plain path's gate (mode 0) when the choice is automatic.
 static hipError_t run_headsum(const RunArgs& a, const Plan& p, Gate g) {
     const uint32_t n = (uint32_t)p.m[0];
     hipStream_t st = a.stream;
