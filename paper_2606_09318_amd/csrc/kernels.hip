@@ -980,35 +980,57 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
     const uint32_t tpc = (1u << s1) / T;                        // tiles per coarse range
     const bool xcd = LR_XCD_GROUPS && (gridDim.x % 8) == 0;
     const uint32_t lane8 = blockIdx.x % 8, step = xcd ? gridDim.x / 8 : gridDim.x;
-    for (uint32_t q = xcd ? blockIdx.x / 8 : blockIdx.x;; q += step) {
-        uint32_t tile = q;
-        if (xcd) {
+    // the workgroup's tiles in order: q advances by step; NONE when done
+    uint32_t q = xcd ? blockIdx.x / 8 : blockIdx.x;
+    auto next_tile = [&]() -> uint32_t {
+        for (;; q += step) {
+            if (!xcd) return q < tiles ? q : NONE;
             const uint32_t c = lane8 + 8 * (q / tpc);
-            tile = c * tpc + q % tpc;
-            if (c * tpc >= tiles) break;
-            if (tile >= tiles) continue;
-        } else if (tile >= tiles) {
-            break;
+            if (c * tpc >= tiles) return NONE;
+            const uint32_t tile = c * tpc + q % tpc;
+            if (tile < tiles) return tile;
         }
-        const uint32_t c = (tile * T) >> s1;  // coarse range of this tile (T divides 2^s1)
+    };
+    // every field of a tile's records in one round of loads (the value loads
+    // do not wait for the element id); the next tile's round is issued while
+    // this tile is grouped (the grouping's barriers wait for LDS only)
+    uint32_t nx[PER], nr[PER], nt[PER];
+    int64_t ns[PER];
+    auto load_tile = [&](uint32_t tile) {
+        const uint32_t c = (tile * T) >> s1;
         const uint32_t lim = fill1 ? min(n, (c << s1) + fill1[c]) : n;
-        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
-        int64_t ss[PER];
-        // every field of the tile's records in one round of loads (the value
-        // loads do not wait for the element id)
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            xs[j] = NONE;
+            nx[j] = NONE;
             if (i < lim) {
-                xs[j] = in.x[i];
+                nx[j] = in.x[i];
                 if constexpr (VALS) {
-                    rs[j] = in.r[i];
-                    if constexpr (ROOT) ts[j] = in.t[i];
-                    if constexpr (W) ss[j] = in.s[i];
+                    nr[j] = in.r[i];
+                    if constexpr (ROOT) nt[j] = in.t[i];
+                    if constexpr (W) ns[j] = in.s[i];
                 }
             }
         }
+    };
+    uint32_t tile = next_tile();
+    if (tile != NONE) load_tile(tile);
+    while (tile != NONE) {
+        const uint32_t c = (tile * T) >> s1;  // coarse range of this tile (T divides 2^s1)
+        uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
+        int64_t ss[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            xs[j] = nx[j];
+            if constexpr (VALS) {
+                rs[j] = nr[j];
+                if constexpr (ROOT) ts[j] = nt[j];
+                if constexpr (W) ss[j] = ns[j];
+            }
+        }
+        q += step;
+        const uint32_t nxt_tile = next_tile();
+        if (nxt_tile != NONE) load_tile(nxt_tile);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             if (xs[j] < n && (xs[j] >> s1) != c) {  // stale record: the input is not a forest
@@ -1018,6 +1040,7 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
             if (xs[j] < n) bs[j] = (xs[j] >> s2) - c * fan;
         }
         place_tile<W, ROOT, PER, VALS>(xs, rs, ts, ss, bs, fan, s2, c * fan, n, fill2, out, ctrl, lds);
+        tile = nxt_tile;
     }
 }
 
@@ -1121,16 +1144,28 @@ __global__ __launch_bounds__(place_tpb(false)) void k_mark1(const uint32_t* __re
     constexpr int TPB_ = place_tpb(false);
     constexpr uint32_t T = PER * TPB_;
     const uint32_t tiles = (n + T - 1) / T;
+    // the next tile's successors are loaded while this tile is grouped (the
+    // grouping's barriers wait for LDS only)
+    uint32_t ns[PER];
+    auto load_tile = [&](uint32_t tile) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
+            ns[j] = (i < n) ? succ[i] : NONE;
+        }
+    };
+    if (blockIdx.x < tiles) load_tile(blockIdx.x);
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
         int64_t ss[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            const uint32_t s = (i < n) ? succ[i] : NONE;
+            const uint32_t s = ns[j];
             xs[j] = (s != i && s < n) ? s : NONE;  // the target of a link
             bs[j] = xs[j] >> s1;
         }
+        if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);
         place_tile<false, false, PER, false>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
     }
 }
