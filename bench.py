@@ -59,13 +59,31 @@ def code_only(text: str) -> str:
     return " ".join(text.split())
 
 
+def chase_code(text: str) -> str:
+    """The chase kernel's definition (template line to closing brace) out of
+    the comment-free kernels source, and the launch-configuration macros."""
+    i = text.index("void k_chase(")
+    start = text.rfind("template", 0, i)
+    depth, j = 0, text.index("{", i)
+    for k in range(j, len(text)):
+        depth += {"{": 1, "}": -1}.get(text[k], 0)
+        if depth == 0:
+            break
+    macros = " ".join(m for m in text.split("#") if m.startswith(("define LR_CHASE_TPB", "define LR_XCD")))
+    return text[start:k + 1] + macros
+
+
 def kernel_source_hash(root: str = ROOT) -> str:
-    """Hash of the code (not the comments) of the kernels and their device
-    structures: the traffic recorded in profiles/chase_traffic.json is used
-    only while it matches."""
+    """Hash of the code (not the comments) of the level-0 chase kernel and the
+    headers it builds on (values, sources, sampler, plan constants): the
+    traffic recorded in profiles/chase_traffic.json is used only while it
+    matches."""
+    csrc = os.path.join(root, "paper_2606_09318_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.hpp"):
-        with open(os.path.join(root, "paper_2606_09318_amd", "csrc", f), encoding="utf-8") as fh:
+    with open(os.path.join(csrc, "kernels.hip"), encoding="utf-8") as fh:
+        h.update(chase_code(code_only(fh.read())).encode())
+    for f in ("device.hpp", "plan.hpp"):
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
             h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
