@@ -56,6 +56,10 @@ constexpr int CHASE_TPB = LR_CHASE_TPB;
 constexpr int BASE_TPB = 1024;
 constexpr int BASE_PER = BASE_MAX_LIMIT / BASE_TPB;  // 16 elements per lane
 constexpr int EXPAND_CH = 8;                         // elements per lane per wave tile
+#ifndef LR_CHASE_POOL
+#define LR_CHASE_POOL 2   // sixteenths of a level's walks handed out from a shared pool at the end
+#endif
+constexpr uint32_t CHASE_GRAB = 64;  // walks a wavefront takes from the pool at a time
 #ifndef LR_XCD_GROUPS
 #define LR_XCD_GROUPS 1   // second grouping pass: the tiles of one coarse range on one XCD
 #endif
@@ -464,14 +468,21 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
         off[k] = L::zero();
     }
     // Each wavefront owns a contiguous range of walk ids and refills its lanes
-    // from it: walk lengths are geometric with mean k, so a few hundred walks
-    // per wavefront already balance the work, and no queue is shared.
+    // from it, so no queue is contended while the chip is busy. In LOG mode
+    // (level 0 of large inputs, hundreds of walks per wavefront) the last
+    // LR_CHASE_POOL sixteenths of the walk ids form a pool instead: a
+    // wavefront done with its own range takes CHASE_GRAB of them at a time
+    // with one atomic, so the wavefronts finish closer together. On the small
+    // upper levels every wavefront would reach the pool at once, and the
+    // contended counter costs more than the balance gains.
     const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t per = total / nwave + 1;
-    const uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, total);
-    uint32_t cursor = (uint32_t)min<uint64_t>((uint64_t)gwave * per, total);
-    bool exhausted = cursor >= whi;
+    const uint32_t pool16 = LOG ? LR_CHASE_POOL : 0u;
+    const uint32_t own = (uint32_t)((uint64_t)total * (16u - pool16) / 16u);
+    const uint32_t per = own / nwave + 1;
+    uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, own);
+    uint32_t cursor = (uint32_t)min<uint64_t>((uint64_t)gwave * per, own);
+    bool exhausted = false;
     uint32_t cbase = 0, cfill = LOG_CHUNK;  // visit-log chunk held by this wavefront (LOG mode)
     bool have = false, dead = false;
     for (;;) {
@@ -484,11 +495,23 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
             nidle += __popcll(idle[k]);
             all_idle &= idle[k] == ~0ull;
         }
+        const bool want = nidle >= refill || all_idle;
+        if (!exhausted && want && cursor >= whi && own >= total) exhausted = true;  // no pool
+        if (!exhausted && want && cursor >= whi) {  // own range (or last grab) used up: the pool
+            uint32_t g = 0;
+            if (lane == 0) g = atomicAdd(&ctrl->lv[lvl].q, CHASE_GRAB);
+            g = __shfl(g, 0);
+            if ((uint64_t)own + g < total) {
+                cursor = own + g;
+                whi = (uint32_t)min<uint64_t>((uint64_t)cursor + CHASE_GRAB, total);
+            } else {
+                exhausted = true;
+            }
+        }
         if (all_idle && exhausted) break;
-        if (!exhausted && (nidle >= refill || all_idle)) {
+        if (!exhausted && want) {
             const uint32_t base = cursor;
-            cursor += nidle;
-            if (cursor >= whi) exhausted = true;
+            cursor = min(cursor + nidle, whi);
             uint32_t acc = base;
 #pragma unroll
             for (int k = 0; k < NW; ++k) {
