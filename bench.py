@@ -73,6 +73,19 @@ def chase_code(text: str) -> str:
     return text[start:k + 1] + macros
 
 
+def library_code_hash(root: str = ROOT) -> str:
+    """Hash of the code (not the comments) of every library source: the
+    whole-call traffic recorded in profiles/chase_traffic.json is used only
+    while it matches."""
+    csrc = os.path.join(root, "paper_2606_09318_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+                h.update(code_only(fh.read()).encode())
+    return h.hexdigest()[:16]
+
+
 def kernel_source_hash(root: str = ROOT) -> str:
     """Hash of the code (not the comments) of the level-0 chase kernel and the
     headers it builds on (values, sources, sampler, plan constants): the
@@ -194,12 +207,15 @@ def main():
     chase_bytes = n * (4 + 12) + S * (8 + 1)
     achieved = chase_bytes / (chase_ms * 1e-3) / 1e9
     traffic = None
+    call_traffic = None
     tfile = os.path.join(ROOT, "profiles", "chase_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tj = json.load(fh)
         if tj.get("kernel_hash") == kernel_source_hash() and tj.get("n") == n:
             traffic = tj.get("hbm_bytes_per_launch")
+        if tj.get("call_code_hash") == library_code_hash() and tj.get("n") == n:
+            call_traffic = tj.get("call_hbm_bytes")
     roofline = {"bound": "hbm", "kernel": "k_chase (level 0)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "chase_ms": round(chase_ms, 4),
@@ -213,6 +229,13 @@ def main():
                            "resolve_and_group": round(float(ph[4]), 4),
                            "expand": round(float(ph[5]), 4), "total": round(float(ph[6]), 4)},
              "useful_bytes_gbs_whole_step": round(whole_bytes / (ms * 1e-3) / 1e9, 1),
+             # HBM bytes of one whole call from the counters (FETCH_SIZE + WRITE_SIZE over
+             # every library kernel of a rank-only call, scaled by the copy calibration;
+             # profiles/chase_traffic.json) over the timed step; null when the sources
+             # changed since the counters were taken
+             "hbm_whole_step": None if call_traffic is None else {
+                 "bytes": call_traffic, "gb_s": round(call_traffic / (ms * 1e-3) / 1e9, 1),
+                 "frac_of_peak": round(call_traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
              "plan": {"levels": plan.levels, "m": [int(plan.m[i]) for i in range(plan.levels + 1)],
                       "spacing": [int(plan.spacing[i]) for i in range(plan.levels)]},
              "generation_s": round(gen_s, 2),
