@@ -110,7 +110,7 @@ static size_t layout_levels(Plan* p, size_t off) {
         // weighted: the arrays after the first hold the interleaved (successor,
         // weight) records during the level-0 chase (16 B per element)
         p->off_fill = off;
-        off += align_up((size_t)(p->nb1 + p->nb2) * 4);
+        off += align_up((size_t)fill_words(p->nb1, p->nb2) * 4);
     }
     for (uint32_t l = 0; l < std::max(L, 1u); ++l) {
         const uint64_t ml = p->m[l];

@@ -469,15 +469,16 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
     }
     // Each wavefront owns a contiguous range of walk ids and refills its lanes
     // from it, so no queue is contended while the chip is busy. In LOG mode
-    // (level 0 of large inputs, hundreds of walks per wavefront) the last
+    // with at least 64 walks per wavefront (level 0 of large inputs) the last
     // LR_CHASE_POOL sixteenths of the walk ids form a pool instead: a
     // wavefront done with its own range takes CHASE_GRAB of them at a time
-    // with one atomic, so the wavefronts finish closer together. On the small
-    // upper levels every wavefront would reach the pool at once, and the
-    // contended counter costs more than the balance gains.
+    // with one atomic, so the wavefronts finish closer together. With few walks
+    // per wavefront (upper levels, short contracted lists) every wavefront
+    // would reach the pool at once, and the contended counter costs more than
+    // the balance gains.
     const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t pool16 = LOG ? LR_CHASE_POOL : 0u;
+    const uint32_t pool16 = (LOG && total >= 64u * nwave) ? LR_CHASE_POOL : 0u;  // many walks per wavefront
     const uint32_t own = (uint32_t)((uint64_t)total * (16u - pool16) / 16u);
     const uint32_t per = own / nwave + 1;
     uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, own);
@@ -823,12 +824,13 @@ __host__ __device__ constexpr size_t place_lds_bytes(bool weighted, bool root, u
 
 // LDS counting sort of one tile by range, then coalesced writes of each
 // range's run at [group(lo_bucket + b) + reserved, ...), space reserved with
-// one atomic per range and tile.
-template <bool W, bool ROOT, int PER, bool VALS = true>
+// one atomic per range and tile. TWO: the ranges' two-sided counters (front
+// and back, one line each), the tile taking the given side.
+template <bool W, bool ROOT, int PER, bool VALS = true, bool TWO = false>
 __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER], const uint32_t (&ts)[PER],
                            const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t shift,
                            uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
-                           Ctrl* ctrl, unsigned char* lds) {
+                           Ctrl* ctrl, unsigned char* lds, uint32_t side = 0) {
     constexpr int TPB_ = place_tpb(ROOT);
     constexpr uint32_t T = (uint32_t)PER * TPB_;
     size_t o = 0;
@@ -870,7 +872,20 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     uint32_t run = block_exscan(sum, scan_sh, &total);
     for (uint32_t b = a; b < e; ++b) {
         const uint32_t h = hist[b];
-        gbase[b] = h ? atomicAdd(&fill[lo_bucket + b], h) : 0u;
+        uint32_t g = 0;
+        if (h) {
+            if constexpr (TWO) {
+                const uint32_t r = lo_bucket + b;
+                const uint32_t old = atomicAdd(&fill[(2 * r + side) * FILL_LINE], h);
+                // the back side's run ends where the previous back run began
+                // (wraps past the range, and is caught below, on overflow)
+                const uint32_t len = (uint32_t)min((uint64_t)1 << shift, (uint64_t)n - ((uint64_t)r << shift));
+                g = side ? len - old - h : old;
+            } else {
+                g = atomicAdd(&fill[lo_bucket + b], h);
+            }
+        }
+        gbase[b] = g;
         hist[b] = run;
         run += h;
     }
@@ -979,12 +994,14 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
                 bs[j] = xs[j] >> s1;
             }
         }
-        place_tile<W, ROOT, PER>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
+        place_tile<W, ROOT, PER, true, true>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds, tile & 1u);
     }
 }
 
-// VALS = false groups element ids only; then the coarse ranges need not be
-// full and fill1 (their counts) bounds what is read.
+// fill1: the coarse ranges' two-sided counters. With values (VALS) every
+// coarse range is full, and its front and back counts must add up to its
+// length; VALS = false groups element ids only: then a coarse range need not
+// be full and its records are its front and back segments.
 template <bool W, bool ROOT, bool VALS = true>
 __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
                                                 uint32_t* __restrict__ fill2, PlaceArrays<W> out, const uint32_t* dm,
@@ -1021,12 +1038,19 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
     int64_t ns[PER];
     auto load_tile = [&](uint32_t tile) {
         const uint32_t c = (tile * T) >> s1;
-        const uint32_t lim = fill1 ? min(n, (c << s1) + fill1[c]) : n;
+        const uint32_t lo = c << s1;
+        const uint32_t len = min(1u << s1, n - lo);
+        uint32_t front = len, back_at = len;  // records at [lo, lo + front) and [lo + back_at, lo + len)
+        if constexpr (!VALS) {
+            front = fill1[2 * c * FILL_LINE];
+            const uint32_t back = fill1[(2 * c + 1) * FILL_LINE];
+            back_at = back < len ? len - back : 0u;
+        }
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
             nx[j] = NONE;
-            if (i < lim) {
+            if (i < n && (i - lo < front || i - lo >= back_at)) {
                 nx[j] = in.x[i];
                 if constexpr (VALS) {
                     nr[j] = in.r[i];
@@ -1040,6 +1064,13 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
     if (tile != NONE) load_tile(tile);
     while (tile != NONE) {
         const uint32_t c = (tile * T) >> s1;  // coarse range of this tile (T divides 2^s1)
+        if (threadIdx.x == 0 && tile % tpc == 0) {
+            // the range's two sides met exactly (more records than ids: some
+            // element was visited twice, or a target has two links)
+            const uint32_t len = min(1u << s1, n - (c << s1));
+            const uint64_t got = (uint64_t)fill1[2 * c * FILL_LINE] + fill1[(2 * c + 1) * FILL_LINE];
+            if (VALS ? got != len : got > len) atomicOr(&ctrl->err, 64u);
+        }
         uint32_t xs[PER], rs[PER], ts[PER], bs[PER];
         int64_t ss[PER];
 #pragma unroll
@@ -1189,7 +1220,7 @@ __global__ __launch_bounds__(place_tpb(false)) void k_mark1(const uint32_t* __re
             bs[j] = xs[j] >> s1;
         }
         if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);
-        place_tile<false, false, PER, false>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds);
+        place_tile<false, false, PER, false, true>(xs, rs, ts, ss, bs, nb1, s1, 0, n, fill1, out, ctrl, lds, tile & 1u);
     }
 }
 
@@ -2112,7 +2143,7 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     hipStream_t st = a.stream;
     const uint32_t n = (uint32_t)p.m[0];
     uint32_t* fill1 = reinterpret_cast<uint32_t*>(ws + p.off_fill);
-    uint32_t* fill2 = fill1 + p.nb1;
+    uint32_t* fill2 = fill1 + 2 * (size_t)p.nb1 * FILL_LINE;
     const PlaceArrays<W> P = place_arrays<W>(ws, p.off_p);
     const PlaceArrays<W> Q = place_arrays<W>(ws, p.off_log);
     constexpr uint32_t T = place_tile_records(W, ROOT);
@@ -2127,7 +2158,7 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
     LR_TRY(allow_lds(k_place2<W, ROOT>, l2));
     hipLaunchKernelGGL((k_place2<W, ROOT>), dim3(grid_for(n, T)), tpb, l2, st, P, ctrl, n, p.s1, p.s2, fill2,
-                       Q, dm, nullptr, a.gate);
+                       Q, dm, fill1, a.gate);
     LR_TRY(hipGetLastError());
     const size_t l3 = ((size_t)1 << p.s2) * (4 + (ROOT ? 4 : 0) + (W ? 8 : 0));
     LR_TRY(allow_lds(k_place3<W, ROOT, Out0>, l3));
@@ -2154,8 +2185,8 @@ static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl*
     const uint32_t n = (uint32_t)p.m[0];
     const Gate mg{&ctrl->multi, 1u};  // plain path taken and more than one list
     uint32_t* fill1 = reinterpret_cast<uint32_t*>(ws + p.off_fill);
-    uint32_t* fill2 = fill1 + p.nb1;
-    LR_TRY(fill(fill1, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, mg));
+    uint32_t* fill2 = fill1 + 2 * (size_t)p.nb1 * FILL_LINE;
+    LR_TRY(fill(fill1, fill_words(p.nb1, p.nb2) * 4, 0u, st, nullptr, mg));
     const PlaceArrays<false> P = place_arrays<false>(ws, p.off_p);
     const PlaceArrays<false> Q = place_arrays<false>(ws, p.off_log);
     constexpr uint32_t T = place_tile_records(false, false);
@@ -2285,7 +2316,7 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         if (l == 0) rec_ev(a, EV_HEADS);
         if (l == 0) {
             if (p.log0) {
-                LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
+                LR_TRY(fill(ws + p.off_fill, fill_words(p.nb1, p.nb2) * 4, 0u, st, nullptr, g));
                 if constexpr (W && WT != 0) {
                     // weighted input: one record per element, interleaved into the
                     // grouping arrays after the first (free until the placement)
@@ -2379,7 +2410,7 @@ static hipError_t run_clevels(const RunArgs& a, const Plan& p, typename Lay<W>::
         const auto* rec = (l == 0) ? lrec : reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]);
         SrcLvl<W> src{rec, (uint32_t)p.m[l]};
         if (l == 0 && p.log0) {  // a long contracted list: visit log and grouped placement, as the plain path
-            LR_TRY(fill(ws + p.off_fill, (uint64_t)(p.nb1 + p.nb2) * 4, 0u, st, nullptr, g));
+            LR_TRY(fill(ws + p.off_fill, fill_words(p.nb1, p.nb2) * 4, 0u, st, nullptr, g));
             LR_TRY((launch_chase<W, true, 1>(p, 0, src, smp, ctrl, ws, st, dm, g)));
         } else {
             LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));

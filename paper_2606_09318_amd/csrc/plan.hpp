@@ -27,6 +27,14 @@ constexpr uint64_t LOG_FORCE_MIN_N = 1ull << 16;          // smallest level 0 LR
 #define LR_PLACE_FINE_SHIFT 13
 #endif
 constexpr uint32_t PLACE_FINE_SHIFT = LR_PLACE_FINE_SHIFT;  // fine placement ranges of 8192 elements (LDS of one workgroup)
+// Grouping counters: every tile of the first pass reserves space in every
+// coarse range, so each coarse range has two counters, a front one that fills
+// the range upward and a back one that fills it downward (even tiles take the
+// front, odd tiles the back), each on a 128 B line of its own: atomics on one
+// line are serialised, and packed counters made the first pass wait on them.
+// The fine ranges' counters follow, packed (few tiles reach each of them).
+constexpr uint32_t FILL_LINE = 32;
+inline uint64_t fill_words(uint32_t nb1, uint32_t nb2) { return 2ull * nb1 * FILL_LINE + nb2; }
 constexpr uint32_t LOCAL_SHIFT = 12;         // tile-local contraction: tiles of 4096 consecutive ids
 constexpr uint32_t LOCAL_TILE = 1u << LOCAL_SHIFT;
 // automatic contraction: considered from this size on; the contracted levels
