@@ -174,6 +174,18 @@ def main():
     ok = bool(torch.equal(rank.index_select(0, order), expect))
     if not ok:
         raise SystemExit("bench: ranks do not match the closed form of the generated list")
+    # the distribution of single calls (events around each call, after the
+    # timed region): median, min and max of 10
+    call_ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        e1.synchronize()
+        call_ts.append(e0.elapsed_time(e1))
+    call_ms = {"median": round(float(np.median(call_ts)), 4), "min": round(min(call_ts), 4),
+               "max": round(max(call_ts), 4), "calls": len(call_ts)}
     # the same call with the root output as well (context; the configuration asks for ranks)
     step(True)
     torch.cuda.synchronize()
@@ -285,7 +297,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
            "config": {"workload": "single random list, n=2^28, uint32 succ (seed 2), uint32 rank output",
                       "n": n, "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "call_ms": call_ms}
     out.update(extra)
     print(json.dumps(out))
 
@@ -624,9 +636,16 @@ def cpu_baseline() -> dict:
     st, r, t, _ = oracle.rank(L.succ, want=("rank", "root"))
     dt = time.perf_counter() - t0
     assert st == 0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(n / dt / 1e9, 5), "unit": "G elements/s", "cores": 1, "kind": "oracle",
             "sample": "one random list of 2^25 elements from the same generator, one run, rank + root",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "host_cpu": model, "host_nproc": os.cpu_count(),
+            "build": "gcc -O3 -march=native"}
 
 
 if __name__ == "__main__":
