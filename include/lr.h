@@ -130,6 +130,14 @@ typedef struct lr_opts {
                                           (1 .. 64 x lane_walks); 0 = default (1) */
     uint32_t lane_walks;               /* level-0 chase: walks each lane holds at
                                           once (1 or 2); 0 = default (1) */
+    uint32_t log_off_bits;             /* visit log of up to 2^28 elements (one
+                                          64-bit record per visit: element,
+                                          walk, offset): the most bits of the
+                                          offset field, 1 .. 31; 0 = as many as
+                                          fit. A walk whose offset outgrows the
+                                          field goes on under a continuation
+                                          id; smaller values only make that
+                                          more frequent (results are the same) */
 } lr_opts;
 
 /* The plan a call will follow (host-only query, no device needed). */

@@ -31,7 +31,7 @@ class LrError(RuntimeError):
 class lr_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("base_max", ctypes.c_uint32),
                 ("spacing", ctypes.c_uint32 * LR_MAX_LEVELS), ("refill", ctypes.c_uint32),
-                ("lane_walks", ctypes.c_uint32)]
+                ("lane_walks", ctypes.c_uint32), ("log_off_bits", ctypes.c_uint32)]
 
 
 class lr_plan(ctypes.Structure):
@@ -115,9 +115,10 @@ def _stream(stream):
 
 
 def make_opts(seed: int = 0, flags: int = 0, base_max: int = 0, spacing=(), refill: int = 0,
-              lane_walks: int = 0) -> lr_opts:
+              lane_walks: int = 0, log_off_bits: int = 0) -> lr_opts:
     o = lr_opts()
     o.seed, o.flags, o.base_max, o.refill, o.lane_walks = seed, flags, base_max, refill, lane_walks
+    o.log_off_bits = log_off_bits
     for i, k in enumerate(spacing):
         o.spacing[i] = k
     return o

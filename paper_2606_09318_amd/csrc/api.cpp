@@ -57,6 +57,9 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
     uint32_t rf = (o && o->refill) ? o->refill : 1u;
     if (rf > 64 * lw) return LR_ERR_INVALID_ARG;
     p->refill = rf;
+    const uint32_t bo = (o && o->log_off_bits) ? o->log_off_bits : 31u;
+    if (bo > 31) return LR_ERR_INVALID_ARG;
+    p->bocap = bo;
     const uint64_t seed = o ? o->seed : 0;
     if (o) {
         for (int l = 0; l < LR_MAX_LEVELS && o->spacing[l]; ++l)
@@ -102,6 +105,23 @@ static size_t layout_levels(Plan* p, size_t off) {
         for (int i = 0; i < arrays; ++i) {
             p->off_log[i] = off;
             off += align_up(cap * (i == 3 ? 8 : 4));
+        }
+        // packed records: 8 B per entry over the first two arrays (adjacent:
+        // cap * 4 is a multiple of the alignment), then the continuations.
+        // Successive continuations of one walk are at least 2^bo apart in
+        // offset (bo >= the smallest offset width), so a level has at most
+        // (its offsets' range) >> bo of them: the visits for a plain level 0,
+        // the input's elements for a contracted list, whose steps count
+        // whole chains. A wavefront's block wastes fewer ids than the next
+        // block's first step uses.
+        static_assert((LOG_CHUNK * 4) % ALIGN == 0, "packed records span the first two log arrays");
+        p->pack = n <= LOG_PACK_MAX_N;
+        if (p->pack) {
+            const uint32_t bo_min = std::min(p->bocap, LOG_BO_MIN);
+            const uint64_t range = std::max<uint64_t>(cap, p->local ? p->lc_n : n);
+            p->ccap = (uint32_t)(2 * (range >> bo_min) + (uint64_t)CONT_GRAB * (LOG_MAX_WAVES + 1));
+            p->off_conts = off;
+            off += align_up((size_t)p->ccap * 8);
         }
         for (int i = 0; i < arrays; ++i) {
             p->off_p[i] = off;

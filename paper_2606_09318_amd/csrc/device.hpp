@@ -38,7 +38,8 @@ struct Ctrl {
     uint32_t mode;                          // automatic contraction: 0 plain path, 1 tile-local contraction
     uint32_t multi;                         // plain path with more than one list: predecessor marks needed
     uint32_t spn;                           // ruler spawning: number of spawned rulers
-    uint32_t pad[30];
+    uint32_t conts;                         // packed visit log: continuation ids handed out
+    uint32_t pad[29];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
@@ -51,15 +52,47 @@ struct Gate {
     __device__ __forceinline__ bool off() const { return p && *p != want; }
 };
 
-// Visit log of the level-0 chase (log mode), structure of arrays: one record
-// (element, walk, offset) per visited element. The same layout holds the
-// records after they are partitioned by element range.
+// Visit log of the level-0 chase (log mode): one record (element, walk,
+// offset) per visited element, in one of two formats.
+//   wide:   three 32-bit arrays x, w, c.
+//   packed: one 64-bit word r = x << (bw + bo) | walk << bo | offset, field
+//           widths from LogFmt. A walk whose offset outgrows its bo bits goes
+//           on under a continuation id nw + j (nw = walks of the level), whose
+//           entry cont[j] = (walk, offset where the continuation starts); the
+//           offset field then counts from there. Continuation ids are handed
+//           out in blocks of CONT_GRAB per wavefront.
+// Weighted levels add the 64-bit weight sum s in both formats.
 template <bool W>
 struct LogArrays {
     uint32_t* x;
     uint32_t* w;
     uint32_t* c;
     int64_t* s;  // weighted levels only
+    uint64_t* r;     // packed records
+    uint2* cont;     // packed: continuation entries (walk, base offset)
+    uint32_t ccap;   // packed: continuation entries available
+    uint32_t bocap;  // packed: most offset bits a record may use
+};
+
+constexpr uint32_t CONT_GRAB = 128;  // continuation ids a wavefront takes at a time (>= its lanes' walks)
+
+// Field widths of the packed visit log for n elements and nw walks: 2^bx > n,
+// so an all-ones record (chunk padding) names no element; 2^bw > nw + ccap
+// (walks and continuations); bo gets the rest of the 64 bits, at most bocap
+// and 31. Chase and grouping derive the same widths from the same numbers.
+struct LogFmt {
+    uint32_t bx, bw, bo;
+    __device__ __forceinline__ LogFmt(uint32_t n, uint32_t nw, uint32_t ccap, uint32_t bocap) {
+        bx = 32u - (uint32_t)__clz((int)n);
+        bw = 32u - (uint32_t)__clz((int)(nw + ccap));
+        bo = min(64u - bx - bw, min(bocap, 31u));
+    }
+    __device__ __forceinline__ uint64_t pack(uint32_t x, uint32_t w, uint32_t o) const {
+        return ((uint64_t)x << (bw + bo)) | ((uint64_t)w << bo) | o;
+    }
+    __device__ __forceinline__ uint32_t x(uint64_t r) const { return (uint32_t)(r >> (bw + bo)); }
+    __device__ __forceinline__ uint32_t w(uint64_t r) const { return (uint32_t)(r >> bo) & ((1u << bw) - 1u); }
+    __device__ __forceinline__ uint32_t o(uint64_t r) const { return (uint32_t)r & ((1u << bo) - 1u); }
 };
 
 // ---------------------------------------------------------------- values --

@@ -252,6 +252,7 @@ __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restric
             ctrl->lv[lvl].H = H;
             ctrl->lv[lvl].q = 0;
             ctrl->chunks = 0;
+            ctrl->conts = 0;
         }
     }
 }
@@ -399,7 +400,10 @@ __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tile
     if (threadIdx.x == 0) {
         ctrl->lv[lvl].H = total;
         ctrl->lv[lvl].q = 0;
-        if (lvl == 0) ctrl->chunks = 0;
+        if (lvl == 0) {
+            ctrl->chunks = 0;
+            ctrl->conts = 0;
+        }
     }
 }
 
@@ -429,6 +433,16 @@ __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__
 }
 
 // ----------------------------------------------------------------- chase --
+// Pads the rest of a wavefront's visit-log chunk with records that name no
+// element (x = NONE wide, all ones packed).
+template <int LOG, bool W>
+__device__ __forceinline__ void pad_chunk(const LogArrays<W>& lg, uint32_t cbase, uint32_t cfill, uint32_t lane) {
+    for (uint32_t q = cfill + lane; q < LOG_CHUNK; q += 64) {
+        if constexpr (LOG == 2) lg.r[cbase + q] = ~0ull;
+        else lg.x[cbase + q] = NONE;
+    }
+}
+
 // Persistent kernel: each lane holds one walk; a wavefront refills its idle
 // lanes from its own range of walk ids (ballot + mbcnt hand out consecutive
 // ids) once `refill` lanes are idle. Each step is
@@ -440,12 +454,12 @@ __global__ __launch_bounds__(TPB) void k_heads_write(const uint8_t* __restrict__
 // address, the active lanes of a wavefront append their (x, walk, offset)
 // records to a chunk of the visit log that the wavefront owns, at consecutive
 // positions (mbcnt over the active lanes), so every step writes whole lines.
-// A chunk that cannot take another step's records is padded with NONE and a
-// new one is taken with one atomic.
+// A chunk that cannot take another step's records is padded and a new one is
+// taken with one atomic. LOG = 1 writes wide records, LOG = 2 packed ones.
 //
 // NW walks per lane: the lane issues the loads of all its walks before it
 // uses any of them, so NW independent gathers are in flight per lane.
-template <bool W, class Src, bool LOG, int NW>
+template <bool W, class Src, int LOG, int NW>
 __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint32_t S, Ctrl* ctrl, int lvl,
                                                      typename Lay<W>::Slot* __restrict__ slot,
                                                      typename Lay<W>::Rec* __restrict__ eb,
@@ -478,7 +492,7 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
     // the balance gains.
     const uint32_t gwave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t pool16 = (LOG && total >= 64u * nwave) ? LR_CHASE_POOL : 0u;  // many walks per wavefront
+    const uint32_t pool16 = (LOG != 0 && total >= 64u * nwave) ? LR_CHASE_POOL : 0u;  // many walks per wavefront
     const uint32_t own = (uint32_t)((uint64_t)total * (16u - pool16) / 16u);
     const uint32_t per = own / nwave + 1;
     uint32_t whi = (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, own);
@@ -486,6 +500,13 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
     bool exhausted = false;
     uint32_t cbase = 0, cfill = LOG_CHUNK;  // visit-log chunk held by this wavefront (LOG mode)
     bool have = false, dead = false;
+    // packed records (LOG == 2): field widths, and per walk slot the id its
+    // records carry (the walk, or its current continuation) and the offset
+    // that id's records count from; continuation ids come from a block of
+    // CONT_GRAB held by the wavefront
+    const LogFmt fmt(m, total, lg.ccap, lg.bocap);
+    uint32_t rw[NW], rb[NW];
+    uint32_t kbase = 0, kfill = CONT_GRAB;
     for (;;) {
         uint64_t idle[NW];
         uint32_t nidle = 0;
@@ -522,6 +543,8 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                         w[k] = my;
                         off[k] = L::zero();
                         steps[k] = 0;
+                        rw[k] = my;
+                        rb[k] = 0;
                         x[k] = (my < S) ? smp.start(my) : reinterpret_cast<const uint32_t*>(eb + my)[0];
                         if (x[k] >= m) {  // corrupt start (cannot happen for valid input)
                             eb[w[k]] = L::rec(TERM | IDX, L::zero());
@@ -539,7 +562,7 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
         for (int k = 0; k < NW; ++k)
             if (w[k] != NONE) src.load(x[k], nxt[k], v[k]);
         uint32_t pos[NW];
-        if constexpr (LOG) {
+        if constexpr (LOG != 0) {
             uint64_t act[NW];
             uint32_t na = 0;
 #pragma unroll
@@ -549,8 +572,7 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
             }
             if (na && !dead) {
                 if (cfill + na > LOG_CHUNK) {
-                    if (have)
-                        for (uint32_t q = cfill + lane; q < LOG_CHUNK; q += 64) lg.x[cbase + q] = NONE;
+                    if (have) pad_chunk<LOG>(lg, cbase, cfill, lane);
                     uint32_t c = 0;
                     if (lane == 0) c = atomicAdd(&ctrl->chunks, 1u);
                     c = __shfl(c, 0);
@@ -572,15 +594,56 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                 }
                 cfill += na;
             }
+            if constexpr (LOG == 2) {
+                // walks whose offset no longer fits the field take a continuation id
+                uint64_t nc[NW];
+                uint32_t ncs = 0;
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    nc[k] = __ballot(!dead && w[k] != NONE && off[k].c - rb[k] >= (1u << fmt.bo));
+                    ncs += __popcll(nc[k]);
+                }
+                if (ncs) {
+                    if (kfill + ncs > CONT_GRAB) {
+                        uint32_t b = 0;
+                        if (lane == 0) b = atomicAdd(&ctrl->conts, CONT_GRAB);
+                        kbase = __shfl(b, 0);
+                        kfill = 0;
+                    }
+                    if ((uint64_t)kbase + kfill + ncs > lg.ccap) {
+                        // cannot happen: the table holds every continuation a full log can need
+                        if (lane == 0) atomicOr(&ctrl->err, 32u);
+                        dead = true;
+                    } else {
+                        uint32_t acc = kbase + kfill;
+#pragma unroll
+                        for (int k = 0; k < NW; ++k) {
+                            if ((nc[k] >> lane) & 1ull) {
+                                const uint32_t j = acc + mbcnt(nc[k]);
+                                lg.cont[j] = make_uint2(w[k], off[k].c);
+                                rw[k] = total + j;
+                                rb[k] = off[k].c;
+                            }
+                            acc += __popcll(nc[k]);
+                        }
+                        kfill += ncs;
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             if (w[k] == NONE) continue;
-            if constexpr (LOG) {
+            if constexpr (LOG == 1) {
                 if (!dead) {
                     lg.x[pos[k]] = x[k];
                     lg.w[pos[k]] = w[k];
                     lg.c[pos[k]] = off[k].c;
+                    if constexpr (W) lg.s[pos[k]] = off[k].s;
+                }
+            } else if constexpr (LOG == 2) {
+                if (!dead) {
+                    lg.r[pos[k]] = fmt.pack(x[k], rw[k], off[k].c - rb[k]);
                     if constexpr (W) lg.s[pos[k]] = off[k].s;
                 }
             } else {
@@ -606,9 +669,8 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
             }
         }
     }
-    if constexpr (LOG) {
-        if (have)
-            for (uint32_t q = cfill + lane; q < LOG_CHUNK; q += 64) lg.x[cbase + q] = NONE;
+    if constexpr (LOG != 0) {
+        if (have) pad_chunk<LOG>(lg, cbase, cfill, lane);
     }
 }
 
@@ -920,7 +982,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
     __syncthreads();
 }
 
-template <bool W, bool ROOT>
+template <bool W, bool ROOT, bool PACK>
 __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
@@ -937,22 +999,33 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
     const uint32_t nw = S + ctrl->lv[0].H;
     const uint32_t tiles = (used + T - 1) / T;
     // The fields of every record of a tile in one round of loads (a padding
-    // record, x = NONE, is read like the others: it shares their lines). The
-    // next tile's round is issued before this tile is grouped: the grouping's
-    // barriers wait for LDS only, so those loads stay in flight meanwhile.
+    // record names no element and is read like the others: it shares their
+    // lines). The next tile's round is issued before this tile is grouped:
+    // the grouping's barriers wait for LDS only, so those loads stay in
+    // flight meanwhile. Packed records are decoded when they are used.
+    const LogFmt fmt(n, nw, lg.ccap, lg.bocap);
     uint32_t nx[PER], nwl[PER];
+    uint64_t nr[PER];
     typename L::Val noff[PER];
     auto load_tile = [&](uint32_t tile) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            nx[j] = NONE;
-            nwl[j] = NONE;
-            if (i < used) {
-                nx[j] = lg.x[i];
-                nwl[j] = lg.w[i];
-                noff[j].c = lg.c[i];
-                if constexpr (W) noff[j].s = lg.s[i];
+            if constexpr (PACK) {
+                nr[j] = ~0ull;
+                if (i < used) {
+                    nr[j] = lg.r[i];
+                    if constexpr (W) noff[j].s = lg.s[i];
+                }
+            } else {
+                nx[j] = NONE;
+                nwl[j] = NONE;
+                if (i < used) {
+                    nx[j] = lg.x[i];
+                    nwl[j] = lg.w[i];
+                    noff[j].c = lg.c[i];
+                    if constexpr (W) noff[j].s = lg.s[i];
+                }
             }
         }
     };
@@ -963,9 +1036,32 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
         typename L::Val offs[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            xs[j] = nx[j];
-            wl[j] = nwl[j];
-            offs[j] = noff[j];
+            if constexpr (PACK) {
+                xs[j] = fmt.x(nr[j]);
+                wl[j] = fmt.w(nr[j]);
+                offs[j].c = fmt.o(nr[j]);
+                if constexpr (W) offs[j].s = noff[j].s;
+            } else {
+                xs[j] = nx[j];
+                wl[j] = nwl[j];
+                offs[j] = noff[j];
+            }
+        }
+        if constexpr (PACK) {
+            // a continuation id stands for (walk, offset its records count from)
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (xs[j] < n && wl[j] >= nw) {
+                    const uint32_t cid = wl[j] - nw;
+                    if (cid < lg.ccap) {
+                        const uint2 e = lg.cont[cid];
+                        wl[j] = e.x;
+                        offs[j].c += e.y;
+                    } else {
+                        wl[j] = NONE;
+                    }
+                }
+            }
         }
         // every walk result (the records of a walk sit together, so these
         // mostly hit the caches), all issued before any is used
@@ -2083,16 +2179,22 @@ static hipError_t launch_base(Src src, Out out, uint32_t m, Ctrl* ctrl, hipStrea
 }
 
 template <bool W>
-static LogArrays<W> log_arrays(char* ws, const size_t* off) {
-    LogArrays<W> a;
-    a.x = reinterpret_cast<uint32_t*>(ws + off[0]);
-    a.w = reinterpret_cast<uint32_t*>(ws + off[1]);
-    a.c = reinterpret_cast<uint32_t*>(ws + off[2]);
-    a.s = W ? reinterpret_cast<int64_t*>(ws + off[3]) : nullptr;
+static LogArrays<W> log_arrays(char* ws, const Plan& p) {
+    LogArrays<W> a{};
+    a.x = reinterpret_cast<uint32_t*>(ws + p.off_log[0]);
+    a.w = reinterpret_cast<uint32_t*>(ws + p.off_log[1]);
+    a.c = reinterpret_cast<uint32_t*>(ws + p.off_log[2]);
+    a.s = W ? reinterpret_cast<int64_t*>(ws + p.off_log[3]) : nullptr;
+    a.r = reinterpret_cast<uint64_t*>(ws + p.off_log[0]);  // packed: over the first two arrays
+    if (p.pack) {
+        a.cont = reinterpret_cast<uint2*>(ws + p.off_conts);
+        a.ccap = p.ccap;
+        a.bocap = p.bocap;
+    }
     return a;
 }
 
-template <bool W, bool LOG, int NW, class Src>
+template <bool W, int LOG, int NW, class Src>
 static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st,
                                const uint32_t* dm = nullptr, Gate gate = Gate{}) {
     using L = Lay<W>;
@@ -2100,16 +2202,24 @@ static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl*
     static uint32_t grid = 0;  // one per template instance
     if (!grid) {
         grid = persistent_grid(kern, CHASE_TPB);
-        if (LOG) grid = std::min<uint32_t>(grid, LOG_MAX_WAVES / (CHASE_TPB / 64));  // bounds the log slack
+        if (LOG != 0) grid = std::min<uint32_t>(grid, LOG_MAX_WAVES / (CHASE_TPB / 64));  // bounds the log slack
     }
     const uint32_t S = (uint32_t)p.m[l + 1];
     auto* slot = reinterpret_cast<typename L::Slot*>(ws + p.off_slot[l]);
     auto* eb = reinterpret_cast<typename L::Rec*>(ws + p.off_eb[l]);
     uint8_t* hp_next = (l + 1 < (int)p.levels) ? reinterpret_cast<uint8_t*>(ws + p.off_slot[l + 1]) : nullptr;
-    LogArrays<W> lg = LOG ? log_arrays<W>(ws, p.off_log) : LogArrays<W>{};
+    LogArrays<W> lg = LOG != 0 ? log_arrays<W>(ws, p) : LogArrays<W>{};
     hipLaunchKernelGGL(kern, dim3(grid), dim3(CHASE_TPB), 0, st, src, smp, S, ctrl, l, slot, eb, hp_next,
                        p.refill, lg, p.max_chunks, dm, gate);
     return hipGetLastError();
+}
+
+// Level-0 chase into the visit log, in the plan's record format.
+template <bool W, int NW, class Src>
+static hipError_t launch_chase_log(const Plan& p, Src src, Sampler smp, Ctrl* ctrl, char* ws, hipStream_t st,
+                                   const uint32_t* dm, Gate gate) {
+    if (p.pack) return launch_chase<W, 2, NW>(p, 0, src, smp, ctrl, ws, st, dm, gate);
+    return launch_chase<W, 1, NW>(p, 0, src, smp, ctrl, ws, st, dm, gate);
 }
 
 #define LR_TRY(x)                              \
@@ -2150,9 +2260,15 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const dim3 tpb(place_tpb(ROOT));
     const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
     const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
-    LR_TRY(allow_lds(k_place1<W, ROOT>, l1));
-    hipLaunchKernelGGL((k_place1<W, ROOT>), dim3(grid_for(cap, T)), tpb, l1, st, log_arrays<W>(ws, p.off_log),
-                       p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, dm, a.gate);
+    if (p.pack) {
+        LR_TRY(allow_lds(k_place1<W, ROOT, true>, l1));
+        hipLaunchKernelGGL((k_place1<W, ROOT, true>), dim3(grid_for(cap, T)), tpb, l1, st, log_arrays<W>(ws, p),
+                           p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, dm, a.gate);
+    } else {
+        LR_TRY(allow_lds(k_place1<W, ROOT, false>, l1));
+        hipLaunchKernelGGL((k_place1<W, ROOT, false>), dim3(grid_for(cap, T)), tpb, l1, st, log_arrays<W>(ws, p),
+                           p.max_chunks, res, S, ctrl, n, p.s1, p.nb1, fill1, P, dm, a.gate);
+    }
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_PART);
     const size_t l2 = place_lds_bytes(W, ROOT, 1u << (p.s1 - p.s2));
@@ -2325,20 +2441,20 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
                                        pr, g);
                     LR_TRY(hipGetLastError());
                     SrcPair<WT> srcp{pr, n};
-                    LR_TRY((launch_chase<W, true, 1>(p, 0, srcp, smp, ctrl, ws, st, nullptr, g)));
+                    LR_TRY((launch_chase_log<W, 1>(p, srcp, smp, ctrl, ws, st, nullptr, g)));
                 } else if (p.lane_walks == 2) {
-                    LR_TRY((launch_chase<W, true, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                    LR_TRY((launch_chase_log<W, 2>(p, src0, smp, ctrl, ws, st, nullptr, g)));
                 } else {
-                    LR_TRY((launch_chase<W, true, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                    LR_TRY((launch_chase_log<W, 1>(p, src0, smp, ctrl, ws, st, nullptr, g)));
                 }
             } else {
-                if (p.lane_walks == 2) LR_TRY((launch_chase<W, false, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
-                else LR_TRY((launch_chase<W, false, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                if (p.lane_walks == 2) LR_TRY((launch_chase<W, 0, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                else LR_TRY((launch_chase<W, 0, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
             }
             rec_ev(a, EV_CHASE0);
         } else {
             SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]), m};
-            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, nullptr, g)));
+            LR_TRY((launch_chase<W, 0, 1>(p, (int)l, src, smp, ctrl, ws, st, nullptr, g)));
         }
     }
     {
@@ -2411,9 +2527,9 @@ static hipError_t run_clevels(const RunArgs& a, const Plan& p, typename Lay<W>::
         SrcLvl<W> src{rec, (uint32_t)p.m[l]};
         if (l == 0 && p.log0) {  // a long contracted list: visit log and grouped placement, as the plain path
             LR_TRY(fill(ws + p.off_fill, fill_words(p.nb1, p.nb2) * 4, 0u, st, nullptr, g));
-            LR_TRY((launch_chase<W, true, 1>(p, 0, src, smp, ctrl, ws, st, dm, g)));
+            LR_TRY((launch_chase_log<W, 1>(p, src, smp, ctrl, ws, st, dm, g)));
         } else {
-            LR_TRY((launch_chase<W, false, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
+            LR_TRY((launch_chase<W, 0, 1>(p, (int)l, src, smp, ctrl, ws, st, dm, g)));
         }
         if (l == 0 && ev_chase0) rec_ev(a, EV_CHASE0);
     }

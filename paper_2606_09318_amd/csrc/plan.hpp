@@ -23,6 +23,12 @@ constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps th
 #endif
 constexpr uint64_t LOG_MIN_N = 1ull << LR_LOG_MIN_LOG2;  // smallest level 0 that uses the visit log
 constexpr uint64_t LOG_FORCE_MIN_N = 1ull << 16;          // smallest level 0 LR_VISIT_LOG applies to
+// Packed visit-log records (one 64-bit word) up to 2^28 elements: then the
+// element field takes at most 29 bits and the walk field (walks plus
+// continuations, fewer than 2^29) at most 29, which leaves the offset field
+// at least LOG_BO_MIN bits. Larger inputs keep the wide 12-byte records.
+constexpr uint64_t LOG_PACK_MAX_N = 1ull << 28;
+constexpr uint32_t LOG_BO_MIN = 6;
 #ifndef LR_PLACE_FINE_SHIFT
 #define LR_PLACE_FINE_SHIFT 13
 #endif
@@ -108,6 +114,10 @@ struct Plan {
     // passes (ranges of 2^s1, then 2^s2 ids) and written range by range from
     // LDS. The fine-grouped records reuse the log arrays.
     bool log0 = false;
+    bool pack = false;       // packed records; else wide
+    uint32_t ccap = 0;       // packed: continuation entries
+    uint32_t bocap = 31;     // packed: most offset bits per record
+    size_t off_conts = 0;    // packed: continuation entries, 8 B each
     uint32_t chunk = 0, max_chunks = 0, s1 = 0, s2 = 0, nb1 = 0, nb2 = 0;
     size_t off_log[4] = {}, off_p[4] = {}, off_fill = 0;  // fill: nb1 then nb2 counters
     uint32_t batch_count = 0;

@@ -146,3 +146,16 @@ def test_visit_log_flag_sizes_the_log():
     small = 1 << 15
     assert lr.lr_workspace_bytes(small, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_VISIT_LOG)) == \
         lr.lr_workspace_bytes(small, lr.LR_W_NONE)
+
+
+def test_packed_visit_log_sizing():
+    """Visit logs of up to 2^28 elements add a continuation table (a smaller
+    offset field needs a larger one); above 2^28 the records stay wide and no
+    table is added; an offset field above 31 bits is rejected."""
+    n = 1 << 26
+    base = lr.lr_workspace_bytes(n)
+    assert lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(log_off_bits=1)) > base
+    assert lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(log_off_bits=20)) == base
+    big = (1 << 28) + 1
+    assert lr.lr_workspace_bytes(big) == lr.lr_workspace_bytes(big, lr.LR_W_NONE, lr.make_opts(log_off_bits=1))
+    assert lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(log_off_bits=32)) == 0

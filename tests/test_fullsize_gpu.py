@@ -22,6 +22,19 @@ def closed_form_ok(rank, root, order_np):
     return ok and bool((root == int(order_np[-1])).all())
 
 
+def test_wide_visit_log_above_2p28():
+    """Above 2^28 elements the visit log keeps wide 12-byte records (the packed
+    64-bit ones hold up to 2^28): ranks and roots of a random list of
+    2^28 + 4097 elements equal the closed form of its generator."""
+    n = (1 << 28) + 4097
+    print(f"case: wide visit log n={n}", flush=True)
+    L = workloads.random_list(n, seed=41)
+    succ = dev(L.succ)
+    r, t = lr.rank(succ)
+    torch.cuda.synchronize()
+    assert closed_form_ok(r, t, L.order)
+
+
 @pytest.mark.parametrize("kind", ["random", "block4096"])
 def test_single_list_2p28(kind):
     n = 1 << 28

@@ -270,6 +270,38 @@ def test_log_mode_all_singletons_and_pairs():
     check_rank(pairs, o)
 
 
+@pytest.mark.parametrize("bits", [1, 3, 7])
+def test_packed_log_continuations(bits):
+    """Packed visit-log records with the offset field capped at `bits` bits:
+    a walk goes on under a new continuation id every 2^bits visits; ranks,
+    roots and weighted sums still equal the oracle's."""
+    n = (1 << 22) + 4321
+    print(f"case: packed log continuations bits={bits}", flush=True)
+    o = lr.make_opts(flags=LOG | lr.LR_NO_LOCAL, log_off_bits=bits)
+    L = workloads.random_list(n, seed=31)
+    check_rank(L.succ, o)
+    F = workloads.forest(n, mean=64, n_long=4, long_len=100000, seed=32)
+    st, s, r, t = gpu_prefix(F.succ, F.weight, o)
+    ost, er, et, es = oracle.rank(F.succ, F.weight)
+    assert st == lr.LR_OK and np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+
+
+@pytest.mark.parametrize("bits", [0, 2])
+def test_packed_log_contracted_list(bits):
+    """The contracted list of tile-local contraction through the packed
+    visit log: its steps count whole chains, so with a 2-bit offset field
+    nearly every record of a walk starts a continuation."""
+    n = (1 << 22) + 99
+    print(f"case: packed log contracted list bits={bits}", flush=True)
+    o = lr.make_opts(flags=LOG | lr.LR_LOCAL, log_off_bits=bits)
+    check_rank(workloads.gamma_list(n, 0.1, seed=33).succ, o)
+    check_rank(workloads.block_list(n, block=4096, seed=34).succ, o)
+    F = workloads.forest(n, mean=8, n_long=1, long_len=300000, seed=35, wdtype=np.int32)
+    st, s, r, t = gpu_prefix(F.succ, F.weight, o)
+    ost, er, et, es = oracle.rank(F.succ, F.weight)
+    assert st == lr.LR_OK and np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
+
+
 def test_log_mode_validate():
     n = 1 << 22
     o = lr.make_opts(flags=lr.LR_VALIDATE | LOG)

@@ -1,6 +1,7 @@
 """Randomised parity: seeded draws of size, input family, path (default,
-tile-local contraction forced or forbidden, ruler spawning, visit log forced),
-level spacings, base-case size and weight type, each ranked on the GPU and
+tile-local contraction forced or forbidden, ruler spawning, visit log forced
+on the plain or the contracted list), level spacings, base-case size, the
+visit log's offset field width and weight type, each ranked on the GPU and
 compared with the oracle element by element. The draws are fixed by the
 seed, so a failure names a reproducible case."""
 import numpy as np
@@ -13,7 +14,8 @@ from gpu_util import gpu_prefix, gpu_rank
 
 pytestmark = pytest.mark.gpu
 
-FLAG_SETS = [0, lr.LR_LOCAL, lr.LR_NO_LOCAL, lr.LR_SPAWN, lr.LR_NO_LOCAL | lr.LR_VISIT_LOG]
+FLAG_SETS = [0, lr.LR_LOCAL, lr.LR_NO_LOCAL, lr.LR_SPAWN, lr.LR_NO_LOCAL | lr.LR_VISIT_LOG,
+             lr.LR_LOCAL | lr.LR_VISIT_LOG]
 
 
 def draw(i):
@@ -24,7 +26,9 @@ def draw(i):
     spacing = () if rng.random() < 0.5 else tuple(int(2 ** rng.integers(1, 8)) for _ in range(rng.integers(1, 4)))
     base = [0, 16, 256, 4096][rng.integers(4)]
     wt = [None, np.int32, np.int64][rng.integers(3)]
-    return n, family, flags, spacing, base, wt, int(rng.integers(1 << 30))
+    seed = int(rng.integers(1 << 30))
+    bits = [0, 0, 1, 2, 5][rng.integers(5)]  # offset field of packed visit-log records (0 = widest)
+    return n, family, flags, spacing, base, wt, seed, bits
 
 
 def make(n, family, seed):
@@ -41,10 +45,11 @@ def make(n, family, seed):
 
 @pytest.mark.parametrize("i", range(200))
 def test_random_config(i):
-    n, family, flags, spacing, base, wt, seed = draw(i)
-    print(f"case {i}: n={n} {family} flags={flags} spacing={spacing} base={base} wt={wt} seed={seed}", flush=True)
+    n, family, flags, spacing, base, wt, seed, bits = draw(i)
+    print(f"case {i}: n={n} {family} flags={flags} spacing={spacing} base={base} wt={wt} seed={seed} "
+          f"log_off_bits={bits}", flush=True)
     succ = make(n, family, seed)
-    o = lr.make_opts(flags=flags, spacing=spacing, base_max=base, seed=seed)
+    o = lr.make_opts(flags=flags, spacing=spacing, base_max=base, seed=seed, log_off_bits=bits)
     if wt is None:
         st, r, t = gpu_rank(succ, o)
         assert st == lr.LR_OK, lr.status_string(st)
