@@ -214,9 +214,11 @@ def main():
     ph = np.median(np.array(phases), axis=0)
     chase_ms = float(ph[2])
     S = int(plan.m[1])
-    # per element: 4 B succ gather + 12 B visit-log record (element, walk, offset);
-    # per walk: 8 B walk record + 1 B predecessor mark
-    chase_bytes = n * (4 + 12) + S * (8 + 1)
+    # per element: 4 B succ gather + the visit-log record (element, walk, offset:
+    # one 8 B word up to 2^28 elements, 12 B above); per walk: 8 B walk record +
+    # 1 B predecessor mark
+    rec = 8 if n <= (1 << 28) else 12
+    chase_bytes = n * (4 + rec) + S * (8 + 1)
     achieved = chase_bytes / (chase_ms * 1e-3) / 1e9
     traffic = None
     call_traffic = None
@@ -233,9 +235,9 @@ def main():
                 "traffic": traffic, "chase_ms": round(chase_ms, 4),
                 "algorithmic_bytes": chase_bytes}
     # per element over the level-0 passes of the timed call (rank only): head sum 4 B read;
-    # chase 4 B gather + 12 B log write; place1 12 B read + 8 B write; place2 8 + 8;
-    # place3 8 B read + 4 B rank write  -> 68 B
-    whole_bytes = n * (4 + 4 + 12 + 12 + 8 + 8 + 8 + 8 + 4)
+    # chase 4 B gather + log record write; place1 log record read + 8 B write;
+    # place2 8 + 8; place3 8 B read + 4 B rank write  -> 60 B with 8 B records
+    whole_bytes = n * (4 + 4 + rec + rec + 8 + 8 + 8 + 8 + 4)
     extra = {"phases_ms": {"detect": round(float(ph[0]), 4), "heads": round(float(ph[1]), 4),
                            "chase_level0": round(chase_ms, 4), "upper_levels_and_base": round(float(ph[3]), 4),
                            "resolve_and_group": round(float(ph[4]), 4),
