@@ -79,7 +79,10 @@ enum {
  * per element) but appends them to per-wavefront logs written in whole lines;
  * two grouping passes then bring every record to its element's range, and
  * the outputs are written range by range. Below 2^25 the random stores are
- * cheaper (the arrays are small enough for the caches to absorb them). */
+ * cheaper (the arrays are small enough for the caches to absorb them). Up to
+ * 2^28 elements a record is one 64-bit word (element, walk, offset; a walk
+ * whose offset outgrows its field goes on under a continuation id, see
+ * log_off_bits), above 2^28 three 32-bit words. */
 /* Ruler spawning (Section 2.2): the first level is chased in two rounds. The
  * walks of the sampled rulers and heads stop after 2k steps, each marking the
  * element it would have taken next; then new rulers are spawned at every such
