@@ -234,6 +234,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "chase_ms": round(chase_ms, 4),
                 "algorithmic_bytes": chase_bytes}
+    if traffic:
+        # the HBM rate the counted bytes imply (each 4 B gather moves a whole line)
+        roofline["traffic_gb_s"] = round(traffic / (chase_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gb_s"] / HBM_PEAK_GBS, 4)
     # per element over the level-0 passes of the timed call (rank only): head sum 4 B read;
     # chase 4 B gather + log record write; place1 log record read + 8 B write;
     # place2 8 + 8; place3 8 B read + 4 B rank write  -> 60 B with 8 B records
