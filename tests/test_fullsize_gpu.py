@@ -35,6 +35,20 @@ def test_wide_visit_log_above_2p28():
     assert closed_form_ok(r, t, L.order)
 
 
+def test_packed_visit_log_continuations_2p28():
+    """The 2^28 random list with the visit log's offset field cut to 4 bits:
+    a walk takes a continuation id every 16 visits (about 16 M of them, from
+    wavefront-owned blocks); every rank and root still equals the closed form
+    of the generator."""
+    n = 1 << 28
+    print("case: packed visit log, 4-bit offsets, n=2^28", flush=True)
+    L = workloads.random_list(n, seed=2, stream=0)
+    succ = dev(L.succ)
+    r, t = lr.rank(succ, opts=lr.make_opts(log_off_bits=4))
+    torch.cuda.synchronize()
+    assert closed_form_ok(r, t, L.order)
+
+
 @pytest.mark.parametrize("kind", ["random", "block4096"])
 def test_single_list_2p28(kind):
     n = 1 << 28
