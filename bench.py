@@ -131,7 +131,7 @@ def main():
         return
 
     if args.sweep:
-        print(json.dumps({"sweep": args.sweep, "unit": "ms per lr_rank call (median of 15), rank output",
+        print(json.dumps({"sweep": args.sweep, "unit": "ms per lr_rank call (median of 15), rank and root outputs",
                           "rows": size_sweep(args.sweep, stream)}))
         return
 
