@@ -98,7 +98,14 @@ static size_t layout_levels(Plan* p, size_t off) {
         uint32_t lg = 0;
         while ((1ull << lg) < n) ++lg;
         p->s2 = PLACE_FINE_SHIFT;                               // a fine range's outputs fit one workgroup's LDS
-        p->s1 = p->s2 + std::max(1u, (lg - p->s2 + 1) / 2);     // split the fan-out evenly over two passes
+        // split the fan-out over the two passes, a little more of it in the
+        // second: the first pass's frontiers are shared by every XCD, so its
+        // partial lines are written back from several L2s, while the second
+        // pass's frontiers stay in one XCD's L2. Weighted records (four
+        // arrays) gain more from longer first-pass runs.
+        const uint32_t bias = weighted ? LR_PLACE_COARSE_BIAS_W : LR_PLACE_COARSE_BIAS;
+        p->s1 = p->s2 + std::max(1u, (lg - p->s2 + 1) / 2 + bias);
+        if ((1ull << p->s1) >= 2 * n) p->s1 = std::max(p->s2 + 1, lg);
         p->nb1 = (uint32_t)((n + (1ull << p->s1) - 1) >> p->s1);
         p->nb2 = (uint32_t)((n + (1ull << p->s2) - 1) >> p->s2);
         const int arrays = weighted ? 4 : 3;

@@ -33,6 +33,14 @@ constexpr uint32_t LOG_BO_MIN = 6;
 #define LR_PLACE_FINE_SHIFT 13
 #endif
 constexpr uint32_t PLACE_FINE_SHIFT = LR_PLACE_FINE_SHIFT;  // fine placement ranges of 8192 elements (LDS of one workgroup)
+// bits of the grouping fan-out moved from the first pass to the second
+// (unweighted / weighted records)
+#ifndef LR_PLACE_COARSE_BIAS
+#define LR_PLACE_COARSE_BIAS 1
+#endif
+#ifndef LR_PLACE_COARSE_BIAS_W
+#define LR_PLACE_COARSE_BIAS_W 2
+#endif
 // Grouping counters: every tile of the first pass reserves space in every
 // coarse range, so each coarse range has two counters, a front one that fills
 // the range upward and a back one that fills it downward (even tiles take the
