@@ -873,7 +873,7 @@ struct PlaceArrays {
 };
 
 template <bool W, bool ROOT>
-constexpr int place_per() { return (int)place_tile_records(W, ROOT) / place_tpb(ROOT); }
+constexpr int place_per() { return (int)place_tile_records(W, ROOT) / place_tpb(W, ROOT); }
 
 // LDS bytes of one grouping tile over nb ranges (device and host agree);
 // without values only the element ids are grouped.
@@ -893,7 +893,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
                            const int64_t (&ss)[PER], const uint32_t (&bs)[PER], uint32_t nb, uint32_t shift,
                            uint32_t lo_bucket, uint32_t n, uint32_t* __restrict__ fill, PlaceArrays<W> out,
                            Ctrl* ctrl, unsigned char* lds, uint32_t side = 0) {
-    constexpr int TPB_ = place_tpb(ROOT);
+    constexpr int TPB_ = place_tpb(W, ROOT);
     constexpr uint32_t T = (uint32_t)PER * TPB_;
     size_t o = 0;
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + o);
@@ -983,7 +983,7 @@ __device__ void place_tile(const uint32_t (&xs)[PER], const uint32_t (&rs)[PER],
 }
 
 template <bool W, bool ROOT, bool PACK>
-__global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
+__global__ __launch_bounds__(place_tpb(W, ROOT)) void k_place1(LogArrays<W> lg, uint32_t max_chunks,
                                                 const typename Lay<W>::Res* __restrict__ res, uint32_t S,
                                                 Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t nb1,
                                                 uint32_t* __restrict__ fill1, PlaceArrays<W> out, const uint32_t* dm,
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
     using L = Lay<W>;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W, ROOT>();
-    constexpr int TPB_ = place_tpb(ROOT);
+    constexpr int TPB_ = place_tpb(W, ROOT);
     constexpr uint32_t T = PER * TPB_;
     const uint32_t used = min(ctrl->chunks, max_chunks) * LOG_CHUNK;
     const uint32_t nw = S + ctrl->lv[0].H;
@@ -1099,14 +1099,14 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place1(LogArrays<W> lg, uin
 // length; VALS = false groups element ids only: then a coarse range need not
 // be full and its records are its front and back segments.
 template <bool W, bool ROOT, bool VALS = true>
-__global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
+__global__ __launch_bounds__(place_tpb(W, ROOT)) void k_place2(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s1, uint32_t s2,
                                                 uint32_t* __restrict__ fill2, PlaceArrays<W> out, const uint32_t* dm,
                                                 const uint32_t* __restrict__ fill1, Gate gate) {
     if (gate.off()) return;
     if (dm) n = dm[0];
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<W, ROOT>();
-    constexpr int TPB_ = place_tpb(ROOT);
+    constexpr int TPB_ = place_tpb(W, ROOT);
     constexpr uint32_t T = PER * TPB_;
     const uint32_t tiles = (n + T - 1) / T;
     const uint32_t fan = 1u << (s1 - s2);
@@ -1197,7 +1197,7 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place2(PlaceArrays<W> in, C
 // One workgroup per fine range of 2^s2 elements: place the records by x in
 // LDS, then write the outputs in element order.
 template <bool W, bool ROOT, class Out>
-__global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
+__global__ __launch_bounds__(place_tpb(W, ROOT)) void k_place3(PlaceArrays<W> in, Ctrl* ctrl, uint32_t n, uint32_t s2, uint32_t nb2,
                                                 const uint32_t* __restrict__ fill2, int check, Out out,
                                                 const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
@@ -1215,7 +1215,7 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, C
     for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
         const uint32_t base = f << s2;
         const uint32_t len = min(R, n - base);
-        for (uint32_t i = t; i < len; i += place_tpb(ROOT)) {
+        for (uint32_t i = t; i < len; i += place_tpb(W, ROOT)) {
             lr[i] = NONE;
             if constexpr (ROOT) lt[i] = NONE;
             if constexpr (W) ls[i] = INT64_MIN;
@@ -1225,12 +1225,12 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, C
         // four records per lane per round, every field loaded before any LDS
         // store (the value loads do not wait for the element id)
         constexpr int U = 4;
-        for (uint32_t i0 = t; i0 < len; i0 += U * place_tpb(ROOT)) {
+        for (uint32_t i0 = t; i0 < len; i0 += U * place_tpb(W, ROOT)) {
             uint32_t kk[U], rv[U], tv[U];
             int64_t sv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t i = i0 + u * place_tpb(ROOT);
+                const uint32_t i = i0 + u * place_tpb(W, ROOT);
                 kk[u] = NONE;
                 if (i < len) {
                     kk[u] = in.x[base + i] - base;
@@ -1251,7 +1251,7 @@ __global__ __launch_bounds__(place_tpb(ROOT)) void k_place3(PlaceArrays<W> in, C
         __syncthreads();
         if (t < len) {
             auto cur = out.begin(base + t);
-            for (uint32_t i = t; i < len; i += place_tpb(ROOT)) {
+            for (uint32_t i = t; i < len; i += place_tpb(W, ROOT)) {
                 typename L::Val v;
                 v.c = lr[i];
                 if constexpr (W) v.s = ls[i];
@@ -1285,13 +1285,13 @@ __global__ __launch_bounds__(TPB) void k_pair(const uint32_t* __restrict__ succ,
 // from LDS in order. Every id is the target of at most one link, so no range
 // receives more targets than it has ids.
 template <bool VEC>
-__global__ __launch_bounds__(place_tpb(false)) void k_mark1(const uint32_t* __restrict__ succ, uint32_t n, uint32_t s1,
+__global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_t* __restrict__ succ, uint32_t n, uint32_t s1,
                                                             uint32_t nb1, uint32_t* __restrict__ fill1,
                                                             PlaceArrays<false> out, Ctrl* ctrl, Gate gate) {
     if (gate.off()) return;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<false, false>();
-    constexpr int TPB_ = place_tpb(false);
+    constexpr int TPB_ = place_tpb(false, false);
     constexpr uint32_t T = PER * TPB_;
     const uint32_t tiles = (n + T - 1) / T;
     // the next tile's successors are loaded while this tile is grouped (the
@@ -1322,13 +1322,13 @@ __global__ __launch_bounds__(place_tpb(false)) void k_mark1(const uint32_t* __re
 
 // One workgroup per fine range: the range's targets set bytes in LDS, then
 // the range's marks are written in order (all n bytes get written).
-__global__ __launch_bounds__(place_tpb(false)) void k_mark3(const uint32_t* __restrict__ tx, uint32_t n, uint32_t s2,
+__global__ __launch_bounds__(place_tpb(false, false)) void k_mark3(const uint32_t* __restrict__ tx, uint32_t n, uint32_t s2,
                                                             uint32_t nb2, const uint32_t* __restrict__ fill2,
                                                             uint8_t* __restrict__ hp, Gate gate) {
     if (gate.off()) return;
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t* mk = reinterpret_cast<uint32_t*>(lds);
-    constexpr int TPB_ = place_tpb(false);
+    constexpr int TPB_ = place_tpb(false, false);
     const uint32_t R = 1u << s2;
     for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
         const uint32_t base = f << s2;
@@ -2257,7 +2257,7 @@ static hipError_t run_place_t(const RunArgs& a, const Plan& p, const typename La
     const PlaceArrays<W> P = place_arrays<W>(ws, p.off_p);
     const PlaceArrays<W> Q = place_arrays<W>(ws, p.off_log);
     constexpr uint32_t T = place_tile_records(W, ROOT);
-    const dim3 tpb(place_tpb(ROOT));
+    const dim3 tpb(place_tpb(W, ROOT));
     const size_t cap = (size_t)p.max_chunks * LOG_CHUNK;
     const size_t l1 = place_lds_bytes(W, ROOT, p.nb1);
     if (p.pack) {
@@ -2306,7 +2306,7 @@ static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl*
     const PlaceArrays<false> P = place_arrays<false>(ws, p.off_p);
     const PlaceArrays<false> Q = place_arrays<false>(ws, p.off_log);
     constexpr uint32_t T = place_tile_records(false, false);
-    const dim3 tpb(place_tpb(false));
+    const dim3 tpb(place_tpb(false, false));
     const bool vec = ((uintptr_t)a.succ % 16) == 0;
     const size_t l1 = place_lds_bytes(false, false, p.nb1, false);
     if (vec) {

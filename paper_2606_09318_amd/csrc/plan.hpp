@@ -82,8 +82,8 @@ constexpr uint32_t SPAWN_K0 = LR_SPAWN_K0;
 #endif
 static_assert((LR_SPAWN_K2 & (LR_SPAWN_K2 - 1)) == 0, "k2 is a power of two");
 // grouping tiles: lanes x LR_PLACE_PER records (half as many weighted); the
-// passes that also carry roots use wider workgroups (measured faster there,
-// slower without roots)
+// passes whose records carry roots or weights use wider workgroups (measured
+// faster there, slower for plain ranks)
 #ifndef LR_PLACE_TPB
 #define LR_PLACE_TPB 512
 #endif
@@ -93,9 +93,9 @@ static_assert((LR_SPAWN_K2 & (LR_SPAWN_K2 - 1)) == 0, "k2 is a power of two");
 #ifndef LR_PLACE_PER
 #define LR_PLACE_PER 8
 #endif
-constexpr int place_tpb(bool root) { return root ? LR_PLACE_TPB_ROOT : LR_PLACE_TPB; }
+constexpr int place_tpb(bool weighted, bool root) { return (weighted || root) ? LR_PLACE_TPB_ROOT : LR_PLACE_TPB; }
 constexpr uint32_t place_tile_records(bool weighted, bool root) {
-    return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * (uint32_t)place_tpb(root);
+    return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * (uint32_t)place_tpb(weighted, root);
 }
 
 struct Plan {
