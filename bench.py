@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
-    ap.add_argument("--list", choices=["random", "block", "forest"], default="random",
+    ap.add_argument("--list", choices=["random", "block", "forest", "euler"], default="random",
                     help="with --only-main: the random list, the block-local list of the same size, or the "
                          "2^27 forest with int64 weights (prefix sums, rank and root)")
     ap.add_argument("--no-serve", action="store_true")
@@ -140,6 +140,9 @@ def main():
         raise SystemExit("--list applies to --only-main runs")
     if args.list == "forest":
         forest_only(args, stream)
+        return
+    if args.list == "euler":
+        euler_only(args, stream)
         return
     t0 = time.time()
     L = workloads.random_list(n, seed=2, stream=0) if args.list == "random" else \
@@ -461,6 +464,41 @@ def locality_bench(n: int, rank, stream, gammas) -> dict:
         r["gamma"] = g
         out["gamma_sweep"].append(r)
     return out
+
+
+def euler_only(args, stream):
+    """Profiling entry: the Euler tour of a 2^26-vertex random recursive tree
+    (2^27 - 2 arcs in random order, +1/-1 int32 weights), lr_prefix_sum with
+    the sums only (they give the depths)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    E = workloads.euler_tour(1 << 26, seed=4)
+    m = E.succ.size
+    succ = torch.from_numpy(E.succ.view(np.int32)).cuda()
+    w = torch.from_numpy(E.weight).cuda()
+    sm = torch.empty(m, dtype=torch.int64, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(m, lr.LR_W_I32))
+
+    def step():
+        st = lr.lr_prefix_sum(succ, w, sm, None, None, ws, None, stream)
+        if st:
+            raise lr.LrError(st, "lr_prefix_sum")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    print(json.dumps({"workload": "Euler tour of a 2^26-vertex tree, int32 weights", "ms_per_step": round(ms, 4),
+                      "g_arcs_per_s": round(m / (ms * 1e-3) / 1e9, 3), "list": "euler"}))
 
 
 def weighted_bench() -> dict:
