@@ -302,6 +302,31 @@ def test_packed_log_contracted_list(bits):
     assert st == lr.LR_OK and np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
 
 
+@pytest.mark.parametrize("wdtype", [np.int32, np.int64])
+def test_log_mode_unaligned_weights_and_successors(wdtype):
+    """The head-sum pass interleaves (successor, weight) records with vector
+    loads only when both arrays are 16-byte aligned; views that start one
+    element in take its scalar path. Sums, ranks and roots equal the oracle's."""
+    n = (1 << 22) + 5
+    print(f"case: log mode unaligned inputs {wdtype.__name__}", flush=True)
+    F = workloads.forest(n, mean=64, n_long=4, long_len=100000, seed=36, wdtype=wdtype)
+    o = lr.make_opts(flags=LOG | lr.LR_NO_LOCAL)
+    wbig = torch.empty(n + 1, dtype=torch.from_numpy(F.weight[:1]).dtype, device="cuda")
+    wbig[1:] = torch.from_numpy(F.weight).cuda()
+    sbig = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    sbig[1:] = dev(F.succ)
+    ost, er, et, es = oracle.rank(F.succ, F.weight)
+    for succ, w in ((dev(F.succ), wbig[1:]), (sbig[1:], wbig[1:]), (sbig[1:], torch.from_numpy(F.weight).cuda())):
+        sm = torch.empty(n, dtype=torch.int64, device="cuda")
+        r = torch.empty(n, dtype=torch.int32, device="cuda")
+        t = torch.empty(n, dtype=torch.int32, device="cuda")
+        ws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_I64, o))
+        assert lr.lr_prefix_sum(succ, w, sm, r, t, ws, o) == lr.LR_OK
+        torch.cuda.synchronize()
+        assert np.array_equal(sm.cpu().numpy(), es)
+        assert np.array_equal(r.cpu().numpy().view(np.uint32), er) and np.array_equal(t.cpu().numpy().view(np.uint32), et)
+
+
 def test_log_mode_validate():
     n = 1 << 22
     o = lr.make_opts(flags=lr.LR_VALIDATE | LOG)
