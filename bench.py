@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
-    ap.add_argument("--list", choices=["random", "block", "forest", "euler"], default="random",
+    ap.add_argument("--list", choices=["random", "block", "forest", "euler", "batch"], default="random",
                     help="with --only-main: the random list, the block-local list of the same size, or the "
                          "2^27 forest with int64 weights (prefix sums, rank and root)")
     ap.add_argument("--no-serve", action="store_true")
@@ -143,6 +143,9 @@ def main():
         return
     if args.list == "euler":
         euler_only(args, stream)
+        return
+    if args.list == "batch":
+        batch_only(args, stream)
         return
     t0 = time.time()
     L = workloads.random_list(n, seed=2, stream=0) if args.list == "random" else \
@@ -499,6 +502,54 @@ def euler_only(args, stream):
     ms = ev0.elapsed_time(ev1) / args.steps
     print(json.dumps({"workload": "Euler tour of a 2^26-vertex tree, int32 weights", "ms_per_step": round(ms, 4),
                       "g_arcs_per_s": round(m / (ms * 1e-3) / 1e9, 3), "list": "euler"}))
+
+
+def batch_only(args, stream):
+    """Profiling entry: the first 64 requests of the serving trace (sizes
+    log-uniform over 2^10..2^24, random and block-local lists alternating)
+    ranked by one lr_rank_batch call; every request checked against its
+    closed form after the timed steps."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    tr = workloads.serving_trace(count=64, lo_log2=10, hi_log2=24, rate_per_s=1.0, seed=5)
+    items, orders = [], []
+    for q in tr:
+        Lq = workloads.request_input(q)
+        items.append((torch.from_numpy(Lq.succ.view(np.int32)).cuda(), torch.empty(q.n, dtype=torch.int32, device="cuda"),
+                      None))
+        orders.append(Lq.order)
+    total = sum(q.n for q in tr)
+    reqs = lr.requests(items)
+    ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items)))
+
+    def step():
+        st = lr.lr_rank_batch(reqs, len(items), ws, None, stream)
+        if st:
+            raise lr.LrError(st, "lr_rank_batch")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    ok = True
+    for (s, r, _), order in zip(items, orders):
+        n = s.numel()
+        expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+        ok = ok and bool(torch.equal(r.index_select(0, torch.from_numpy(order.view(np.int32)).cuda()), expect))
+    if not ok:
+        raise SystemExit("bench: a batched request does not match its closed form")
+    print(json.dumps({"workload": "64 serving-trace requests in one lr_rank_batch call", "requests": len(items),
+                      "elements": total, "ms_per_step": round(ms, 4),
+                      "g_elements_per_s": round(total / (ms * 1e-3) / 1e9, 3), "list": "batch"}))
 
 
 def weighted_bench() -> dict:

@@ -266,7 +266,11 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         p->off_batch_desc = off;
         off += align_up((size_t)batch_count * sizeof(BatchDesc));
         p->off_batch_bases = off;
-        off += align_up((size_t)(batch_count + 1) * 4);
+        off += align_up(batch_table_bytes(batch_count));
+        p->off_batch_part = off;  // at most n / BATCH_CHUNK + one partial chunk per request
+        off += align_up(((size_t)n / BATCH_CHUNK + batch_count + 1) * 16);
+        p->off_batch_sums = off;
+        off += align_up((size_t)batch_count * 16);
     }
     p->total = off + ALIGN;  // room to align the caller's base pointer
     ps->lp.total = p->total;
@@ -504,17 +508,21 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     if ((s = check_base_lds(p)) != LR_OK) return s;
     if (ps.autol && (s = check_base_lds(ps.lp)) != LR_OK) return s;
     const size_t desc_bytes = (size_t)count * sizeof(BatchDesc);
-    const size_t base_bytes = (size_t)(count + 1) * 4;
+    const size_t base_bytes = batch_table_bytes(count);
     if (host_cap < desc_bytes + base_bytes) return LR_ERR_INVALID_ARG;
     BatchDesc* hd = static_cast<BatchDesc*>(host_stage);
     uint32_t* hb = reinterpret_cast<uint32_t*>(static_cast<char*>(host_stage) + desc_bytes);
-    uint32_t acc = 0;
+    uint32_t* hc = hb + count + 1;  // each request's first chunk
+    uint32_t acc = 0, chunks = 0;
     for (uint32_t i = 0; i < count; ++i) {
         hd[i] = BatchDesc{reqs[i].succ, reqs[i].rank, reqs[i].root, reqs[i].n};
         hb[i] = acc;
+        hc[i] = chunks;
         acc += (uint32_t)reqs[i].n;
+        chunks += (uint32_t)((reqs[i].n + BATCH_CHUNK - 1) / BATCH_CHUNK);
     }
     hb[count] = acc;
+    hc[count] = chunks;
     char* w = carve(ws);
     BatchDesc* dd = reinterpret_cast<BatchDesc*>(w + p.off_batch_desc);
     uint32_t* db = reinterpret_cast<uint32_t*>(w + p.off_batch_bases);
@@ -522,13 +530,15 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     if (hipMemcpyAsync(dd, hd, desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LR_ERR_HIP;
     if (hipMemcpyAsync(db, hb, base_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LR_ERR_HIP;
     if (copy_done && hipEventRecord(*copy_done, st) != hipSuccess) return LR_ERR_HIP;
-    if (run_batch_gather(dd, db, count, (uint32_t)N, concat, st) != hipSuccess) return LR_ERR_HIP;
+    uint8_t* part = reinterpret_cast<uint8_t*>(w + p.off_batch_part);
+    if (run_batch_gather(dd, db, db + count + 1, count, chunks, concat, part, st) != hipSuccess) return LR_ERR_HIP;
     RunArgs a;
     a.plan = &p;
     a.lplan = ps.autol ? &ps.lp : nullptr;
     a.succ = concat;
     a.desc = dd;
     a.bases = db;
+    a.boff = db + count + 1;
     a.count = count;
     for (uint32_t i = 0; i < count; ++i) a.any_root |= reqs[i].root != nullptr;
     a.ws = w;
@@ -546,7 +556,7 @@ extern "C" lr_status lr_rank_batch(const lr_request* reqs, uint32_t count, void*
     if (!reqs) return LR_ERR_INVALID_ARG;
     for (uint32_t i = 0; i < count; ++i)
         if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) return LR_ERR_INVALID_ARG;
-    const size_t need = (size_t)count * sizeof(BatchDesc) + (size_t)(count + 1) * 4;
+    const size_t need = (size_t)count * sizeof(BatchDesc) + batch_table_bytes(count);
     Staging& g = g_stage;
     if (g.pending) {
         if (hipEventSynchronize(g.done) != hipSuccess) return LR_ERR_HIP;

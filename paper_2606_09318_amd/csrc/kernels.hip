@@ -1406,30 +1406,121 @@ __global__ __launch_bounds__(TPB) void k_wy_copy(const typename Lay<W>::Rec* __r
 }
 
 // ----------------------------------------------------------------- batch --
-// concat[g] = base(q) + succ_q[g - base(q)] for the request q owning g;
-// out-of-range successors become terminals (no list leaves its request).
+// One workgroup per chunk of BATCH_CHUNK ids of one request:
+// concat[g] = base(q) + succ_q[g - base(q)]; out-of-range successors become
+// terminals (no list leaves its request). The chunk also sums, for the one-list
+// head test, ids minus successors of non-terminals and counts terminals.
 __global__ __launch_bounds__(TPB) void k_batch_gather(const BatchDesc* __restrict__ d,
-                                                      const uint32_t* __restrict__ bases, uint32_t count,
-                                                      uint32_t total, uint32_t* __restrict__ concat) {
-    const uint32_t lane = lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t ntile = (total + 64 * EXPAND_CH - 1) / (64 * EXPAND_CH);
-    for (uint32_t tile = wave; tile < ntile; tile += nwaves) {
-        const uint32_t base = tile * 64 * EXPAND_CH;
-        if (base + lane >= total) continue;
-        uint32_t q = batch_find(bases, count, base + lane);
-        uint32_t lo = bases[q], hi = bases[q + 1];
-#pragma unroll
-        for (int j = 0; j < EXPAND_CH; ++j) {
-            const uint32_t g = base + j * 64 + lane;
-            if (g < total) {
-                while (g >= hi && q + 1 < count) { ++q; lo = hi; hi = bases[q + 1]; }
-                const uint32_t l = g - lo;
-                const uint32_t s = d[q].succ[l];
-                concat[g] = (s < hi - lo) ? lo + s : g;
-            }
+                                                      const uint32_t* __restrict__ bases,
+                                                      const uint32_t* __restrict__ boff, uint32_t count,
+                                                      uint32_t nchunks, uint32_t* __restrict__ concat,
+                                                      uint2* __restrict__ part) {
+    __shared__ uint64_t shs[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64];
+    for (uint32_t b = blockIdx.x; b < nchunks; b += gridDim.x) {
+        const uint32_t q = batch_find(boff, count, b);  // the request whose chunks hold b
+        const uint32_t lo = bases[q], nq = bases[q + 1] - lo;
+        const uint32_t start = (b - boff[q]) * BATCH_CHUNK;
+        const uint32_t end = min(start + BATCH_CHUNK, nq);
+        const uint32_t* sq = d[q].succ;
+        uint64_t hs = 0;
+        uint32_t nt = 0;
+        for (uint32_t i = start + threadIdx.x; i < end; i += TPB) {
+            const uint32_t s = sq[i];
+            const uint32_t g = lo + i;
+            const uint32_t c = (s < nq) ? lo + s : g;
+            concat[g] = c;
+            if (c == g) { ++nt; hs += g; }
+            else hs += (uint64_t)g - c;
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            hs += __shfl_xor(hs, o);
+            nt += __shfl_xor(nt, o);
+        }
+        if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
+            part[2 * b] = make_uint2((uint32_t)hs, (uint32_t)(hs >> 32));
+            part[2 * b + 1] = make_uint2(nt, 0u);
+        }
+        __syncthreads();  // shs, snt are reused by the next chunk
+    }
+}
+
+// One workgroup per request: its chunks' partial sums -> (head sum, terminals).
+__global__ __launch_bounds__(TPB) void k_batch_reduce(const uint2* __restrict__ part,
+                                                      const uint32_t* __restrict__ boff, uint32_t count,
+                                                      uint2* __restrict__ sums, Gate gate) {
+    if (gate.off()) return;
+    __shared__ uint64_t shs[TPB / 64];
+    __shared__ uint32_t snt[TPB / 64];
+    for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
+        uint64_t hs = 0;
+        uint32_t nt = 0;
+        for (uint32_t b = boff[q] + threadIdx.x; b < boff[q + 1]; b += TPB) {
+            const uint2 h = part[2 * b];
+            hs += (uint64_t)h.x | ((uint64_t)h.y << 32);
+            nt += part[2 * b + 1].x;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            hs += __shfl_xor(hs, o);
+            nt += __shfl_xor(nt, o);
+        }
+        if ((threadIdx.x & 63) == 0) { shs[threadIdx.x >> 6] = hs; snt[threadIdx.x >> 6] = nt; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
+            sums[2 * q] = make_uint2((uint32_t)hs, (uint32_t)(hs >> 32));
+            sums[2 * q + 1] = make_uint2(nt, 0u);
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup, after the whole batch's head-sum pass: if every non-empty
+// request holds exactly one terminal, each is one list whose head is its head
+// sum (the one-list shortcut per request). Then the heads that are not sampled
+// rulers become the level-0 walk list in request order, and the level-0
+// marking and compaction are skipped as for a single list; otherwise nothing
+// changes and the forest path runs.
+__global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ sums,
+                                                      const uint32_t* __restrict__ bases, uint32_t count,
+                                                      Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
+                                                      uint32_t rec_bytes, Gate gate) {
+    if (gate.off()) return;
+    __shared__ uint32_t sh[1024 / 64];
+    int ok = 1;
+    for (uint32_t q = threadIdx.x; q < count; q += 1024) {
+        const uint32_t lo = bases[q], hi = bases[q + 1];
+        if (lo == hi) continue;
+        const uint64_t hs = (uint64_t)sums[2 * q].x | ((uint64_t)sums[2 * q].y << 32);
+        if (sums[2 * q + 1].x != 1 || hs < lo || hs >= hi) ok = 0;
+    }
+    if (!__syncthreads_and(ok)) return;
+    uint32_t run = 0;  // heads written so far
+    for (uint32_t q0 = 0; q0 < count; q0 += 1024) {
+        const uint32_t q = q0 + threadIdx.x;
+        uint32_t h = NONE;
+        if (q < count && bases[q] != bases[q + 1]) {
+            h = sums[2 * q].x;  // < 2^31: the check above
+            if (smp.sampled(h)) h = NONE;
+        }
+        uint32_t tot;
+        const uint32_t pos = run + block_exscan(h != NONE ? 1u : 0u, sh, &tot);
+        if (h != NONE) *reinterpret_cast<uint32_t*>(eb + (size_t)(S + pos) * rec_bytes) = h;
+        run += tot;
+        __syncthreads();  // sh is reused by the next round
+    }
+    if (threadIdx.x == 0) {
+        ctrl->single = 1;
+        ctrl->multi = 0;
+        ctrl->lv[0].H = run;
+        ctrl->lv[0].q = 0;
+        ctrl->chunks = 0;
+        ctrl->conts = 0;
     }
 }
 
@@ -2355,6 +2446,23 @@ static hipError_t run_headsum(const RunArgs& a, const Plan& p, Gate g) {
     return hipGetLastError();
 }
 
+// Batches: after the head-sum pass, the per-request head sums and, when every
+// request is one list, their heads as the level-0 walks (see k_batch_heads).
+static hipError_t run_batch_heads(const RunArgs& a, const Plan& p, Gate g) {
+    if (!a.desc || !a.boff || p.levels == 0) return hipSuccess;
+    hipStream_t st = a.stream;
+    const uint2* part = reinterpret_cast<const uint2*>(a.ws + p.off_batch_part);
+    uint2* sums = reinterpret_cast<uint2*>(a.ws + p.off_batch_sums);
+    const uint32_t grid = std::max(1u, std::min<uint32_t>(a.count, (uint32_t)device_cus() * 8));
+    hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(TPB), 0, st, part, a.boff, a.count, sums, g);
+    LR_TRY(hipGetLastError());
+    const Sampler smp0{(uint32_t)p.m[0], p.log2k[0], p.lseed[0]};
+    hipLaunchKernelGGL(k_batch_heads, dim3(1), dim3(1024), 0, st, sums, a.bases, a.count,
+                       reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl), smp0, a.ws + p.off_eb[0], (uint32_t)p.m[1],
+                       (uint32_t)p.rec_bytes, g);
+    return hipGetLastError();
+}
+
 // Automatic contraction, the device-side guess (sets Ctrl.mode).
 static hipError_t run_guess(const RunArgs& a, const Plan& p, uint32_t thr) {
     const uint32_t n = (uint32_t)p.m[0];
@@ -2395,7 +2503,10 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     // Otherwise: predecessor marks (the one-list case skips these kernels).
     uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
     {
-        if (a.prologue) LR_TRY(run_headsum(a, p, Gate{}));
+        if (a.prologue) {
+            LR_TRY(run_headsum(a, p, Gate{}));
+            LR_TRY(run_batch_heads(a, p, Gate{}));
+        }
         if (p.log0) {
             LR_TRY(run_marks(a, p, hp0, ctrl));
         } else {
@@ -2736,6 +2847,7 @@ static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
     pa.prologue = false;
     pa.gate = Gate{&ctrl->mode, 0u};
     LR_TRY(run_headsum(pa, p, pa.gate));
+    LR_TRY(run_batch_heads(pa, p, pa.gate));
     return run_srs_t<W, WT>(pa, out0);
 }
 
@@ -2812,11 +2924,12 @@ hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted) {
     }
 }
 
-hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, uint32_t count, uint32_t total,
-                            uint32_t* concat, hipStream_t st) {
-    if (!total) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(total, TPB * EXPAND_CH)), dim3(TPB), 0, st, desc, bases, count,
-                       total, concat);
+hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, const uint32_t* boff, uint32_t count,
+                            uint32_t nchunks, uint32_t* concat, uint8_t* part, hipStream_t st) {
+    if (!nchunks) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)device_cus() * 16);
+    hipLaunchKernelGGL(k_batch_gather, dim3(grid), dim3(TPB), 0, st, desc, bases, boff, count, nchunks, concat,
+                       reinterpret_cast<uint2*>(part));
     return hipGetLastError();
 }
 

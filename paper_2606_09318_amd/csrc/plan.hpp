@@ -98,6 +98,12 @@ constexpr uint32_t place_tile_records(bool weighted, bool root) {
     return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * (uint32_t)place_tpb(weighted, root);
 }
 
+// Batches: the concatenation is cut into chunks of BATCH_CHUNK ids that never
+// cross a request, each reducing its request's head sum; the host uploads the
+// request bases and each request's first chunk (two tables of count + 1).
+constexpr uint32_t BATCH_CHUNK = 4096;
+inline size_t batch_table_bytes(uint32_t count) { return 2 * ((size_t)count + 1) * 4; }
+
 struct Plan {
     bool weighted = false;
     uint32_t levels = 0;                   // ruling-set levels before the base case
@@ -115,7 +121,8 @@ struct Plan {
     size_t off_slot[LR_MAX_LEVELS] = {};
     size_t off_eb[LR_MAX_LEVELS] = {};
     size_t off_tile[LR_MAX_LEVELS] = {};
-    size_t off_batch_succ = 0, off_batch_desc = 0, off_batch_bases = 0;
+    size_t off_batch_succ = 0, off_batch_desc = 0, off_batch_bases = 0;  // bases: then the chunk offsets
+    size_t off_batch_part = 0, off_batch_sums = 0;  // per chunk, per request: (head sum, terminals)
     // level 0 in log mode: the chase appends (element, walk, offset) records to
     // a chunked visit log instead of storing at random addresses; after the
     // recursion the records are resolved and grouped by element range in two

@@ -24,6 +24,7 @@ struct RunArgs {
     // batch outputs (rank/root per request) instead of rank/root above
     const BatchDesc* desc = nullptr;
     const uint32_t* bases = nullptr;
+    const uint32_t* boff = nullptr;   // batch: each request's first chunk (BATCH_CHUNK ids), count + 1 entries
     uint32_t count = 0;
     bool any_root = false;            // batch: some request wants roots
     char* ws = nullptr;
@@ -50,9 +51,12 @@ lr_status prefix_sum_records(const uint32_t* succ, const void* weight, int wt, v
 hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted);
 
 // Batch staging: copy the requests' successor arrays into one forest over the
-// concatenated id range (ids shifted by the request's base).
-hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, uint32_t count, uint32_t total,
-                            uint32_t* concat, hipStream_t st);
+// concatenated id range (ids shifted by the request's base), chunk by chunk
+// (boff: each request's first chunk of BATCH_CHUNK ids, nchunks in all); each
+// chunk also writes its request's partial head sum and terminal count (16 B)
+// to part.
+hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, const uint32_t* boff, uint32_t count,
+                            uint32_t nchunks, uint32_t* concat, uint8_t* part, hipStream_t st);
 
 // Validation pass before ranking: range and in-degree check on the input.
 hipError_t run_validate_input(const uint32_t* succ, uint32_t n, uint32_t* counts, uint32_t* err,

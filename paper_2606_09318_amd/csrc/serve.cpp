@@ -10,6 +10,7 @@
 
 #include "device.hpp"
 #include "lr.h"
+#include "plan.hpp"
 #include "sched.hpp"
 
 namespace lr {
@@ -29,7 +30,7 @@ public:
         }
         bytes_ = (cfg_.hbm_budget / cfg_.max_inflight) / 256 * 256;
         const uint32_t mb = cfg_.max_batch ? cfg_.max_batch : 1;
-        stage_cap_ = (size_t)mb * sizeof(BatchDesc) + (size_t)(mb + 1) * 4;
+        stage_cap_ = (size_t)mb * sizeof(BatchDesc) + batch_table_bytes(mb);
         slots_.resize(cfg_.max_inflight);
         for (uint32_t i = 0; i < cfg_.max_inflight; ++i) {
             Slot& s = slots_[i];

@@ -83,6 +83,39 @@ def test_batch_log_mode_without_roots():
         assert np.array_equal(host_u32(r), oracle.rank(L.succ)[1])
 
 
+@pytest.mark.parametrize("with_forest", [False, True])
+def test_batch_of_single_lists_and_a_forest(with_forest):
+    """Every request one list: each request's head comes from its own head
+    sum and no predecessor marks are needed; one request that is a forest of
+    several lists (and an empty request) sends the batch down the marking
+    path. Both against the oracle, in the visit-log path and below it."""
+    sizes = [1 << 20, 5000, 1, (1 << 19) + 7, 0, 70001]
+    items, inputs = [], []
+    for i, n in enumerate(sizes):
+        if n == 0:
+            a = np.zeros(0, np.uint32)
+        elif with_forest and i == 3:
+            a = workloads.forest(n, mean=50, n_long=2, long_len=10000, seed=600 + i).succ
+        else:
+            a = (workloads.random_list(n, seed=600 + i) if i % 2 == 0 else workloads.block_list(n, 4096, seed=600 + i)).succ
+        inputs.append(a)
+        items.append((dev(a) if n else torch.empty(0, dtype=torch.int32, device="cuda"),
+                      torch.full((max(n, 1),), -5, dtype=torch.int32, device="cuda")[:n],
+                      torch.full((max(n, 1),), -5, dtype=torch.int32, device="cuda")[:n]))
+    print(f"case: batch of single lists, forest={with_forest}", flush=True)
+    reqs = lr.requests(items)
+    for flags in (0, lr.LR_VISIT_LOG | lr.LR_NO_LOCAL):
+        o = lr.make_opts(flags=flags)
+        ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items), o))
+        assert lr.lr_rank_batch(reqs, len(items), ws, o) == lr.LR_OK
+        torch.cuda.synchronize()
+        for a, (_, r, t) in zip(inputs, items):
+            if a.size == 0:
+                continue
+            _, er, et, _ = oracle.rank(a)
+            assert np.array_equal(host_u32(r), er) and np.array_equal(host_u32(t), et)
+
+
 def test_batch_forced_levels():
     sizes = [3000, 50000, 1, 70000, 999]
     items, inputs = make_requests(sizes, seed=77)
