@@ -1480,12 +1480,12 @@ __global__ __launch_bounds__(TPB) void k_batch_reduce(const uint2* __restrict__ 
     }
 }
 
-// One workgroup, after the whole batch's head-sum pass: if every non-empty
-// request holds exactly one terminal, each is one list whose head is its head
-// sum (the one-list shortcut per request). Then the heads that are not sampled
-// rulers become the level-0 walk list in request order, and the level-0
-// marking and compaction are skipped as for a single list; otherwise nothing
-// changes and the forest path runs.
+// One workgroup, in place of the head-sum pass for a batch: if every
+// non-empty request holds exactly one terminal, each is one list whose head is
+// its head sum (the one-list shortcut per request). Then the heads that are
+// not sampled rulers become the level-0 walk list in request order, and the
+// level-0 marking and compaction are skipped as for a single list; otherwise
+// the forest path runs.
 __global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ sums,
                                                       const uint32_t* __restrict__ bases, uint32_t count,
                                                       Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
@@ -1499,7 +1499,13 @@ __global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ 
         const uint64_t hs = (uint64_t)sums[2 * q].x | ((uint64_t)sums[2 * q].y << 32);
         if (sums[2 * q + 1].x != 1 || hs < lo || hs >= hi) ok = 0;
     }
-    if (!__syncthreads_and(ok)) return;
+    if (!__syncthreads_and(ok)) {
+        if (threadIdx.x == 0) {
+            ctrl->single = 0;
+            ctrl->multi = 1;
+        }
+        return;
+    }
     uint32_t run = 0;  // heads written so far
     for (uint32_t q0 = 0; q0 < count; q0 += 1024) {
         const uint32_t q = q0 + threadIdx.x;
@@ -2446,10 +2452,10 @@ static hipError_t run_headsum(const RunArgs& a, const Plan& p, Gate g) {
     return hipGetLastError();
 }
 
-// Batches: after the head-sum pass, the per-request head sums and, when every
-// request is one list, their heads as the level-0 walks (see k_batch_heads).
+// Batches, in place of the head-sum pass: the per-request head sums (from
+// the gather pass) and, when every request is one list, their heads as the
+// level-0 walks (see k_batch_heads); else the forest path.
 static hipError_t run_batch_heads(const RunArgs& a, const Plan& p, Gate g) {
-    if (!a.desc || !a.boff || p.levels == 0) return hipSuccess;
     hipStream_t st = a.stream;
     const uint2* part = reinterpret_cast<const uint2*>(a.ws + p.off_batch_part);
     uint2* sums = reinterpret_cast<uint2*>(a.ws + p.off_batch_sums);
@@ -2503,10 +2509,7 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     // Otherwise: predecessor marks (the one-list case skips these kernels).
     uint8_t* hp0 = reinterpret_cast<uint8_t*>(ws + p.off_slot[0]);
     {
-        if (a.prologue) {
-            LR_TRY(run_headsum(a, p, Gate{}));
-            LR_TRY(run_batch_heads(a, p, Gate{}));
-        }
+        if (a.prologue) LR_TRY(a.desc ? run_batch_heads(a, p, Gate{}) : run_headsum(a, p, Gate{}));
         if (p.log0) {
             LR_TRY(run_marks(a, p, hp0, ctrl));
         } else {
@@ -2846,8 +2849,7 @@ static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
     RunArgs pa = a;
     pa.prologue = false;
     pa.gate = Gate{&ctrl->mode, 0u};
-    LR_TRY(run_headsum(pa, p, pa.gate));
-    LR_TRY(run_batch_heads(pa, p, pa.gate));
+    LR_TRY(a.desc ? run_batch_heads(pa, p, pa.gate) : run_headsum(pa, p, pa.gate));
     return run_srs_t<W, WT>(pa, out0);
 }
 
