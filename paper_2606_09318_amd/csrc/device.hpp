@@ -287,17 +287,21 @@ struct OutBatch {
     const uint32_t* bases;
     uint32_t count;
     using L = Lay<false>;
-    struct Cur { uint32_t q, lo, hi; };
+    // the request holding the current element, with its output arrays
+    struct Cur { uint32_t q, lo, hi; uint32_t* rank; uint32_t* root; };
     __device__ __forceinline__ Cur begin(uint32_t g) const {
         const uint32_t q = batch_find(bases, count, g);
-        return {q, bases[q], bases[q + 1]};
+        return {q, bases[q], bases[q + 1], d[q].rank, d[q].root};
     }
     __device__ __forceinline__ void store(Cur& c, uint32_t g, L::Val v, uint32_t r) const {
-        while (g >= c.hi && c.q + 1 < count) { c.q++; c.lo = c.hi; c.hi = bases[c.q + 1]; }
-        const BatchDesc& q = d[c.q];
+        if (g >= c.hi && c.q + 1 < count) {
+            while (g >= c.hi && c.q + 1 < count) { c.q++; c.lo = c.hi; c.hi = bases[c.q + 1]; }
+            c.rank = d[c.q].rank;
+            c.root = d[c.q].root;
+        }
         const uint32_t l = g - c.lo;
-        q.rank[l] = v.c;
-        if (q.root) q.root[l] = r - c.lo;
+        c.rank[l] = v.c;
+        if (c.root) c.root[l] = r - c.lo;
     }
 };
 
