@@ -200,7 +200,11 @@ size_t lr_batch_workspace_bytes(const lr_request* reqs, uint32_t count, const lr
  * requests), so every kernel of the method runs once for the whole batch.
  * `reqs` is a HOST array of `count` descriptors; it is copied into the
  * workspace before the call returns. The sum of the n must be below 2^31.
- * Results are identical to ranking each request alone. */
+ * Results are identical to ranking each request alone. When every request is
+ * one list (exactly one terminal), each request's head comes from its own
+ * streaming sum (the one-list test of Fig. 1's findInit, per request) and no
+ * predecessor marks are computed; a batch with a forest among its requests
+ * marks predecessors over the whole concatenation, which costs more. */
 lr_status lr_rank_batch(const lr_request* reqs, uint32_t count,
                         void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
 
