@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
-    ap.add_argument("--list", choices=["random", "block", "forest", "euler", "batch"], default="random",
+    ap.add_argument("--list", choices=["random", "block", "forest", "euler", "tree", "batch"], default="random",
                     help="with --only-main: the random list, the block-local list of the same size, or the "
                          "2^27 forest with int64 weights (prefix sums, rank and root)")
     ap.add_argument("--no-serve", action="store_true")
@@ -141,8 +141,8 @@ def main():
     if args.list == "forest":
         forest_only(args, stream)
         return
-    if args.list == "euler":
-        euler_only(args, stream)
+    if args.list in ("euler", "tree"):
+        euler_only(args, stream, tree=args.list == "tree")
         return
     if args.list == "batch":
         batch_only(args, stream)
@@ -469,27 +469,40 @@ def locality_bench(n: int, rank, stream, gammas) -> dict:
     return out
 
 
-def euler_only(args, stream):
+def euler_only(args, stream, tree=False):
     """Profiling entry: the Euler tour of a 2^26-vertex random recursive tree
     (2^27 - 2 arcs in random order, +1/-1 int32 weights), lr_prefix_sum with
-    the sums only (they give the depths)."""
+    the sums only (they give the depths); with tree, lr_euler_tree on the same
+    tour (depth, preorder number and subtree size of every vertex)."""
     import numpy as np
     import torch
 
     import paper_2606_09318_amd as lr
     import workloads
 
-    E = workloads.euler_tour(1 << 26, seed=4)
+    V = 1 << 26
+    E = workloads.euler_tour(V, seed=4)
     m = E.succ.size
     succ = torch.from_numpy(E.succ.view(np.int32)).cuda()
-    w = torch.from_numpy(E.weight).cuda()
-    sm = torch.empty(m, dtype=torch.int64, device="cuda")
-    ws = lr.workspace(lr.lr_workspace_bytes(m, lr.LR_W_I32))
+    if tree:
+        dn = torch.from_numpy(E.down_arc.view(np.int32)).cuda()
+        upa = torch.from_numpy(E.up_arc.view(np.int32)).cuda()
+        dv, pv, zv = (torch.empty(V, dtype=torch.int32, device="cuda") for _ in range(3))
+        ws = lr.workspace(lr.lr_euler_tree_workspace_bytes(V))
 
-    def step():
-        st = lr.lr_prefix_sum(succ, w, sm, None, None, ws, None, stream)
-        if st:
-            raise lr.LrError(st, "lr_prefix_sum")
+        def step():
+            st = lr.lr_euler_tree(succ, dn, upa, V, 0, dv, pv, zv, ws, None, stream)
+            if st:
+                raise lr.LrError(st, "lr_euler_tree")
+    else:
+        w = torch.from_numpy(E.weight).cuda()
+        sm = torch.empty(m, dtype=torch.int64, device="cuda")
+        ws = lr.workspace(lr.lr_workspace_bytes(m, lr.LR_W_I32))
+
+        def step():
+            st = lr.lr_prefix_sum(succ, w, sm, None, None, ws, None, stream)
+            if st:
+                raise lr.LrError(st, "lr_prefix_sum")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -500,8 +513,15 @@ def euler_only(args, stream):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    print(json.dumps({"workload": "Euler tour of a 2^26-vertex tree, int32 weights", "ms_per_step": round(ms, 4),
-                      "g_arcs_per_s": round(m / (ms * 1e-3) / 1e9, 3), "list": "euler"}))
+    if tree:
+        if not bool(torch.equal(dv.cpu(), torch.from_numpy(E.depth.view(np.int32)))):
+            raise SystemExit("bench: tree depths do not match the generator's")
+        print(json.dumps({"workload": "tree computations on a 2^26-vertex tree's Euler tour",
+                          "ms_per_step": round(ms, 4), "g_vertices_per_s": round(V / (ms * 1e-3) / 1e9, 3),
+                          "list": "tree"}))
+    else:
+        print(json.dumps({"workload": "Euler tour of a 2^26-vertex tree, int32 weights", "ms_per_step": round(ms, 4),
+                          "g_arcs_per_s": round(m / (ms * 1e-3) / 1e9, 3), "list": "euler"}))
 
 
 def batch_only(args, stream):
