@@ -1284,16 +1284,20 @@ __global__ __launch_bounds__(TPB) void k_pair(const uint32_t* __restrict__ succ,
 // placement passes (ids only) and each range of 2^s2 ids writes its marks
 // from LDS in order. Every id is the target of at most one link, so no range
 // receives more targets than it has ids.
-template <bool VEC>
+// TGT: the input is a plain list of nin target ids below n (entry `skip`
+// excluded) instead of a successor array of n entries.
+template <bool VEC, bool TGT = false>
 __global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_t* __restrict__ succ, uint32_t n, uint32_t s1,
                                                             uint32_t nb1, uint32_t* __restrict__ fill1,
-                                                            PlaceArrays<false> out, Ctrl* ctrl, Gate gate) {
+                                                            PlaceArrays<false> out, Ctrl* ctrl, Gate gate,
+                                                            uint32_t nin = 0, uint32_t skip = NONE) {
     if (gate.off()) return;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<false, false>();
     constexpr int TPB_ = place_tpb(false, false);
     constexpr uint32_t T = PER * TPB_;
-    const uint32_t tiles = (n + T - 1) / T;
+    if constexpr (!TGT) nin = n;
+    const uint32_t tiles = (nin + T - 1) / T;
     // the next tile's successors are loaded while this tile is grouped (the
     // grouping's barriers wait for LDS only)
     uint32_t ns[PER];
@@ -1301,7 +1305,7 @@ __global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
-            ns[j] = (i < n) ? succ[i] : NONE;
+            ns[j] = (i < nin) ? succ[i] : NONE;
         }
     };
     if (blockIdx.x < tiles) load_tile(blockIdx.x);
@@ -1312,7 +1316,8 @@ __global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_
         for (int j = 0; j < PER; ++j) {
             const uint32_t i = tile * T + j * TPB_ + threadIdx.x;
             const uint32_t s = ns[j];
-            xs[j] = (s != i && s < n) ? s : NONE;  // the target of a link
+            if constexpr (TGT) xs[j] = (i != skip && s < n) ? s : NONE;  // a target id
+            else xs[j] = (s != i && s < n) ? s : NONE;                  // the target of a link
             bs[j] = xs[j] >> s1;
         }
         if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);
@@ -1322,6 +1327,9 @@ __global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_
 
 // One workgroup per fine range: the range's targets set bytes in LDS, then
 // the range's marks are written in order (all n bytes get written).
+// WEIGHTS: write +1 for a marked id and -1 for the others (as int8) instead
+// of 1 / 0.
+template <bool WEIGHTS = false>
 __global__ __launch_bounds__(place_tpb(false, false)) void k_mark3(const uint32_t* __restrict__ tx, uint32_t n, uint32_t s2,
                                                             uint32_t nb2, const uint32_t* __restrict__ fill2,
                                                             uint8_t* __restrict__ hp, Gate gate) {
@@ -1351,9 +1359,12 @@ __global__ __launch_bounds__(place_tpb(false, false)) void k_mark3(const uint32_
         __syncthreads();
         if ((len & 3) == 0) {
             uint32_t* hw = reinterpret_cast<uint32_t*>(hp + base);
-            for (uint32_t i = threadIdx.x; i < len / 4; i += TPB_) hw[i] = mk[i];
+            // bytes 1 -> 0x01 and 0 -> 0xFF: each byte times 0xFE stays in its byte
+            for (uint32_t i = threadIdx.x; i < len / 4; i += TPB_)
+                hw[i] = WEIGHTS ? 0xFFFFFFFFu - mk[i] * 0xFEu : mk[i];
         } else {
-            for (uint32_t i = threadIdx.x; i < len; i += TPB_) hp[base + i] = mb[i];
+            for (uint32_t i = threadIdx.x; i < len; i += TPB_)
+                hp[base + i] = WEIGHTS ? (mb[i] ? 0x01 : 0xFF) : mb[i];
         }
         __syncthreads();
     }
@@ -2420,9 +2431,49 @@ static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl*
     hipLaunchKernelGGL((k_place2<false, false, false>), dim3(grid_for(n, T)), tpb, l2, st, P, ctrl, n, p.s1, p.s2,
                        fill2, Q, nullptr, fill1, mg);
     LR_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_mark3, dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), tpb, (size_t)1 << p.s2,
-                       st, Q.x, n, p.s2, p.nb2, fill2, hp0, mg);
+    hipLaunchKernelGGL(k_mark3<false>, dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), tpb,
+                       (size_t)1 << p.s2, st, Q.x, n, p.s2, p.nb2, fill2, hp0, mg);
     return hipGetLastError();
+}
+
+// Euler-tour arc weights (+1 for the down arcs named in `down`, -1 for the
+// rest) without one random byte store per vertex: the down arcs' ids are
+// grouped by range with the predecessor-mark passes and every 8192-id range
+// writes its weights from LDS in order. Uses the grouping arrays of the
+// workspace of the prefix sum that follows (weighted, m elements), which are
+// free until that call; *done stays false when its plan has none (no visit
+// log at this size) and the caller scatters instead.
+hipError_t tree_arc_weights(const uint32_t* down, uint32_t V, uint32_t root, int8_t* w, uint32_t m, void* ws,
+                            const lr_opts* opts, hipStream_t st, bool* done) {
+    *done = false;
+    PlanSet ps;
+    if (make_plans(m, true, opts, 0, &ps) != LR_OK) return hipSuccess;
+    const Plan& p = ps.p;
+    if (!p.log0 || p.levels == 0) return hipSuccess;
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + ALIGN - 1) / ALIGN * ALIGN);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + p.off_ctrl);
+    uint32_t* fill1 = reinterpret_cast<uint32_t*>(base + p.off_fill);
+    uint32_t* fill2 = fill1 + 2 * (size_t)p.nb1 * FILL_LINE;
+    LR_TRY(fill(fill1, fill_words(p.nb1, p.nb2) * 4, 0u, st));
+    const PlaceArrays<false> P = place_arrays<false>(base, p.off_p);
+    const PlaceArrays<false> Q = place_arrays<false>(base, p.off_log);
+    constexpr uint32_t T = place_tile_records(false, false);
+    const dim3 tpb(place_tpb(false, false));
+    const size_t l1 = place_lds_bytes(false, false, p.nb1, false);
+    LR_TRY(allow_lds(k_mark1<false, true>, l1));
+    hipLaunchKernelGGL((k_mark1<false, true>), dim3(grid_for(V, T)), tpb, l1, st, down, m, p.s1, p.nb1, fill1, P, ctrl,
+                       Gate{}, V, root);
+    LR_TRY(hipGetLastError());
+    const size_t l2 = place_lds_bytes(false, false, 1u << (p.s1 - p.s2), false);
+    LR_TRY(allow_lds(k_place2<false, false, false>, l2));
+    hipLaunchKernelGGL((k_place2<false, false, false>), dim3(grid_for(m, T)), tpb, l2, st, P, ctrl, m, p.s1, p.s2,
+                       fill2, Q, nullptr, fill1, Gate{});
+    LR_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_mark3<true>, dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), tpb,
+                       (size_t)1 << p.s2, st, Q.x, m, p.s2, p.nb2, fill2, reinterpret_cast<uint8_t*>(w), Gate{});
+    LR_TRY(hipGetLastError());
+    *done = true;
+    return hipSuccess;
 }
 
 // Validation of the input (LR_VALIDATE): range and in-degree counts.

@@ -58,6 +58,11 @@ hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted);
 hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, const uint32_t* boff, uint32_t count,
                             uint32_t nchunks, uint32_t* concat, uint8_t* part, hipStream_t st);
 
+// Euler-tour arc weights by grouping (see kernels.hip); *done false: the
+// caller scatters the weights itself.
+hipError_t tree_arc_weights(const uint32_t* down, uint32_t V, uint32_t root, int8_t* w, uint32_t m, void* ws,
+                            const lr_opts* opts, hipStream_t st, bool* done);
+
 // Validation pass before ranking: range and in-degree check on the input.
 hipError_t run_validate_input(const uint32_t* succ, uint32_t n, uint32_t* counts, uint32_t* err,
                               hipStream_t st);

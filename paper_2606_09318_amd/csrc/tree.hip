@@ -179,14 +179,20 @@ extern "C" lr_status lr_euler_tree(const uint32_t* succ, const uint32_t* down, c
     const bool validate = opts && (opts->flags & LR_VALIDATE);
     lr_opts inner = opts ? *opts : lr_opts{};
     inner.flags &= ~(uint32_t)LR_PROFILE;
-    hipLaunchKernelGGL(k_tree_clear, dim3(tree_grid(m / 4 + 1)), dim3(TREE_TPB), 0, st, w, (uint32_t)m,
-                       validate ? 0u : 0xffffffffu, head);
+    // without validation, large tours get their weights from the grouped
+    // passes (every byte written in order) instead of a random store per vertex
+    bool grouped = false;
+    if (m && !validate &&
+        tree_arc_weights(down, (uint32_t)V, root, w, (uint32_t)m, w0 + t.inner, &inner, st, &grouped) != hipSuccess)
+        return LR_ERR_HIP;
+    hipLaunchKernelGGL(k_tree_clear, dim3(grouped ? 1 : tree_grid(m / 4 + 1)), dim3(TREE_TPB), 0, st, w,
+                       grouped ? 0u : (uint32_t)m, validate ? 0u : 0xffffffffu, head);
     if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
     if (m) {
         if (validate)
             hipLaunchKernelGGL(k_tree_weights<true>, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up,
                                (uint32_t)V, root, (uint32_t)m, w, err);
-        else
+        else if (!grouped)
             hipLaunchKernelGGL(k_tree_weights<false>, dim3(tree_grid(V)), dim3(TREE_TPB), 0, st, down, up,
                                (uint32_t)V, root, (uint32_t)m, w, err);
         if (validate)

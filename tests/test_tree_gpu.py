@@ -65,13 +65,17 @@ def test_modes_and_forced_levels(flags):
     check(parent, opts=lr.make_opts(flags=flags, spacing=(4, 4), base_max=64))
 
 
-def test_optional_outputs_and_other_root():
+@pytest.mark.parametrize("flags", [0, lr.LR_NO_LOCAL | lr.LR_VISIT_LOG])
+def test_optional_outputs_and_other_root(flags):
+    """Output subsets and a root other than vertex 0; with the visit log the
+    arc weights come from the grouped passes, which skip the root's entry."""
     V = 50000
+    opt = lr.make_opts(flags=flags)
     parent = workloads.recursive_tree(V, seed=9)
     E = workloads.tour_of(parent, seed=9)
     _, ed, ep, ez = oracle.tree(parent, 0)
     for mask in [(True, False, False), (False, True, False), (False, False, True), (False, False, False)]:
-        st, outs = gpu_tree(E, 0, None, mask)
+        st, outs = gpu_tree(E, 0, opt, mask)
         assert st == lr.LR_OK
         for o, e in zip(outs, (ed, ep, ez)):
             if o is not None:
@@ -84,7 +88,7 @@ def test_optional_outputs_and_other_root():
     parent2[sigma] = sigma[parent]
     E2 = workloads.EulerInput(E.succ, E.weight, parent2, E.down_arc[np.argsort(sigma)], E.up_arc[np.argsort(sigma)],
                               None)
-    st, (d, p, z) = gpu_tree(E2, r)
+    st, (d, p, z) = gpu_tree(E2, r, opt)
     assert st == lr.LR_OK
     _, d2, _, z2 = oracle.tree(parent2, r)
     assert np.array_equal(d, d2) and np.array_equal(z, z2)
