@@ -182,6 +182,27 @@ lr_status lr_prefix_sum(const uint32_t* succ, const void* weight, lr_wtype w, in
                         uint32_t* rank, uint32_t* root, uint64_t n,
                         void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
 
+/* lr_rank without a caller workspace and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that must not call hipMalloc, harnesses that forbid it). The
+ * workspace is a static device array of LR_NOALLOC_SCRATCH_BYTES (128 MiB)
+ * that each GPU the call runs on holds until the process ends; its device
+ * address is looked up on the first call on a device. The call makes no
+ * hipMalloc, hipFree or other allocating call.
+ *   succ, rank, root, n, opts: as lr_rank. The stream must belong to the
+ *   current device.
+ * Limit: n whose lr_rank workspace (lr_workspace_bytes(n, LR_W_NONE, opts))
+ * exceeds LR_NOALLOC_SCRATCH_BYTES returns LR_ERR_WORKSPACE and does
+ * nothing; with default options that is n above 6,632,960 (about 2^22.7).
+ * LR_PROFILE is rejected with LR_ERR_INVALID_ARG (profiling creates events).
+ * Every call on one GPU uses the same array, and each call rewrites what it
+ * reads: calls that may overlap on one GPU (other streams, other threads)
+ * race and give unspecified results. Calls on one stream are ordered and
+ * safe. */
+#define LR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+lr_status lr_rank_noalloc(const uint32_t* succ, uint32_t* rank, uint32_t* root, uint64_t n,
+                          const lr_opts* opts, void* stream);
+
 /* One unweighted ranking request of a batch. All pointers are device
  * pointers; rank is required, root may be NULL; root ids are local to the
  * request (in [0, n)). */

@@ -69,6 +69,7 @@ def load():
         "lr_plan_query": (st, [u64, st, P(lr_opts), P(lr_plan)]),
         "lr_workspace_bytes": (sz, [u64, st, P(lr_opts)]),
         "lr_rank": (st, [vp, vp, vp, u64, vp, sz, P(lr_opts), vp]),
+        "lr_rank_noalloc": (st, [vp, vp, vp, u64, P(lr_opts), vp]),
         "lr_prefix_sum": (st, [vp, vp, st, vp, vp, vp, u64, vp, sz, P(lr_opts), vp]),
         "lr_batch_workspace_bytes": (sz, [P(lr_request), u32, P(lr_opts)]),
         "lr_rank_batch": (st, [P(lr_request), u32, vp, sz, P(lr_opts), vp]),
@@ -158,6 +159,10 @@ def lr_wyllie_workspace_bytes(n: int, w: int = LR_W_NONE) -> int:
 def lr_rank(succ, rank, root, ws, opts=None, stream=None) -> int:
     return load().lr_rank(_ptr(succ), _ptr(rank), _ptr(root), succ.numel(), _ptr(ws),
                           0 if ws is None else ws.numel() * ws.element_size(), _opts(opts), _stream(stream))
+
+
+def lr_rank_noalloc(succ, rank, root, opts=None, stream=None) -> int:
+    return load().lr_rank_noalloc(_ptr(succ), _ptr(rank), _ptr(root), succ.numel(), _opts(opts), _stream(stream))
 
 
 def lr_prefix_sum(succ, weight, sum_, rank, root, ws, opts=None, stream=None) -> int:
