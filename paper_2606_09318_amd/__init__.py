@@ -60,6 +60,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    # torch's HIP runtime first: the library then binds to that runtime. Loaded
+    # before torch, it would pull in the system runtime, torch would add its
+    # own copy, and torch's streams would be unknown handles to the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, u64, u32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t
     st = ctypes.c_int
