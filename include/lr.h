@@ -334,7 +334,8 @@ lr_status lr_server_create(const lr_server_config* cfg, lr_server** out);
  * valid until the ticket completes). */
 lr_status lr_server_submit(lr_server* s, const lr_request* req, uint64_t* ticket);
 /* 0 = pending, 1 = done (*status and *latency_s, seconds from submit to the
- * server observing completion, are filled), -1 = unknown ticket. */
+ * server observing completion, are filled; the submit time is taken when
+ * lr_server_submit is entered, before any lock), -1 = unknown ticket. */
 int lr_server_poll(lr_server* s, uint64_t ticket, lr_status* status, double* latency_s);
 /* Block until every submitted request has completed. */
 lr_status lr_server_drain(lr_server* s);
@@ -342,7 +343,8 @@ void lr_server_destroy(lr_server* s);
 
 /* Replay a request trace through a server created from cfg: request i is
  * submitted at arrival_s[i] seconds after the start (host clock). Writes
- * each request's latency (submit -> completion) to latency_s[i] and the time
+ * each request's latency (scheduled arrival -> completion observed) to
+ * latency_s[i] and the time
  * from the start to the last completion to *makespan_s; status[i] (may be
  * NULL) receives each request's status. */
 lr_status lr_server_replay(const lr_server_config* cfg, const lr_request* reqs, const double* arrival_s,

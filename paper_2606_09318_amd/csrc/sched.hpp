@@ -3,6 +3,12 @@
 // admits waiting requests (FIFO) into whichever slot is free, as many as fit
 // the slot's workspace, and records each request's completion time.
 // Host-only C++ (no HIP), so it can be tested with a fake executor.
+//
+// Latency is measured from a request's arrival: the time the caller passes
+// to submit (a trace replay passes the scheduled arrival), else the time
+// submit was entered, taken before any lock, so time spent waiting for the
+// scheduler's lock counts. Launches run outside the lock, so submissions and
+// polls never wait for a batch being enqueued.
 #pragma once
 #include <stdint.h>
 
@@ -25,7 +31,8 @@ public:
     virtual size_t slot_bytes() const = 0;
     // Workspace a batch of these requests needs (0 = cannot be served).
     virtual size_t workspace(const lr_request* reqs, uint32_t count) const = 0;
-    // Start a batch on a free slot; returns LR_OK once it is enqueued.
+    // Start a batch on a free slot; returns LR_OK once it is enqueued. Called
+    // from the scheduler's worker thread only, never under its lock.
     virtual lr_status launch(uint32_t slot, const lr_request* reqs, uint32_t count) = 0;
     // 1 = the slot's batch has finished, 0 = still running, -1 = it failed.
     virtual int poll(uint32_t slot) = 0;
@@ -49,14 +56,16 @@ public:
         worker_.join();
     }
 
-    uint64_t submit(const lr_request& r) {
+    // Enqueue a request that arrived at `arrival`.
+    uint64_t submit(const lr_request& r, clock::time_point arrival) {
         std::lock_guard<std::mutex> g(mu_);
         const uint64_t id = tickets_.size();
-        tickets_.push_back(Ticket{r, clock::now(), {}, LR_OK, 0});
+        tickets_.push_back(Ticket{r, arrival, {}, LR_OK, 0});
         queue_.push_back(id);
         cv_.notify_all();
         return id;
     }
+    uint64_t submit(const lr_request& r) { return submit(r, clock::now()); }
 
     int poll(uint64_t id, lr_status* st, double* lat) {
         std::lock_guard<std::mutex> g(mu_);
@@ -100,8 +109,8 @@ private:
         t.t_done = now;
     }
 
-    // One pass: retire finished slots, then fill free slots. Caller holds mu_.
-    bool step() {
+    // Retire finished slots. Caller holds mu_.
+    bool retire() {
         bool progress = false;
         for (uint32_t s = 0; s < busy_.size(); ++s) {
             if (!busy_[s].on) continue;
@@ -114,56 +123,78 @@ private:
             busy_[s].ids.clear();
             progress = true;
         }
+        return progress;
+    }
+
+    // Take the next batch for a free slot off the queue (FIFO, as many as fit
+    // the slot); requests that can never fit are rejected alone. Caller holds
+    // mu_. Returns false when no slot is free or nothing is waiting.
+    bool admit(uint32_t* slot, std::vector<lr_request>* reqs, std::vector<uint64_t>* ids, bool* progress) {
         for (uint32_t s = 0; s < busy_.size() && !queue_.empty(); ++s) {
             if (busy_[s].on) continue;
-            std::vector<lr_request> reqs;
-            std::vector<uint64_t> ids;
+            reqs->clear();
+            ids->clear();
             uint64_t total = 0;
-            while (!queue_.empty() && reqs.size() < max_batch_) {
+            while (!queue_.empty() && reqs->size() < max_batch_) {
                 const uint64_t id = queue_.front();
                 const lr_request& r = tickets_[id].req;
-                reqs.push_back(r);
-                const size_t need = ex_->workspace(reqs.data(), (uint32_t)reqs.size());
+                reqs->push_back(r);
+                const size_t need = ex_->workspace(reqs->data(), (uint32_t)reqs->size());
                 if (need == 0 || need > ex_->slot_bytes() || total + r.n >= (1ull << 31)) {
-                    reqs.pop_back();
-                    if (reqs.empty()) {  // can never be served: reject alone
+                    reqs->pop_back();
+                    if (reqs->empty()) {  // can never be served: reject alone
                         queue_.pop_front();
                         finish(id, LR_ERR_WORKSPACE, clock::now());
-                        progress = true;
+                        *progress = true;
                         continue;
                     }
                     break;
                 }
                 total += r.n;
-                ids.push_back(id);
+                ids->push_back(id);
                 queue_.pop_front();
             }
-            if (reqs.empty()) continue;
-            const lr_status st = ex_->launch(s, reqs.data(), (uint32_t)reqs.size());
-            if (st != LR_OK) {
-                const auto now = clock::now();
-                for (uint64_t id : ids) finish(id, st, now);
-            } else {
-                for (uint64_t id : ids) tickets_[id].state = 1;
-                busy_[s].on = true;
-                busy_[s].ids = std::move(ids);
-                running_ += (uint32_t)busy_[s].ids.size();
-                batches_++;
-            }
-            progress = true;
+            if (reqs->empty()) continue;
+            // the slot and its requests are taken before the lock is released
+            for (uint64_t id : *ids) tickets_[id].state = 1;
+            busy_[s].on = true;
+            busy_[s].ids = *ids;
+            running_ += (uint32_t)ids->size();
+            *slot = s;
+            return true;
         }
-        return progress;
+        return false;
     }
 
     void loop() {
         std::unique_lock<std::mutex> g(mu_);
+        std::vector<lr_request> reqs;
+        std::vector<uint64_t> ids;
         for (;;) {
-            const bool progress = step();
+            bool progress = retire();
+            uint32_t slot = 0;
+            while (admit(&slot, &reqs, &ids, &progress)) {
+                g.unlock();
+                const lr_status st = ex_->launch(slot, reqs.data(), (uint32_t)reqs.size());
+                g.lock();
+                if (st != LR_OK) {  // the batch fails alone; its slot is free again
+                    const auto now = clock::now();
+                    for (uint64_t id : ids) finish(id, st, now);
+                    running_ -= (uint32_t)ids.size();
+                    busy_[slot].on = false;
+                    busy_[slot].ids.clear();
+                } else {
+                    batches_++;
+                }
+                progress = true;
+            }
             if (queue_.empty() && running_ == 0) done_cv_.notify_all();
             if (stop_ && queue_.empty() && running_ == 0) break;
             if (!progress) {
                 if (running_ == 0) {
-                    cv_.wait_for(g, std::chrono::milliseconds(5));
+                    // a timed wait on the system clock (pthread_cond_timedwait,
+                    // which thread sanitizers model); 5 ms either way
+                    cv_.wait_until(g, std::chrono::system_clock::now() + std::chrono::milliseconds(5));
                 } else {  // batches in flight: poll their completion closely
                     g.unlock();
                     std::this_thread::yield();

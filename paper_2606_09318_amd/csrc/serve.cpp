@@ -62,10 +62,15 @@ public:
     lr_status launch(uint32_t i, const lr_request* reqs, uint32_t count) override {
         Slot& s = slots_[i];
         (void)hipSetDevice(dev_);
+        if (s.failed) {  // a failed launch may have left copies from the staging buffer in flight
+            if (hipEventSynchronize(s.done) != hipSuccess) return LR_ERR_HIP;
+            s.failed = false;
+        }
         lr_status st = batch_enqueue(reqs, count, s.ws, bytes_, &cfg_.opts, s.stream, s.stage, stage_cap_, nullptr);
-        if (st != LR_OK) return st;
-        if (hipEventRecord(s.done, s.stream) != hipSuccess) return LR_ERR_HIP;
-        return LR_OK;
+        const bool recorded = hipEventRecord(s.done, s.stream) == hipSuccess;
+        if (st == LR_OK && !recorded) st = LR_ERR_HIP;
+        if (st != LR_OK) s.failed = true;  // the scheduler frees the slot at once
+        return st;
     }
 
     int poll(uint32_t i) override {
@@ -81,6 +86,7 @@ private:
         hipEvent_t done = nullptr;
         void* stage = nullptr;
         char* ws = nullptr;
+        bool failed = false;  // the last launch failed: wait for s.done before reusing the staging
     };
     lr_server_config cfg_{};
     int dev_ = 0;
@@ -153,11 +159,13 @@ lr_status lr_server_replay(const lr_server_config* cfg, const lr_request* reqs, 
             if (due - now > std::chrono::microseconds(300)) std::this_thread::sleep_for(std::chrono::microseconds(100));
             else std::this_thread::yield();
         }
-        st = lr_server_submit(s, &reqs[i], &tickets[i]);
-        if (st != LR_OK) {
+        if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) {
             lr_server_destroy(s);
-            return st;
+            return LR_ERR_INVALID_ARG;
         }
+        // latency counts from the scheduled arrival, so a late submission
+        // (the replay loop itself delayed) is not hidden
+        tickets[i] = s->sched->submit(reqs[i], due);
     }
     s->sched->drain();
     auto last = t0;
