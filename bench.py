@@ -35,6 +35,8 @@ def parse():
                          "2^27 forest with int64 weights (prefix sums, rank and root)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only the CPU oracle on the 2^28 random list itself (1 untimed + 3 timed runs)")
     ap.add_argument("--no-weighted", action="store_true")
     ap.add_argument("--serve-count", type=int, default=4096)
     ap.add_argument("--gamma", type=float, nargs="*", default=[0.0, 0.01, 0.1, 0.3],
@@ -128,6 +130,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4, "reps": 5}))
+        return
+
+    if args.cpu_full:
+        print(json.dumps({"cpu_oracle_2p28": cpu_baseline(28, warmup=1, reps=3)}))
         return
 
     if args.sweep:
@@ -669,7 +675,10 @@ def weighted_bench() -> dict:
 
 def serve_bench(count: int) -> dict:
     """Continuous batching vs one launch sequence per request on the serving
-    trace (Poisson arrivals, sizes log-uniform over 2^10..2^24)."""
+    trace (Poisson arrivals, sizes log-uniform over 2^10..2^24). After every
+    replay all requests are checked against the closed form of their
+    generated order on the device (outputs reset before each replay), and
+    the number of failing requests is reported."""
     import numpy as np
     import torch
 
@@ -677,13 +686,14 @@ def serve_bench(count: int) -> dict:
     import workloads
 
     tr = workloads.serving_trace(count=count, lo_log2=10, hi_log2=24, rate_per_s=1.0, seed=5)
-    items = []
+    items, orders = [], []
     total = 0
     t0 = time.time()
     for q in tr:
         Lq = workloads.request_input(q)
         s = torch.from_numpy(Lq.succ.view(np.int32)).to("cuda:0", non_blocking=False)
         items.append((s, torch.empty(q.n, dtype=torch.int32, device="cuda:0"), None))
+        orders.append(torch.from_numpy(Lq.order.view(np.int32)).to("cuda:0"))
         total += q.n
     gen_s = time.time() - t0
     reqs = lr.requests(items)
@@ -694,73 +704,107 @@ def serve_bench(count: int) -> dict:
         c.hbm_budget, c.max_inflight, c.max_batch = budget, inflight, max_batch
         return c
 
+    def failures() -> int:
+        bad = 0
+        for (_, r, _), o in zip(items, orders):
+            n = r.numel()
+            if not torch.equal(r.index_select(0, o), torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda:0")):
+                bad += 1
+        return bad
+
+    def replay(c, arrivals) -> dict:
+        for _, r, _ in items:
+            r.fill_(-1)
+        torch.cuda.synchronize()
+        st, lat, sts, mk = lr.lr_server_replay(c, reqs, arrivals, count)
+        lat = np.array(lat) * 1e3
+        return {"status_ok": bool(st == 0 and all(x == 0 for x in sts)),
+                "throughput_g_elements_per_s": round(total / mk / 1e9, 3), "makespan_s": round(mk, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "closed_form_failures": failures()}
+
+    def arrivals(rate) -> list:
+        return [q.arrival_s for q in workloads.serving_trace(count=count, lo_log2=10, hi_log2=24, rate_per_s=rate,
+                                                              seed=5)]
+
     torch.cuda.synchronize()
-    # saturation throughput: every request present at t = 0
-    st, lat, sts, mk = lr.lr_server_replay(cfg(2, count), reqs, [0.0] * count, count)
-    sat = total / mk
-    rate = 0.8 * sat / (total / count)
-    arr = [0.0] * count
-    t = 0.0
-    for i, q in enumerate(workloads.serving_trace(count=count, lo_log2=10, hi_log2=24, rate_per_s=rate, seed=5)):
-        arr[i] = q.arrival_s
+    mean_n = total / count
+    # saturation throughputs: every request present at t = 0
+    sat_b = replay(cfg(2, count), [0.0] * count)
+    sat_p = replay(cfg(1, 1), [0.0] * count)
+    sat = total / sat_b["makespan_s"]
+    rate = 0.8 * sat / mean_n
+    arr = arrivals(rate)
     res = {"requests": count, "total_elements": total, "offered_rate_req_per_s": round(rate, 1),
            "hbm_budget_gib": budget >> 30, "saturation_g_elements_per_s": round(sat / 1e9, 3),
-           "input_generation_s": round(gen_s, 1)}
-    for name, c in (("batched", cfg(2, count)), ("per_request", cfg(1, 1))):
-        st, lat, sts, mk = lr.lr_server_replay(c, reqs, arr, count)
-        lat = np.array(lat) * 1e3
-        res[name] = {"status_ok": bool(st == 0 and all(s == 0 for s in sts)),
-                     "throughput_g_elements_per_s": round(total / mk / 1e9, 3), "makespan_s": round(mk, 3),
-                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+           "saturation_per_request_g_elements_per_s": sat_p["throughput_g_elements_per_s"],
+           "saturation_runs": {"batched": sat_b, "per_request": sat_p},
+           "input_generation_s": round(gen_s, 1),
+           "latency": "host clock from each request's scheduled arrival to the server seeing it complete",
+           "correctness": "closed_form_failures = requests whose ranks differ from the closed form of "
+                          "their generated order, all requests checked after every replay"}
+    res["batched"] = replay(cfg(2, count), arr)
+    res["per_request"] = replay(cfg(1, 1), arr)
+    # a load both servers sustain: 0.7 x the per-request saturation, so the
+    # latencies compare at equal throughput
+    rate_eq = 0.7 * (sat_p["throughput_g_elements_per_s"] * 1e9) / mean_n
+    arr_eq = arrivals(rate_eq)
+    res["equal_load"] = {"offered_rate_req_per_s": round(rate_eq, 1),
+                         "offered_g_elements_per_s": round(rate_eq * mean_n / 1e9, 3),
+                         "batched": replay(cfg(2, count), arr_eq), "per_request": replay(cfg(1, 1), arr_eq)}
     # offered-load sweep for the batched server (same trace, arrival times scaled)
     res["load_sweep"] = []
     for load in (0.5, 0.7, 0.9, 1.1):
-        scale = 0.8 / load
-        st, lat, sts, mk = lr.lr_server_replay(cfg(2, count), reqs, [a * scale for a in arr], count)
-        lat = np.array(lat) * 1e3
-        res["load_sweep"].append({"load": load, "status_ok": bool(st == 0 and all(s == 0 for s in sts)),
-                                  "throughput_g_elements_per_s": round(total / mk / 1e9, 3),
-                                  "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                                  "p99_ms": round(float(np.percentile(lat, 99)), 3)})
-    # spot check: a few requests against their closed form
-    for i in range(0, count, max(1, count // 16)):
-        Lq = workloads.request_input(tr[i])
-        r = items[i][1].cpu().numpy().view(np.uint32)
-        expect = np.empty(tr[i].n, np.uint32)
-        expect[Lq.order] = np.arange(tr[i].n - 1, -1, -1, dtype=np.uint32)
-        if not np.array_equal(r, expect):
-            res["closed_form_ok"] = False
-            break
-    else:
-        res["closed_form_ok"] = True
-    del items
+        r = replay(cfg(2, count), [a * 0.8 / load for a in arr])
+        r["load"] = load
+        res["load_sweep"].append(r)
+    res["closed_form_failures_total"] = sum(x["closed_form_failures"] for x in
+                                            [sat_b, sat_p, res["batched"], res["per_request"],
+                                             res["equal_load"]["batched"], res["equal_load"]["per_request"]]
+                                            + res["load_sweep"])
+    del items, orders
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline() -> dict:
-    """The oracle as it stands (sequential pointer chasing, one thread) on a
-    bounded sample of the same workload: one random list of 2^25 elements."""
+def cpu_baseline(log2n: int = 26, warmup: int = 0, reps: int = 1) -> dict:
+    """The oracle as it stands (sequential pointer chasing, one thread) on the
+    random-list workload's generator (seed 2, stream 0): by default a bounded
+    sample of 2^26 elements, one run; --cpu-full runs the 2^28 list itself."""
+    import numpy as np
+
     import oracle
     import workloads
 
-    n = 1 << 25
+    n = 1 << log2n
     L = workloads.random_list(n, seed=2, stream=0)
-    t0 = time.perf_counter()
-    st, r, t, _ = oracle.rank(L.succ, want=("rank", "root"))
-    dt = time.perf_counter() - t0
-    assert st == 0
+    ts = []
+    for i in range(warmup + reps):
+        t0 = time.perf_counter()
+        st, r, t, _ = oracle.rank(L.succ, want=("rank", "root"))
+        dt = time.perf_counter() - t0
+        assert st == 0
+        if i >= warmup:
+            ts.append(dt)
+        print(json.dumps({"cpu_oracle_run": i, "n": n, "seconds": round(dt, 2), "timed": i >= warmup}),
+              file=sys.stderr, flush=True)
+    expect = np.empty(n, np.uint32)
+    expect[L.order] = np.arange(n - 1, -1, -1, dtype=np.uint32)
+    assert np.array_equal(r, expect)
     model = None
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": round(n / dt / 1e9, 5), "unit": "G elements/s", "cores": 1, "kind": "oracle",
-            "sample": "one random list of 2^25 elements from the same generator, one run, rank + root",
-            "seconds": round(dt, 2), "host_cpu": model, "host_nproc": os.cpu_count(),
-            "build": "gcc -O3 -march=native"}
+    med = float(np.median(ts))
+    what = "the 2^28 random list itself" if log2n == 28 else f"a random list of 2^{log2n} elements"
+    return {"value": round(n / med / 1e9, 5), "unit": "G elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} from the same generator (seed 2), rank + root, {warmup} untimed + {reps} timed "
+                      f"run(s), median",
+            "seconds": {"median": round(med, 2), "min": round(min(ts), 2), "max": round(max(ts), 2)},
+            "host_cpu": model, "host_nproc": os.cpu_count(), "build": "gcc -O3 -march=native"}
 
 
 if __name__ == "__main__":

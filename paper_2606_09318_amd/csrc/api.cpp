@@ -320,6 +320,8 @@ static lr_status check_base_lds(const Plan& p) {
     const uint64_t mL = p.m[p.levels];
     if (base_lds_bytes(mL, p.weighted) > device_max_lds()) return LR_ERR_UNSUPPORTED;
     if (p.log0 && ((size_t)1 << p.s2) * (p.weighted ? 16 : 8) > device_max_lds()) return LR_ERR_UNSUPPORTED;
+    // the grouping tiles' LDS is sized for at most PLACE_MAX_RANGES ranges per pass
+    if (p.log0 && (p.nb1 > PLACE_MAX_RANGES || (1u << (p.s1 - p.s2)) > PLACE_MAX_RANGES)) return LR_ERR_UNSUPPORTED;
     return LR_OK;
 }
 

@@ -63,6 +63,8 @@ constexpr uint32_t CHASE_GRAB = 64;  // walks a wavefront takes from the pool at
 #ifndef LR_XCD_GROUPS
 #define LR_XCD_GROUPS 1   // second grouping pass: the tiles of one coarse range on one XCD
 #endif
+static_assert(CHASE_TPB % 64 == 0 && CHASE_TPB >= 64 && CHASE_TPB <= 1024, "chase workgroup width");
+static_assert(LR_CHASE_POOL >= 0 && LR_CHASE_POOL < 16, "pool share of the walks, in sixteenths");
 
 // ------------------------------------------------------------------ fill --
 __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,

@@ -98,6 +98,36 @@ constexpr uint32_t place_tile_records(bool weighted, bool root) {
     return (weighted ? LR_PLACE_PER / 2 : LR_PLACE_PER) * (uint32_t)place_tpb(weighted, root);
 }
 
+// Compile-time limits of the tuning overrides above, so a variant built with
+// -DNAME=VALUE that cannot launch fails here and not at run time. LDS: gfx950
+// gives one workgroup at most 160 KiB. A grouping tile holds T records (4 B
+// element + 4 B rank [+ 4 B root] [+ 8 B sum]) and two 4 B counters per range
+// of its pass; the plan keeps every pass at most 2^11 ranges (split of the
+// fan-out over two passes up to 2^31 elements).
+constexpr size_t LDS_MAX = 160 * 1024;
+constexpr uint32_t PLACE_MAX_RANGES = 1u << 11;
+constexpr size_t place_tile_lds(bool weighted, bool root) {
+    return (size_t)place_tile_records(weighted, root) * (8 + (root ? 4 : 0) + (weighted ? 8 : 0)) + 8 +
+           8 * (size_t)PLACE_MAX_RANGES;
+}
+static_assert(LR_PLACE_TPB % 64 == 0 && LR_PLACE_TPB >= 64 && LR_PLACE_TPB <= 1024, "grouping workgroup width");
+static_assert(LR_PLACE_TPB_ROOT % 64 == 0 && LR_PLACE_TPB_ROOT >= 64 && LR_PLACE_TPB_ROOT <= 1024,
+              "grouping workgroup width (roots, weights)");
+static_assert(LR_PLACE_PER >= 2 && LR_PLACE_PER % 2 == 0, "records per lane (halved for weighted records)");
+static_assert(place_tile_lds(false, false) <= LDS_MAX && place_tile_lds(false, true) <= LDS_MAX &&
+                  place_tile_lds(true, false) <= LDS_MAX && place_tile_lds(true, true) <= LDS_MAX,
+              "a grouping tile must fit one workgroup's LDS: lower LR_PLACE_PER or the workgroup width");
+static_assert(PLACE_FINE_SHIFT >= 10 && ((size_t)1 << PLACE_FINE_SHIFT) * 16 <= LDS_MAX,
+              "a fine placement range (4 B rank + 4 B root + 8 B sum per id) must fit one workgroup's LDS");
+static_assert(LOG_CHUNK >= 256 && (LOG_CHUNK & (LOG_CHUNK - 1)) == 0,
+              "a visit-log chunk takes at least two steps of a wavefront (64 walks x 2 per lane)");
+static_assert(LR_LOCAL_GUESS_16THS <= LR_LOCAL_AUTO_16THS && LR_LOCAL_AUTO_16THS <= 16,
+              "the contracted path's guess threshold lies within its capacity");
+static_assert(LR_SPAWN_K0 >= 2 && LR_SPAWN_K0 <= 4096 && (LR_SPAWN_K0 & (LR_SPAWN_K0 - 1)) == 0 &&
+                  LR_SPAWN_CAP >= 1 && LR_SPAWN_K2 >= 2,
+              "spawning spacing and cap");
+static_assert(LR_PLACE_COARSE_BIAS <= 4 && LR_PLACE_COARSE_BIAS_W <= 4, "fan-out bias");
+
 // Batches: the concatenation is cut into chunks of BATCH_CHUNK ids that never
 // cross a request, each reducing its request's head sum; the host uploads the
 // request bases and each request's first chunk (two tables of count + 1).

@@ -7,9 +7,10 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2606_09318_amd as lr
 import workloads
-from gpu_util import certificate_gpu, dev
+from gpu_util import certificate_gpu, dev, host_u32
 
 pytestmark = pytest.mark.gpu
 
@@ -111,18 +112,37 @@ def test_euler_tour_2p26_depths():
 
 
 def test_euler_tree_2p26():
-    """Tree computations on the 2^26-vertex random recursive tree: depth equals
-    the parent recurrence; sizes and preorder satisfy the tree invariants
-    (checked on the device)."""
+    """Tree computations on the 2^26-vertex random recursive tree, every vertex
+    checked twice: against the oracle's depth-first traversal, and against a
+    complete certificate evaluated on the device (children in ascending id
+    order): depth(v) = depth(parent) + 1, size(v) = 1 + the sizes of v's
+    children, preorder(first child of v) = preorder(v) + 1 and
+    preorder(next sibling) = preorder(sibling) + size(sibling). These
+    equations, with the root's depth 0 and preorder 0, have exactly one
+    solution, so passing them is exactness without the oracle."""
     V = 1 << 26
     print(f"case: euler tree V={V}", flush=True)
     E = workloads.euler_tour(V, seed=4)
     d, p, z = lr.euler_tree(dev(E.succ), dev(E.down_arc), dev(E.up_arc), 0)
     torch.cuda.synchronize()
-    assert torch.equal(d, dev(E.depth))
+    st, ed, ep, ez = oracle.tree(E.parent, 0)
+    assert st == 0
+    assert np.array_equal(host_u32(d), ed)
+    assert np.array_equal(host_u32(p), ep)
+    assert np.array_equal(host_u32(z), ez)
+    # the certificate, on the device
     par = dev(E.parent).long()
     nr = torch.arange(V, device="cuda") != 0
-    pl, zl, dl = p.long(), z.long(), d.long()
-    assert int(zl.sum()) == int((dl + 1).sum()) and int(z[0]) == V and int(p[0]) == 0
-    assert bool((pl[nr] > pl[par[nr]]).all()) and bool((pl[nr] < pl[par[nr]] + zl[par[nr]]).all())
-    assert torch.equal(torch.sort(p).values, torch.arange(V, dtype=torch.int32, device="cuda"))
+    dl, pl, zl = d.long(), p.long(), z.long()
+    assert int(d[0]) == 0 and int(p[0]) == 0
+    assert torch.equal(dl[nr], dl[par[nr]] + 1)
+    child_sum = torch.zeros(V, dtype=torch.int64, device="cuda").index_add_(0, par[nr], zl[nr])
+    assert torch.equal(zl, child_sum + 1)
+    kids = torch.nonzero(nr).squeeze(1)
+    kids = kids[torch.argsort(par[kids] * V + kids)]      # children grouped by parent, ascending ids
+    kp = par[kids]
+    first = torch.ones_like(kp, dtype=torch.bool)
+    first[1:] = kp[1:] != kp[:-1]
+    assert torch.equal(pl[kids[first]], pl[kp[first]] + 1)
+    nxt, prev = kids[1:][~first[1:]], kids[:-1][~first[1:]]
+    assert torch.equal(pl[nxt], pl[prev] + zl[prev])
