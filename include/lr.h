@@ -83,6 +83,19 @@ enum {
  * 2^28 elements a record is one 64-bit word (element, walk, offset; a walk
  * whose offset outgrows its field goes on under a continuation id, see
  * log_off_bits), above 2^28 three 32-bit words. */
+/* Walk cap and bounded fallback: how long a walk runs depends on where the
+ * next sampled ruler sits in list order (Section 2.2: the longest sublist
+ * decides the number of rounds). On an order unrelated to the sampling the
+ * walks at spacing k are about geometric with mean k; an order built against
+ * the sampling (every sampled ruler placed after all other elements, say)
+ * would make one walk cover almost the whole list. Every walk therefore
+ * stops after 64 k steps; if any does, the call ranks its input by pointer
+ * doubling with J-fold jumps per round (J = 128 up to 2^21 elements, at most
+ * 3 rounds; J = 16 above, at most 8 rounds), independent of the order, with
+ * identical results. The fallback's kernels are enqueued with every call and
+ * return at once when no walk was capped (a few microseconds per call);
+ * lr_profile_last reports whether it ran. Under LR_VALIDATE a cycle reached
+ * by a walk is reported through the same fallback. */
 /* Ruler spawning (Section 2.2): the first level is chased in two rounds. The
  * walks of the sampled rulers and heads stop after 2k steps, each marking the
  * element it would have taken next; then new rulers are spawned at every such
@@ -289,9 +302,12 @@ lr_status lr_autotune(const uint32_t* succ, const void* weight, lr_wtype w, uint
  * LR_PROFILE on this thread: [0] predecessor marks, [1] head compaction,
  * [2] level-0 chase, [3] upper levels, base case and their propagation,
  * [4] level-0 record resolution and first grouping pass (0 for inputs
- * without the visit log), [5] level-0 propagation to the outputs, [6] total.
- * Synchronises on the recorded events. Returns the number of values
- * written. */
+ * without the visit log), [5] level-0 propagation to the outputs, [6] total,
+ * [7] 1 if the call ran the bounded fallback (a walk reached its step cap,
+ * see below), else 0 (read from the device: the workspace must still hold
+ * the call's state). Synchronises on the recorded events. Returns the number
+ * of values written. The phase times of a call that ran the fallback cover
+ * the stopped ruling-set path; [6] then excludes the fallback's rounds. */
 int lr_profile_last(double* ms, int cap);
 
 /* Device calibration (diagnostic, not part of any ranking call): on the

@@ -227,8 +227,10 @@ def lr_autotune(succ, weight, ws, base=None, stream=None):
 
 
 def lr_profile_last() -> list[float]:
-    buf = (ctypes.c_double * 7)()
-    k = load().lr_profile_last(buf, 7)
+    """Phase times (ms) of the last LR_PROFILE call on this thread, then 1.0
+    if that call ran the bounded fallback, else 0.0."""
+    buf = (ctypes.c_double * 8)()
+    k = load().lr_profile_last(buf, 8)
     return list(buf[:k])
 
 

@@ -259,6 +259,13 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         q->log0 = use_log(q->m[0], q->levels, o);
         off = std::max(off, layout_levels(q, layout_local(q, n, body)));
     }
+    // the bounded fallback (a walk reached its step cap): two record arrays
+    // over the input, after the common header
+    if (p->levels >= 1 || spawn) {
+        p->off_fb = body;
+        off = std::max(off, body + 2 * align_up((size_t)n * p->rec_bytes + 16));
+        ps->lp.off_fb = body;
+    }
     if (batch_count) {
         p->batch_count = batch_count;
         p->off_batch_succ = off;
@@ -288,8 +295,15 @@ lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_
 struct ProfState {
     hipEvent_t ev[EV_COUNT] = {};
     bool made = false, valid = false;
+    const uint32_t* mode = nullptr;  // the profiled call's path word (device), null without walks
 };
 static thread_local ProfState g_prof;
+
+// The profiled call's path word, for lr_profile_last (plans with walks only).
+static void prof_capped(const RunArgs& a, const Plan& p) {
+    if (a.ev) g_prof.mode = (p.levels >= 1 || p.spawn) ? &reinterpret_cast<const Ctrl*>(a.ws + p.off_ctrl)->mode
+                                                        : nullptr;
+}
 
 static hipEvent_t* prof_events(bool on) {
     if (!on) return nullptr;
@@ -307,10 +321,12 @@ static char* carve(void* ws) { return reinterpret_cast<char*>(align_up(reinterpr
 static lr_status finish(hipError_t e, const RunArgs& a, const Plan& p) {
     if (e != hipSuccess) return LR_ERR_HIP;
     if (a.validate) {
-        uint32_t err = 0;
-        const Ctrl* c = reinterpret_cast<const Ctrl*>(a.ws + p.off_ctrl);
-        if (hipMemcpyAsync(&err, &c->err, 4, hipMemcpyDeviceToHost, a.stream) != hipSuccess) return LR_ERR_HIP;
+        Ctrl c{};
+        if (hipMemcpyAsync(&c, a.ws + p.off_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, a.stream) != hipSuccess)
+            return LR_ERR_HIP;
         if (hipStreamSynchronize(a.stream) != hipSuccess) return LR_ERR_HIP;
+        const bool walks = p.levels >= 1 || p.spawn;
+        const uint32_t err = (walks && c.mode == MODE_FALLBACK) ? (c.err & (ERR_INPUT | ERR_FALLBACK_CYCLE)) : c.err;
         if (err) return LR_ERR_BAD_LIST;
     }
     return LR_OK;
@@ -349,6 +365,7 @@ static lr_status rank_common(const uint32_t* succ, const void* weight, int wt, b
     a.stream = static_cast<hipStream_t>(stream);
     a.validate = opts && (opts->flags & LR_VALIDATE);
     a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
+    prof_capped(a, p);
     return finish(run_srs(a), a, p);
 }
 
@@ -547,6 +564,7 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     a.stream = st;
     a.validate = opts && (opts->flags & LR_VALIDATE);
     a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
+    prof_capped(a, p);
     return finish(run_srs(a), a, p);
 }
 
@@ -586,8 +604,11 @@ extern "C" int lr_profile_last(double* ms, int cap) {
     for (int i = 1; i < EV_COUNT; ++i) (void)hipEventElapsedTime(&v[i], g_prof.ev[i - 1], g_prof.ev[i]);
     float total = 0;
     (void)hipEventElapsedTime(&total, g_prof.ev[0], g_prof.ev[EV_COUNT - 1]);
-    double out[7] = {v[EV_DETECT], v[EV_HEADS], v[EV_CHASE0], v[EV_UPPER], v[EV_PART], v[EV_EXPAND], total};
-    int k = std::min(cap, 7);
+    uint32_t mode = MODE_PLAIN;
+    if (cap > 7 && g_prof.mode && hipMemcpy(&mode, g_prof.mode, 4, hipMemcpyDeviceToHost) != hipSuccess) return 0;
+    double out[8] = {v[EV_DETECT], v[EV_HEADS], v[EV_CHASE0], v[EV_UPPER], v[EV_PART], v[EV_EXPAND], total,
+                     mode == MODE_FALLBACK ? 1.0 : 0.0};
+    int k = std::min(cap, 8);
     for (int i = 0; i < k; ++i) ms[i] = out[i];
     return k;
 }

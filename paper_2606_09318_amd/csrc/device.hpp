@@ -35,7 +35,8 @@ struct Ctrl {
     uint64_t hsum;                          // level 0: sum of ids minus sum of successors of non-terminals
     uint32_t dm[MAXL + 1];                  // element count per level when sizes are known only on the
                                             // device (the contracted list of tile-local contraction)
-    uint32_t mode;                          // automatic contraction: 0 plain path, 1 tile-local contraction
+    uint32_t mode;                          // the path that runs (MODE_*): set by each path's first
+                                            // kernels, MODE_FALLBACK once a walk reached its cap
     uint32_t multi;                         // plain path with more than one list: predecessor marks needed
     uint32_t spn;                           // ruler spawning: number of spawned rulers
     uint32_t conts;                         // packed visit log: continuation ids handed out
@@ -43,14 +44,40 @@ struct Ctrl {
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
-// Device-side choice between two enqueued kernel sequences: a kernel whose
-// gate is set runs only when the word it points to holds `want`, and
+// Device-side choice between enqueued kernel sequences: a kernel whose gate
+// is set runs only when the word it points to (Ctrl.mode) holds `want`, and
 // otherwise returns before touching memory. A null gate always runs.
 struct Gate {
     const uint32_t* p;
     uint32_t want;
     __device__ __forceinline__ bool off() const { return p && *p != want; }
 };
+
+// Values of Ctrl.mode: the path whose kernels run. Each path's first kernels
+// set it (the automatic choice between plain and contracted path included),
+// and a walk that reaches its step cap turns it to MODE_FALLBACK, so every
+// later kernel of the path returns and only the fallback runs.
+enum : uint32_t { MODE_PLAIN = 0, MODE_LOCAL = 1, MODE_FALLBACK = 2, MODE_SPAWN = 3 };
+
+// Ctrl.err bits (LR_VALIDATE): the input check sets ERR_INPUT (an index out
+// of range, two predecessors); the ranking path's consistency checks set
+// others; the fallback sets ERR_FALLBACK_CYCLE for a path that never reaches
+// a terminal. After a fallback only ERR_INPUT and ERR_FALLBACK_CYCLE count:
+// a path stopped by a cap leaves inconsistent state behind.
+constexpr uint32_t ERR_INPUT = 1u | 2u;
+constexpr uint32_t ERR_FALLBACK_CYCLE = 256u;
+
+// Walk step cap: a walk at level spacing k stops after WALK_CAP_MULT * k
+// steps. On a list whose order is independent of the sampling, walk lengths
+// are about geometric with mean k, so R walks exceed the cap with
+// probability about R * e^-64 (never, in practice); only an order built
+// against the sampling reaches it. The fallback then ranks the input by
+// pointer doubling, whose rounds do not depend on the order.
+// A walk that outgrows its level (a cycle: input that is not a forest) is
+// stopped the same way; the fallback then reports it under LR_VALIDATE.
+// Spacings are at most 2^12, so the cap fits 32 bits.
+constexpr uint32_t WALK_CAP_MULT = 64;
+__device__ __forceinline__ uint32_t walk_cap(uint32_t m, uint32_t log2k) { return min(m, WALK_CAP_MULT << log2k); }
 
 // Visit log of the level-0 chase (log mode): one record (element, walk,
 // offset) per visited element, in one of two formats.
@@ -180,6 +207,7 @@ struct SrcIn {
     const void* weight;
     uint32_t m;
     using L = Lay<W>;
+    static constexpr bool kLinks = true;  // every record is one link: a walk's count is its step count
     __device__ __forceinline__ void load(uint32_t x, uint32_t& nxt, typename L::Val& v) const {
         const uint32_t s = succ[x];
         int64_t w = 1;
@@ -204,6 +232,7 @@ struct SrcPair {
     const PairRec<WT>* r;
     uint32_t m;
     using L = Lay<true>;
+    static constexpr bool kLinks = true;
     __device__ __forceinline__ void load(uint32_t x, uint32_t& nxt, typename L::Val& v) const {
         const PairRec<WT> p = r[x];
         const bool t = (p.s == x) | (p.s >= m);
@@ -217,6 +246,7 @@ struct SrcLvl {
     const typename Lay<W>::Rec* e;
     uint32_t m;
     using L = Lay<W>;
+    static constexpr bool kLinks = false;  // records are segments: counts exceed step counts
     __device__ __forceinline__ void load(uint32_t x, uint32_t& nxt, typename L::Val& v) const {
         const typename L::Rec r = e[x];
         nxt = r.nxt;

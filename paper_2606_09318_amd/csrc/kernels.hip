@@ -219,7 +219,7 @@ __global__ __launch_bounds__(TPB) void k_ldecide(const uint32_t* __restrict__ pa
 // initial-element walk; multi says whether predecessor marks are needed.
 __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restrict__ partial, uint32_t nparts,
                                                        Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
-                                                       uint32_t rec_bytes, int lvl, Gate gate) {
+                                                       uint32_t rec_bytes, int lvl, uint32_t mode, Gate gate) {
     if (gate.off()) return;
     uint64_t hs = 0;
     uint32_t nt = 0;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restric
         for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
         ctrl->nterm = nt;
         ctrl->hsum = hs;
-        ctrl->mode = 0;
+        if (mode != NONE) ctrl->mode = mode;
         const bool single = nt == 1 && hs < smp.m;
         ctrl->single = single ? 1u : 0u;
         ctrl->multi = single ? 0u : 1u;
@@ -461,8 +461,12 @@ __device__ __forceinline__ void pad_chunk(const LogArrays<W>& lg, uint32_t cbase
 //
 // NW walks per lane: the lane issues the loads of all its walks before it
 // uses any of them, so NW independent gathers are in flight per lane.
+// At most 80 scalar registers: the persistent grid is 8 waves per SIMD, and
+// waves allocated 96 scalar registers (the next granule) measured 1.5-2 %
+// slower at 2^28 elements, although the compiler's occupancy estimate is 8
+// either way.
 template <bool W, class Src, int LOG, int NW>
-__global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint32_t S, Ctrl* ctrl, int lvl,
+__global__ __launch_bounds__(CHASE_TPB) __attribute__((amdgpu_num_sgpr(80))) void k_chase(Src src, Sampler smp, uint32_t S, Ctrl* ctrl, int lvl,
                                                      typename Lay<W>::Slot* __restrict__ slot,
                                                      typename Lay<W>::Rec* __restrict__ eb,
                                                      uint8_t* __restrict__ hp_next, uint32_t refill,
@@ -474,6 +478,7 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
     const uint32_t lane = lane_id();
     const uint32_t total = S + ctrl->lv[lvl].H;
     const uint32_t m = smp.m;
+    const uint32_t cap = walk_cap(m, smp.log2k);
     uint32_t w[NW], x[NW], steps[NW];
     Val off[NW];
 #pragma unroll
@@ -656,9 +661,14 @@ __global__ __launch_bounds__(CHASE_TPB) void k_chase(Src src, Sampler smp, uint3
                 w[k] = NONE;
             } else {
                 off[k] = L::add(off[k], v[k]);
-                if (++steps[k] >= m) {              // longer than the level: input has a cycle
+                // steps so far: on the input level every record is one link,
+                // so the walk's count is its step count and no counter is kept
+                uint32_t walked;
+                if constexpr (Src::kLinks) walked = off[k].c;
+                else walked = ++steps[k];
+                if (walked >= cap) {                // too long (or a cycle): the bounded fallback takes over
                     eb[w[k]] = L::rec(TERM | IDX, off[k]);
-                    atomicOr(&ctrl->err, 8u);
+                    ctrl->mode = MODE_FALLBACK;
                     w[k] = NONE;
                 } else if (smp.sampled(nxt[k])) {   // reached the next ruler
                     const uint32_t c = nxt[k] >> smp.log2k;
@@ -1418,6 +1428,61 @@ __global__ __launch_bounds__(TPB) void k_wy_copy(const typename Lay<W>::Rec* __r
     }
 }
 
+// ------------------------------------------------------------- fallback --
+// The bounded fallback, run only when a walk of the ruling-set path reached
+// its step cap (an order built against the sampling): pointer doubling with
+// J-fold jumps per round, so a round follows up to J - 1 records and
+// ceil(log_J n) rounds reach every terminal, whatever the order. A record
+// (nxt, value) spans its value's links from its element to nxt; nxt =
+// TERM | t once the path has reached its terminal t. Every kernel of the
+// fallback is enqueued with every call and returns at once unless the cap
+// was hit, so the rounds are few: J = 128 up to 2^21 elements (at most 3
+// rounds), 16 above (at most 8).
+constexpr uint32_t FB_GRID_PER_CU = 2;
+
+// One round: compose up to J consecutive records (the first round reads the
+// input itself). The last round writes the outputs; with err set, a path
+// that has not reached a terminal (a cycle) is reported.
+template <bool W, bool FIRST, bool LAST, class Src, class Out>
+__global__ __launch_bounds__(TPB) void k_fb_round(Src src, const typename Lay<W>::Rec* __restrict__ a,
+                                                  typename Lay<W>::Rec* __restrict__ b, uint32_t m, uint32_t J,
+                                                  Out out, uint32_t* err, Gate gate) {
+    if (gate.off()) return;
+    using L = Lay<W>;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    typename Out::Cur cur = out.begin(i);
+    for (; i < m; i += stride) {
+        typename L::Val acc;
+        uint32_t j;
+        if constexpr (FIRST) src.load(i, j, acc);  // a terminal t: TERM | t, value 0
+        else {
+            const typename L::Rec r = a[i];
+            acc = L::val(r);
+            j = r.nxt;
+        }
+        for (uint32_t t = 1; t < J && !(j & TERM); ++t) {
+            typename L::Val v;
+            uint32_t nj;
+            if constexpr (FIRST) src.load(j, nj, v);
+            else {
+                const typename L::Rec q = a[j];
+                v = L::val(q);
+                nj = q.nxt;
+            }
+            acc = L::add(acc, v);
+            j = nj;
+        }
+        if constexpr (LAST) {
+            if (!(j & TERM) && err) atomicOr(err, ERR_FALLBACK_CYCLE);
+            out.store(cur, i, acc, j & IDX);
+        } else {
+            b[i] = L::rec(j, acc);
+        }
+    }
+}
+
 // ----------------------------------------------------------------- batch --
 // One workgroup per chunk of BATCH_CHUNK ids of one request:
 // concat[g] = base(q) + succ_q[g - base(q)]; out-of-range successors become
@@ -1516,6 +1581,7 @@ __global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ 
         if (threadIdx.x == 0) {
             ctrl->single = 0;
             ctrl->multi = 1;
+            ctrl->mode = MODE_PLAIN;
         }
         return;
     }
@@ -1536,6 +1602,7 @@ __global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ 
     if (threadIdx.x == 0) {
         ctrl->single = 1;
         ctrl->multi = 0;
+        ctrl->mode = MODE_PLAIN;
         ctrl->lv[0].H = run;
         ctrl->lv[0].q = 0;
         ctrl->chunks = 0;
@@ -1756,14 +1823,17 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
 // contracted list's size and the sizes of the ruling-set levels above it.
 struct LevelShifts { uint8_t lg[MAXL]; };
 
+// forced: the contracted path runs alone and this kernel sets its mode
 __global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, uint32_t ntiles, Ctrl* ctrl,
-                                                  uint32_t levels, LevelShifts ks, uint32_t cap, Gate gate) {
+                                                  uint32_t levels, LevelShifts ks, uint32_t cap, uint32_t forced,
+                                                  Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
     const uint32_t total = wg_exscan_inplace(cnt, ntiles, sh);
     if (threadIdx.x == 0) {
+        if (forced) ctrl->mode = MODE_LOCAL;
         if (total > cap) {  // the guess was wrong: more than the contracted levels hold
-            ctrl->mode = 0;  // every later kernel of this path returns; the plain path runs
+            ctrl->mode = MODE_PLAIN;  // every later kernel of this path returns; the plain path runs
             return;
         }
         cnt[ntiles] = total;
@@ -1897,6 +1967,7 @@ __global__ __launch_bounds__(TPB) void k_lc_expand(const uint32_t* __restrict__ 
 // Slots: all ones = free; (walk, offset) = reached; SPF | walk = a phase-1
 // cap target (before the spawn pass) or a spawned ruler (after it).
 constexpr uint32_t SPF = TERM;        // slot flag: cap target / spawned ruler
+constexpr uint32_t LOG2_SPAWN_K2 = 31 - __builtin_clz((unsigned)LR_SPAWN_K2);  // second chase: mean walk 2^this
 constexpr int SP_TPB = 256;
 
 // Every slot free (all ones), and the control words of the path reset.
@@ -1907,6 +1978,7 @@ __global__ __launch_bounds__(TPB) void k_sp_prep(uint32_t* __restrict__ slotw, u
         ctrl->spn = 0;
         ctrl->single = 0;
         ctrl->multi = 0;
+        ctrl->mode = MODE_SPAWN;
     }
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n4 = words / 4;
@@ -2084,9 +2156,10 @@ __global__ __launch_bounds__(SP_TPB) void k_sp_chase2(SrcIn<W, WT> src, Sampler 
     const uint32_t per = R2 / nwave + 1;
     uint32_t cursor = T0 + (uint32_t)min<uint64_t>((uint64_t)gwave * per, R2);
     const uint32_t whi = T0 + (uint32_t)min<uint64_t>((uint64_t)(gwave + 1) * per, R2);
-    uint32_t w = NONE, x = 0, nxt = 0;
+    uint32_t w = NONE, x = 0, nxt = 0, steps = 0;
     Val v = L::zero(), off = L::zero();
     bool fresh = false;  // walk just started: the record of x is not loaded yet
+    const uint32_t cap = walk_cap(m, LOG2_SPAWN_K2);
     for (;;) {
         const uint64_t idle = __ballot(w == NONE);
         if (idle == ~0ull && cursor >= whi) break;
@@ -2100,6 +2173,7 @@ __global__ __launch_bounds__(SP_TPB) void k_sp_chase2(SrcIn<W, WT> src, Sampler 
                     x = s0;
                     off = L::zero();
                     fresh = true;
+                    steps = 0;
                 } else {
                     lrec[my] = L::rec(TERM | IDX, L::zero());
                     atomicOr(&ctrl->err, 8u);
@@ -2139,6 +2213,11 @@ __global__ __launch_bounds__(SP_TPB) void k_sp_chase2(SrcIn<W, WT> src, Sampler 
             off = o2;
             nxt = ln;
             v = lv;
+            if (++steps >= cap) {                   // the bounded fallback takes over
+                lrec[w] = L::rec(TERM | IDX, o2);
+                ctrl->mode = MODE_FALLBACK;
+                w = NONE;
+            }
         } else if (sw & SPF) {                      // a spawned ruler: the walk ends on it
             const uint32_t c = sw & IDX;
             lrec[w] = L::rec(c, o2);
@@ -2501,7 +2580,7 @@ static hipError_t run_headsum(const RunArgs& a, const Plan& p, Gate g) {
     const Sampler smp0{n, p.log2k[0], p.lseed[0]};
     hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs,
                        reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl), smp0, a.ws + p.off_eb[0], (uint32_t)p.m[1],
-                       (uint32_t)p.rec_bytes, 0, g);
+                       (uint32_t)p.rec_bytes, 0, (uint32_t)MODE_PLAIN, g);
     return hipGetLastError();
 }
 
@@ -2756,12 +2835,16 @@ static hipError_t run_local_t(const RunArgs& a, Out0 out0) {
     uint8_t* hp0 = Lv ? reinterpret_cast<uint8_t*>(ws + p.off_slot[0]) : nullptr;
     const uint32_t gc = LR_LC_GRID_PER_CU ? std::min<uint32_t>(p.lc_ntiles, (uint32_t)device_cus() * LR_LC_GRID_PER_CU)
                                           : p.lc_ntiles;
+    // alone (forced), the path's mode is set by the scan: the kernels up to it
+    // run ungated
+    const Gate gpre = a.prologue ? Gate{} : g;
     hipLaunchKernelGGL((k_lc_chain<W, WT>), dim3(gc), dim3(LC_TPB), 0, st, a.succ, a.weight, n, p.lc_ntiles, cnt, dir,
-                       stage, pos, wd, ctrl, g);
+                       stage, pos, wd, ctrl, gpre);
     LR_TRY(hipGetLastError());
     LevelShifts ks{};
     for (uint32_t l = 0; l < Lv; ++l) ks.lg[l] = (uint8_t)p.log2k[l];
-    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks, (uint32_t)p.m[0], g);
+    hipLaunchKernelGGL(k_lc_scan, dim3(1), dim3(1024), 0, st, cnt, p.lc_ntiles, ctrl, Lv, ks, (uint32_t)p.m[0],
+                       (uint32_t)a.prologue, gpre);
     LR_TRY(hipGetLastError());
     rec_ev(a, EV_DETECT);
     if (hp0) {
@@ -2811,7 +2894,7 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
     {
         const uint64_t words = (uint64_t)n * p.rec_bytes / 4;
         hipLaunchKernelGGL(k_sp_prep, dim3(grid_for(words, TPB * 4)), dim3(TPB), 0, st,
-                           reinterpret_cast<uint32_t*>(slot), words, ctrl, g);
+                           reinterpret_cast<uint32_t*>(slot), words, ctrl, Gate{});
         LR_TRY(hipGetLastError());
     }
     {  // one list: its head from the streaming sum, and no predecessor marks
@@ -2822,7 +2905,7 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
         else hipLaunchKernelGGL(k_headsum<false>, dim3(gs), dim3(TPB), 0, st, a.succ, n, part, g);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_headsum_final, dim3(1), dim3(TPB), 0, st, part, gs, ctrl, smp,
-                           reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, SPL, g);
+                           reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, SPL, NONE, g);
         LR_TRY(hipGetLastError());
     }
     LR_TRY(fill(hp_in, n, 0u, st, ctrl, g));
@@ -2886,7 +2969,7 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
 // taken. Both paths are enqueued and the one not chosen returns from every
 // kernel at once (no host synchronisation, so the call stays capturable).
 template <bool W, int WT, class Out0>
-static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
+static hipError_t run_path_t(const RunArgs& a, Out0 out0) {
     if (a.plan->spawn) return run_spawn_t<W, WT>(a, out0);
     if (!a.lplan) return a.plan->local ? run_local_t<W, WT>(a, out0) : run_srs_t<W, WT>(a, out0);
     const Plan& p = *a.plan;
@@ -2897,13 +2980,69 @@ static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
     RunArgs la = a;
     la.plan = a.lplan;
     la.prologue = false;
-    la.gate = Gate{&ctrl->mode, 1u};
+    la.gate = Gate{&ctrl->mode, MODE_LOCAL};
     LR_TRY((run_local_t<W, WT>(la, out0)));  // its scan falls back to mode 0 if the list is too long
     RunArgs pa = a;
     pa.prologue = false;
-    pa.gate = Gate{&ctrl->mode, 0u};
+    pa.gate = Gate{&ctrl->mode, MODE_PLAIN};
     LR_TRY(a.desc ? run_batch_heads(pa, p, pa.gate) : run_headsum(pa, p, pa.gate));
     return run_srs_t<W, WT>(pa, out0);
+}
+
+// The bounded fallback over the input (see k_fb_round); every kernel returns
+// at once unless some walk reached its cap.
+template <bool W, int WT, class Out0>
+static hipError_t run_fallback_t(const RunArgs& a, Out0 out0) {
+    using L = Lay<W>;
+    using Src = SrcIn<W, WT>;
+    const Plan& p = *a.plan;
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);
+    const uint64_t n64 = p.spawn ? p.sp_n : (p.local ? p.lc_n : p.m[0]);
+    const uint32_t n = (uint32_t)n64;
+    const Gate g{&ctrl->mode, MODE_FALLBACK};
+    auto* A = reinterpret_cast<typename L::Rec*>(a.ws + p.off_fb);
+    auto* B = reinterpret_cast<typename L::Rec*>(a.ws + p.off_fb + (n64 * sizeof(typename L::Rec) + 16 + ALIGN - 1) /
+                                                                     ALIGN * ALIGN);
+    const uint32_t grid = std::min(grid_for(n, TPB * 4), (uint32_t)device_cus() * FB_GRID_PER_CU);
+    const uint32_t J = n64 <= (1ull << 21) ? 128u : 16u;
+    uint32_t rounds = 1;
+    for (uint64_t span = J; span < n64; span *= J) ++rounds;
+    const Src src{a.succ, a.weight, n};
+    uint32_t* err = a.validate ? &ctrl->err : nullptr;
+    for (uint32_t r = 0; r < rounds; ++r) {
+        const bool first = r == 0, last = r + 1 == rounds;
+        if (first && last)
+            hipLaunchKernelGGL((k_fb_round<W, true, true, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A, B,
+                               n, J, out0, err, g);
+        else if (first)
+            hipLaunchKernelGGL((k_fb_round<W, true, false, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A,
+                               B, n, J, out0, err, g);
+        else if (last)
+            hipLaunchKernelGGL((k_fb_round<W, false, true, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A,
+                               B, n, J, out0, err, g);
+        else
+            hipLaunchKernelGGL((k_fb_round<W, false, false, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A,
+                               B, n, J, out0, err, g);
+        LR_TRY(hipGetLastError());
+        std::swap(A, B);  // the round's output is the next round's input
+    }
+    return hipSuccess;
+}
+
+// Every path's first kernels set Ctrl.mode and a capped walk turns it to
+// MODE_FALLBACK; the fallback runs after the path and returns at once unless
+// that happened. A path that runs alone has no gates (a gate costs every
+// kernel a dependent load): after a cap it runs on to its end, bounded (every
+// walk stops at its cap, every other kernel is bounded whatever its input),
+// and the fallback then overwrites its outputs. Under automatic contraction
+// both paths are gated on the mode anyway, so they stop at once. A plan
+// without levels (the base case alone) has no walks and no fallback.
+template <bool W, int WT, class Out0>
+static hipError_t run_any_t(const RunArgs& a, Out0 out0) {
+    const Plan& p = *a.plan;
+    const bool walks = p.levels >= 1 || p.spawn;
+    LR_TRY((run_path_t<W, WT>(a, out0)));
+    return walks ? run_fallback_t<W, WT>(a, out0) : hipSuccess;
 }
 
 template <int WT>

@@ -148,6 +148,8 @@ struct Plan {
     // workspace layout (byte offsets)
     size_t off_ctrl = 0;
     size_t off_hsum = 0;                   // HEADSUM_BLOCKS x 16 B partial sums
+    size_t off_fb = 0;                     // the bounded fallback's two record arrays (over every path's
+                                           // arrays, which are dead when it runs)
     size_t off_slot[LR_MAX_LEVELS] = {};
     size_t off_eb[LR_MAX_LEVELS] = {};
     size_t off_tile[LR_MAX_LEVELS] = {};

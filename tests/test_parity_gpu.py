@@ -199,7 +199,8 @@ def test_profile_phases():
     st, _, _ = gpu_rank(L.succ, lr.make_opts(flags=lr.LR_PROFILE))
     assert st == 0
     ms = lr.lr_profile_last()
-    assert len(ms) == 7 and all(x >= 0 for x in ms) and ms[6] > 0
+    assert len(ms) == 8 and all(x >= 0 for x in ms) and ms[6] > 0
+    assert ms[7] == 0.0  # an ordinary random list never needs the fallback
     torch.cuda.synchronize()
 
 
