@@ -232,8 +232,11 @@ size_t lr_batch_workspace_bytes(const lr_request* reqs, uint32_t count, const lr
 /* Rank many independent requests in one pass: the requests are treated as one
  * forest over the concatenation of their index ranges (lists never cross
  * requests), so every kernel of the method runs once for the whole batch.
- * `reqs` is a HOST array of `count` descriptors; it is copied into the
- * workspace before the call returns. The sum of the n must be below 2^31.
+ * `reqs` is a HOST array of `count` descriptors; they reach the device as
+ * kernel arguments (96 per launch of a small table-writing kernel), so the
+ * array may be reused as soon as the call returns, the call never
+ * synchronises (without LR_VALIDATE) and it can be captured into a HIP graph.
+ * The sum of the n must be below 2^31.
  * Results are identical to ranking each request alone. When every request is
  * one list (exactly one terminal), each request's head comes from its own
  * streaming sum (the one-list test of Fig. 1's findInit, per request) and no
@@ -241,6 +244,34 @@ size_t lr_batch_workspace_bytes(const lr_request* reqs, uint32_t count, const lr
  * marks predecessors over the whole concatenation, which costs more. */
 lr_status lr_rank_batch(const lr_request* reqs, uint32_t count,
                         void* ws, size_t ws_bytes, const lr_opts* opts, void* stream);
+
+/* A batch captured once as a HIP graph and replayed with other requests.
+ * The graph is planned for a capacity: at most max_requests requests and
+ * max_elements elements in all per launch. Every launch writes the request
+ * table on the device from kernel arguments (one small kernel per 96
+ * requests) and replays the graph; its kernels read the actual sizes from
+ * the device, so any requests within the capacity run with the same graph
+ * and give the same results as lr_rank_batch (the plain path: no automatic
+ * contraction). The graph is bound to the workspace given at creation (at
+ * least lr_batch_graph_workspace_bytes); launches of one graph must not
+ * overlap (stream-ordered launches on one stream are fine); device buffers
+ * of the requests must stay valid until the launch completes. Options: no
+ * LR_VALIDATE, LR_PROFILE, LR_SPAWN or LR_LOCAL (LR_ERR_INVALID_ARG). A
+ * launch over the capacity returns LR_ERR_WORKSPACE; a request with a root
+ * output on a graph created without want_root returns LR_ERR_INVALID_ARG.
+ * Creation captures on a stream of its own and synchronises nothing else;
+ * launches never synchronise. */
+typedef struct lr_batch_graph lr_batch_graph;
+typedef struct lr_batch_graph_config {
+    uint64_t max_elements;   /* most elements over the requests of one launch (< 2^31) */
+    uint32_t max_requests;   /* most requests of one launch */
+    uint32_t want_root;      /* nonzero: requests may ask for root outputs */
+    lr_opts opts;            /* ruler spacings, base size, seed, ... for every launch */
+} lr_batch_graph_config;
+size_t lr_batch_graph_workspace_bytes(const lr_batch_graph_config* cfg);
+lr_status lr_batch_graph_create(const lr_batch_graph_config* cfg, void* ws, size_t ws_bytes, lr_batch_graph** out);
+lr_status lr_batch_graph_launch(lr_batch_graph* g, const lr_request* reqs, uint32_t count, void* stream);
+void lr_batch_graph_destroy(lr_batch_graph* g);
 
 /* GPU baseline: Wyllie pointer doubling over the whole input (Section 1,
  * Section 2.6: pointer doubling, ceil(log2 n) rounds of
@@ -343,6 +374,12 @@ typedef struct lr_server_config {
     uint32_t max_inflight;    /* concurrent batches (streams), >= 1 */
     uint32_t max_batch;       /* most requests per batch (1 = one launch per request) */
     lr_opts opts;             /* options for every batch */
+    uint32_t graphs;          /* nonzero: a batch replays a captured lr_batch_graph of its
+                                 size bucket (capacities 2^(j/2) elements from 2^16 on,
+                                 max_batch requests; captured per slot on first use);
+                                 batches whose bucket does not fit a slot, or options a
+                                 graph cannot take, are enqueued as lr_rank_batch */
+    uint32_t pad;
 } lr_server_config;
 
 lr_status lr_server_create(const lr_server_config* cfg, lr_server** out);

@@ -47,6 +47,11 @@ class lr_request(ctypes.Structure):
 
 class lr_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("opts", lr_opts), ("graphs", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class lr_batch_graph_config(ctypes.Structure):
+    _fields_ = [("max_elements", ctypes.c_uint64), ("max_requests", ctypes.c_uint32), ("want_root", ctypes.c_uint32),
                 ("opts", lr_opts)]
 
 
@@ -86,6 +91,10 @@ def load():
         "lr_calibrate_workspace_bytes": (sz, []),
         "lr_calibrate": (st, [vp, sz, P(ctypes.c_double), st, vp]),
         "lr_euler_tree": (st, [vp, vp, vp, u64, u32, vp, vp, vp, vp, sz, P(lr_opts), vp]),
+        "lr_batch_graph_workspace_bytes": (sz, [P(lr_batch_graph_config)]),
+        "lr_batch_graph_create": (st, [P(lr_batch_graph_config), vp, sz, P(vp)]),
+        "lr_batch_graph_launch": (st, [vp, P(lr_request), u32, vp]),
+        "lr_batch_graph_destroy": (None, [vp]),
         "lr_server_create": (st, [P(lr_server_config), P(vp)]),
         "lr_server_submit": (st, [vp, P(lr_request), P(u64)]),
         "lr_server_poll": (st, [vp, u64, P(st), P(ctypes.c_double)]),
@@ -203,6 +212,48 @@ def lr_batch_workspace_bytes(reqs: ctypes.Array, count: int, opts=None) -> int:
 def lr_rank_batch(reqs: ctypes.Array, count: int, ws, opts=None, stream=None) -> int:
     return load().lr_rank_batch(reqs, count, _ptr(ws), ws.numel() * ws.element_size(), _opts(opts),
                                 _stream(stream))
+
+
+def batch_graph_config(max_elements: int, max_requests: int, want_root: bool = False,
+                       opts: lr_opts | None = None) -> lr_batch_graph_config:
+    c = lr_batch_graph_config()
+    c.max_elements, c.max_requests, c.want_root = max_elements, max_requests, int(want_root)
+    if opts is not None:
+        c.opts = opts
+    return c
+
+
+def lr_batch_graph_workspace_bytes(cfg: lr_batch_graph_config) -> int:
+    return int(load().lr_batch_graph_workspace_bytes(ctypes.byref(cfg)))
+
+
+class BatchGraph:
+    """lr_batch_graph: a batch captured once as a HIP graph (for a capacity of
+    requests and elements) and replayed with other requests. The workspace
+    tensor is kept alive with the graph."""
+
+    def __init__(self, cfg: lr_batch_graph_config, ws):
+        self.ws = ws
+        h = ctypes.c_void_p()
+        s = load().lr_batch_graph_create(ctypes.byref(cfg), _ptr(ws), ws.numel() * ws.element_size(),
+                                         ctypes.byref(h))
+        if s:
+            raise LrError(s, "lr_batch_graph_create")
+        self.h = h
+
+    def launch(self, reqs: ctypes.Array, count: int, stream=None) -> int:
+        return load().lr_batch_graph_launch(self.h, reqs, count, _stream(stream))
+
+    def close(self):
+        if self.h:
+            load().lr_batch_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lr_euler_tree_workspace_bytes(V: int, opts: lr_opts | None = None) -> int:

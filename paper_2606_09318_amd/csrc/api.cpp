@@ -274,6 +274,8 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         off += align_up((size_t)batch_count * sizeof(BatchDesc));
         p->off_batch_bases = off;
         off += align_up(batch_table_bytes(batch_count));
+        p->off_batch_hdr = off;
+        off += align_up(sizeof(BatchHdr));
         p->off_batch_part = off;  // at most n / BATCH_CHUNK + one partial chunk per request
         off += align_up(((size_t)n / BATCH_CHUNK + batch_count + 1) * 16);
         p->off_batch_sums = off;
@@ -491,27 +493,11 @@ size_t lr_batch_workspace_bytes(const lr_request* reqs, uint32_t count, const lr
 
 namespace lr {
 
-// Staging of the request table: a per-thread pinned host buffer; before it is
-// rewritten, the copy that last read it must have completed.
-struct Staging {
-    void* host = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-    ~Staging() {
-        if (pending && done) (void)hipEventSynchronize(done);
-        if (host) (void)hipHostFree(host);
-        if (done) (void)hipEventDestroy(done);
-    }
-};
-static thread_local Staging g_stage;
-
-// Enqueue a batch whose request table is already built on the host.
+// Enqueue a batch: the request table is written on the device from kernel
+// arguments (no host staging, no synchronisation), then the method runs once
+// over the concatenation.
 lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t ws_bytes, const lr_opts* opts,
-                        hipStream_t st, void* host_stage, size_t host_cap, hipEvent_t* copy_done);
-
-lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t ws_bytes, const lr_opts* opts,
-                        hipStream_t st, void* host_stage, size_t host_cap, hipEvent_t* copy_done) {
+                        hipStream_t st) {
     uint64_t N = 0;
     for (uint32_t i = 0; i < count; ++i) {
         if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) return LR_ERR_INVALID_ARG;
@@ -526,38 +512,18 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     if (!ws || ws_bytes < p.total) return LR_ERR_WORKSPACE;
     if ((s = check_base_lds(p)) != LR_OK) return s;
     if (ps.autol && (s = check_base_lds(ps.lp)) != LR_OK) return s;
-    const size_t desc_bytes = (size_t)count * sizeof(BatchDesc);
-    const size_t base_bytes = batch_table_bytes(count);
-    if (host_cap < desc_bytes + base_bytes) return LR_ERR_INVALID_ARG;
-    BatchDesc* hd = static_cast<BatchDesc*>(host_stage);
-    uint32_t* hb = reinterpret_cast<uint32_t*>(static_cast<char*>(host_stage) + desc_bytes);
-    uint32_t* hc = hb + count + 1;  // each request's first chunk
-    uint32_t acc = 0, chunks = 0;
-    for (uint32_t i = 0; i < count; ++i) {
-        hd[i] = BatchDesc{reqs[i].succ, reqs[i].rank, reqs[i].root, reqs[i].n};
-        hb[i] = acc;
-        hc[i] = chunks;
-        acc += (uint32_t)reqs[i].n;
-        chunks += (uint32_t)((reqs[i].n + BATCH_CHUNK - 1) / BATCH_CHUNK);
-    }
-    hb[count] = acc;
-    hc[count] = chunks;
+    uint32_t chunks = 0;
+    for (uint32_t i = 0; i < count; ++i) chunks += (uint32_t)((reqs[i].n + BATCH_CHUNK - 1) / BATCH_CHUNK);
     char* w = carve(ws);
-    BatchDesc* dd = reinterpret_cast<BatchDesc*>(w + p.off_batch_desc);
-    uint32_t* db = reinterpret_cast<uint32_t*>(w + p.off_batch_bases);
-    uint32_t* concat = reinterpret_cast<uint32_t*>(w + p.off_batch_succ);
-    if (hipMemcpyAsync(dd, hd, desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LR_ERR_HIP;
-    if (hipMemcpyAsync(db, hb, base_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LR_ERR_HIP;
-    if (copy_done && hipEventRecord(*copy_done, st) != hipSuccess) return LR_ERR_HIP;
-    uint8_t* part = reinterpret_cast<uint8_t*>(w + p.off_batch_part);
-    if (run_batch_gather(dd, db, db + count + 1, count, chunks, concat, part, st) != hipSuccess) return LR_ERR_HIP;
+    if (run_batch_table(reqs, count, p, w, false, chunks, st) != hipSuccess) return LR_ERR_HIP;
     RunArgs a;
     a.plan = &p;
     a.lplan = ps.autol ? &ps.lp : nullptr;
-    a.succ = concat;
-    a.desc = dd;
-    a.bases = db;
-    a.boff = db + count + 1;
+    a.succ = reinterpret_cast<const uint32_t*>(w + p.off_batch_succ);
+    a.desc = reinterpret_cast<const BatchDesc*>(w + p.off_batch_desc);
+    a.bases = reinterpret_cast<const uint32_t*>(w + p.off_batch_bases);
+    a.boff = a.bases + count + 1;
+    a.bhdr = reinterpret_cast<const BatchHdr*>(w + p.off_batch_hdr);
     a.count = count;
     for (uint32_t i = 0; i < count; ++i) a.any_root |= reqs[i].root != nullptr;
     a.ws = w;
@@ -574,27 +540,122 @@ extern "C" lr_status lr_rank_batch(const lr_request* reqs, uint32_t count, void*
                                    const lr_opts* opts, void* stream) {
     if (count == 0) return LR_OK;
     if (!reqs) return LR_ERR_INVALID_ARG;
-    for (uint32_t i = 0; i < count; ++i)
-        if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) return LR_ERR_INVALID_ARG;
-    const size_t need = (size_t)count * sizeof(BatchDesc) + batch_table_bytes(count);
-    Staging& g = g_stage;
-    if (g.pending) {
-        if (hipEventSynchronize(g.done) != hipSuccess) return LR_ERR_HIP;
-        g.pending = false;
-    }
-    if (g.cap < need) {
-        if (g.host) (void)hipHostFree(g.host);
-        g.host = nullptr;
-        g.cap = 0;
-        if (hipHostMalloc(&g.host, need, hipHostMallocDefault) != hipSuccess) return LR_ERR_HIP;
-        g.cap = need;
-    }
-    if (!g.done && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return LR_ERR_HIP;
-    lr_status s = batch_enqueue(reqs, count, ws, ws_bytes, opts, static_cast<hipStream_t>(stream), g.host, g.cap,
-                                &g.done);
-    if (s == LR_OK) g.pending = true;
-    return s;
+    return batch_enqueue(reqs, count, ws, ws_bytes, opts, static_cast<hipStream_t>(stream));
 }
+
+// ------------------------------------------------------------ batch graph --
+// A batch planned for a capacity (max_elements, max_requests) and captured
+// once as a HIP graph; each launch writes the request table (kernel
+// arguments, a few small launches) and replays the graph, whose kernels read
+// the actual sizes from the device.
+struct lr_batch_graph {
+    lr::Plan plan;
+    char* ws = nullptr;
+    uint32_t max_requests = 0;
+    uint64_t max_elements = 0;
+    uint32_t max_chunks = 0;
+    bool want_root = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace lr {
+
+static lr_status graph_plan(const lr_batch_graph_config* c, Plan* p) {
+    if (!c || c->max_requests == 0 || c->max_elements == 0) return LR_ERR_INVALID_ARG;
+    if (c->max_elements >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    // no synchronising or event-recording options in a graph; the path with
+    // device-side sizes is the plain one (no automatic contraction, no spawning)
+    if (c->opts.flags & (LR_VALIDATE | LR_PROFILE | LR_SPAWN | LR_LOCAL)) return LR_ERR_INVALID_ARG;
+    lr_opts o = c->opts;
+    o.flags |= LR_NO_LOCAL;
+    return make_plan(c->max_elements, false, &o, c->max_requests, p);
+}
+
+}  // namespace lr
+
+extern "C" {
+
+size_t lr_batch_graph_workspace_bytes(const lr_batch_graph_config* cfg) {
+    Plan p;
+    if (lr::graph_plan(cfg, &p) != LR_OK) return 0;
+    return p.total;
+}
+
+lr_status lr_batch_graph_create(const lr_batch_graph_config* cfg, void* ws, size_t ws_bytes, lr_batch_graph** out) {
+    if (!out) return LR_ERR_INVALID_ARG;
+    *out = nullptr;
+    Plan p;
+    lr_status s = lr::graph_plan(cfg, &p);
+    if (s != LR_OK) return s;
+    if (!ws || ws_bytes < p.total) return LR_ERR_WORKSPACE;
+    if ((s = check_base_lds(p)) != LR_OK) return s;
+    auto* g = new lr_batch_graph();
+    g->plan = p;
+    g->ws = carve(ws);
+    g->max_requests = cfg->max_requests;
+    g->max_elements = cfg->max_elements;
+    g->max_chunks = (uint32_t)(cfg->max_elements / BATCH_CHUNK + cfg->max_requests);
+    g->want_root = cfg->want_root != 0;
+    // capture the ranking sequence on a stream of our own
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        delete g;
+        return LR_ERR_HIP;
+    }
+    RunArgs a;
+    a.plan = &g->plan;
+    a.succ = reinterpret_cast<const uint32_t*>(g->ws + p.off_batch_succ);
+    a.desc = reinterpret_cast<const BatchDesc*>(g->ws + p.off_batch_desc);
+    a.bases = reinterpret_cast<const uint32_t*>(g->ws + p.off_batch_bases);
+    a.boff = a.bases + cfg->max_requests + 1;
+    a.bhdr = reinterpret_cast<const BatchHdr*>(g->ws + p.off_batch_hdr);
+    a.count = cfg->max_requests;
+    a.any_root = g->want_root;
+    a.dev_sizes = true;
+    a.ws = g->ws;
+    a.stream = cs;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipError_t er = (e == hipSuccess) ? run_srs(a) : e;
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = er;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    g->graph = graph;
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        lr_batch_graph_destroy(g);
+        return LR_ERR_HIP;
+    }
+    *out = g;
+    return LR_OK;
+}
+
+lr_status lr_batch_graph_launch(lr_batch_graph* g, const lr_request* reqs, uint32_t count, void* stream) {
+    if (!g || (count && !reqs)) return LR_ERR_INVALID_ARG;
+    if (count == 0) return LR_OK;
+    if (count > g->max_requests) return LR_ERR_WORKSPACE;
+    uint64_t N = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (reqs[i].n && (!reqs[i].succ || !reqs[i].rank)) return LR_ERR_INVALID_ARG;
+        if (reqs[i].root && !g->want_root) return LR_ERR_INVALID_ARG;
+        N += reqs[i].n;
+    }
+    if (N > g->max_elements) return LR_ERR_WORKSPACE;
+    if (N == 0) return LR_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (run_batch_table(reqs, count, g->plan, g->ws, true, g->max_chunks, st) != hipSuccess) return LR_ERR_HIP;
+    return hipGraphLaunch(g->exec, st) == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
+void lr_batch_graph_destroy(lr_batch_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"
 
 extern "C" int lr_profile_last(double* ms, int cap) {
     if (!ms || cap <= 0 || !g_prof.valid) return 0;

@@ -295,12 +295,20 @@ struct OutLvl {
 };
 
 // Batch request table in device memory: bases[q] is the first global id of
-// request q, bases[count] the total.
+// request q, bases[count] the total. The table is written on the device from
+// descriptors passed by value as kernel arguments (no host staging, nothing
+// for a graph replay to read from host memory); the header holds the sizes.
 struct BatchDesc {
     const uint32_t* succ;
     uint32_t* rank;
     uint32_t* root;
     uint64_t n;
+};
+struct BatchHdr {
+    uint32_t count;    // requests
+    uint32_t nchunks;  // BATCH_CHUNK-id chunks over all requests (none crosses a request)
+    uint32_t total;    // elements (= bases[count])
+    uint32_t pad;
 };
 
 __device__ __forceinline__ uint32_t batch_find(const uint32_t* bases, uint32_t count, uint32_t g) {
@@ -315,20 +323,22 @@ __device__ __forceinline__ uint32_t batch_find(const uint32_t* bases, uint32_t c
 struct OutBatch {
     const BatchDesc* d;
     const uint32_t* bases;
-    uint32_t count;
+    const BatchHdr* hdr;
     using L = Lay<false>;
     // the request holding the current element, with its output arrays
-    struct Cur { uint32_t q, lo, hi; uint32_t* rank; uint32_t* root; };
+    struct Cur { uint32_t q, lo, hi, count; uint32_t* rank; uint32_t* root; };
     __device__ __forceinline__ Cur begin(uint32_t g) const {
+        const uint32_t count = hdr->count;
         const uint32_t q = batch_find(bases, count, g);
-        return {q, bases[q], bases[q + 1], d[q].rank, d[q].root};
+        return {q, bases[q], bases[q + 1], count, d[q].rank, d[q].root};
     }
     __device__ __forceinline__ void store(Cur& c, uint32_t g, L::Val v, uint32_t r) const {
-        if (g >= c.hi && c.q + 1 < count) {
-            while (g >= c.hi && c.q + 1 < count) { c.q++; c.lo = c.hi; c.hi = bases[c.q + 1]; }
+        if (g >= c.hi && c.q + 1 < c.count) {
+            while (g >= c.hi && c.q + 1 < c.count) { c.q++; c.lo = c.hi; c.hi = bases[c.q + 1]; }
             c.rank = d[c.q].rank;
             c.root = d[c.q].root;
         }
+        if (g >= c.hi) return;  // past the last request (cannot happen for ids below the total)
         const uint32_t l = g - c.lo;
         c.rank[l] = v.c;
         if (c.root) c.root[l] = r - c.lo;

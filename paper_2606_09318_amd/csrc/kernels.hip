@@ -85,9 +85,11 @@ __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t
 // stores suffice (no atomics, no cross-XCD coherence traffic).
 template <bool VEC>
 __global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ succ, uint32_t m,
-                                                uint8_t* __restrict__ hp, const Ctrl* ctrl, Gate gate) {
+                                                uint8_t* __restrict__ hp, const Ctrl* ctrl, const uint32_t* dm,
+                                                Gate gate) {
     if (gate.off()) return;
     if (ctrl->single) return;
+    if (dm) m = dm[0];
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t done = 0;
@@ -1302,12 +1304,14 @@ template <bool VEC, bool TGT = false>
 __global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_t* __restrict__ succ, uint32_t n, uint32_t s1,
                                                             uint32_t nb1, uint32_t* __restrict__ fill1,
                                                             PlaceArrays<false> out, Ctrl* ctrl, Gate gate,
-                                                            uint32_t nin = 0, uint32_t skip = NONE) {
+                                                            uint32_t nin = 0, uint32_t skip = NONE,
+                                                            const uint32_t* dm = nullptr) {
     if (gate.off()) return;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int PER = place_per<false, false>();
     constexpr int TPB_ = place_tpb(false, false);
     constexpr uint32_t T = PER * TPB_;
+    if (dm) n = dm[0];
     if constexpr (!TGT) nin = n;
     const uint32_t tiles = (nin + T - 1) / T;
     // the next tile's successors are loaded while this tile is grouped (the
@@ -1344,14 +1348,17 @@ __global__ __launch_bounds__(place_tpb(false, false)) void k_mark1(const uint32_
 template <bool WEIGHTS = false>
 __global__ __launch_bounds__(place_tpb(false, false)) void k_mark3(const uint32_t* __restrict__ tx, uint32_t n, uint32_t s2,
                                                             uint32_t nb2, const uint32_t* __restrict__ fill2,
-                                                            uint8_t* __restrict__ hp, Gate gate) {
+                                                            uint8_t* __restrict__ hp, Gate gate,
+                                                            const uint32_t* dm = nullptr) {
     if (gate.off()) return;
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t* mk = reinterpret_cast<uint32_t*>(lds);
     constexpr int TPB_ = place_tpb(false, false);
     const uint32_t R = 1u << s2;
+    if (dm) n = dm[0];
     for (uint32_t f = blockIdx.x; f < nb2; f += gridDim.x) {
         const uint32_t base = f << s2;
+        if (base >= n) break;  // device-side size: the ranges past it hold no ids
         const uint32_t len = min(R, n - base);
         for (uint32_t i = threadIdx.x; i < R / 4; i += TPB_) mk[i] = 0;
         __syncthreads();
@@ -1446,9 +1453,10 @@ constexpr uint32_t FB_GRID_PER_CU = 2;
 template <bool W, bool FIRST, bool LAST, class Src, class Out>
 __global__ __launch_bounds__(TPB) void k_fb_round(Src src, const typename Lay<W>::Rec* __restrict__ a,
                                                   typename Lay<W>::Rec* __restrict__ b, uint32_t m, uint32_t J,
-                                                  Out out, uint32_t* err, Gate gate) {
+                                                  Out out, uint32_t* err, const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
     using L = Lay<W>;
+    if (dm) m = src.m = dm[0];
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
@@ -1483,18 +1491,83 @@ __global__ __launch_bounds__(TPB) void k_fb_round(Src src, const typename Lay<W>
     }
 }
 
+// Per level, log2 of the ruler spacing (device-side level sizes follow from them).
+struct LevelShifts { uint8_t lg[MAXL]; };
+
 // ----------------------------------------------------------------- batch --
+// The request table is built on the device: k_batch_desc copies descriptors
+// passed by value (up to BATCH_ARG_DESC per launch) into the workspace, and
+// k_batch_index scans their sizes into the request bases and first chunks and
+// fills the header. With device-side sizes (a batch planned for a capacity,
+// as a replayed graph is) it also publishes the level sizes.
+struct BatchDescArg {
+    BatchDesc d[BATCH_ARG_DESC];
+    uint32_t first;  // table index of d[0]
+    uint32_t cnt;    // descriptors in this launch
+    uint32_t count;  // requests of the whole batch (written to the header)
+};
+static_assert(sizeof(BatchDescArg) <= 4096, "kernel arguments");
+
+__global__ __launch_bounds__(64) void k_batch_desc(BatchDescArg a, BatchDesc* __restrict__ dst,
+                                                   BatchHdr* __restrict__ hdr) {
+    for (uint32_t i = threadIdx.x; i < a.cnt; i += 64) dst[a.first + i] = a.d[i];
+    if (a.first == 0 && threadIdx.x == 0) hdr->count = a.count;
+}
+
+// One workgroup: bases[q] = elements before request q, boff[q] = chunks
+// before it (count + 1 entries each); the header's chunk and element totals;
+// with levels > 0 (device-side sizes) dm[0] = total and dm[l + 1] =
+// ceil(dm[l] / k_l).
+__global__ __launch_bounds__(1024) void k_batch_index(const BatchDesc* __restrict__ d, uint32_t* __restrict__ bases,
+                                                      uint32_t* __restrict__ boff, BatchHdr* __restrict__ hdr,
+                                                      Ctrl* ctrl, uint32_t levels, LevelShifts ks) {
+    __shared__ uint32_t sh[2 * (1024 / 64)];
+    const uint32_t count = hdr->count;
+    const uint32_t per = (count + 1023u) >> 10;
+    const uint32_t lo = min(threadIdx.x * per, count), hi = min(lo + per, count);
+    uint32_t sn = 0, sc = 0;
+    for (uint32_t q = lo; q < hi; ++q) {
+        const uint32_t n = (uint32_t)d[q].n;
+        sn += n;
+        sc += (n + BATCH_CHUNK - 1) / BATCH_CHUNK;
+    }
+    uint32_t tn, tc;
+    uint32_t an = block_exscan(sn, sh, &tn);
+    uint32_t ac = block_exscan(sc, sh + 1024 / 64, &tc);
+    for (uint32_t q = lo; q < hi; ++q) {
+        const uint32_t n = (uint32_t)d[q].n;
+        bases[q] = an;
+        boff[q] = ac;
+        an += n;
+        ac += (n + BATCH_CHUNK - 1) / BATCH_CHUNK;
+    }
+    if (threadIdx.x == 0) {
+        bases[count] = tn;
+        boff[count] = tc;
+        hdr->nchunks = tc;
+        hdr->total = tn;
+        if (levels) {
+            uint32_t m = tn;
+            ctrl->dm[0] = m;
+            for (uint32_t l = 0; l < levels; ++l) {
+                m = (m + (1u << ks.lg[l]) - 1u) >> ks.lg[l];
+                ctrl->dm[l + 1] = m;
+            }
+        }
+    }
+}
+
 // One workgroup per chunk of BATCH_CHUNK ids of one request:
 // concat[g] = base(q) + succ_q[g - base(q)]; out-of-range successors become
 // terminals (no list leaves its request). The chunk also sums, for the one-list
 // head test, ids minus successors of non-terminals and counts terminals.
 __global__ __launch_bounds__(TPB) void k_batch_gather(const BatchDesc* __restrict__ d,
                                                       const uint32_t* __restrict__ bases,
-                                                      const uint32_t* __restrict__ boff, uint32_t count,
-                                                      uint32_t nchunks, uint32_t* __restrict__ concat,
-                                                      uint2* __restrict__ part) {
+                                                      const uint32_t* __restrict__ boff, const BatchHdr* hdr,
+                                                      uint32_t* __restrict__ concat, uint2* __restrict__ part) {
     __shared__ uint64_t shs[TPB / 64];
     __shared__ uint32_t snt[TPB / 64];
+    const uint32_t count = hdr->count, nchunks = hdr->nchunks;
     for (uint32_t b = blockIdx.x; b < nchunks; b += gridDim.x) {
         const uint32_t q = batch_find(boff, count, b);  // the request whose chunks hold b
         const uint32_t lo = bases[q], nq = bases[q + 1] - lo;
@@ -1529,11 +1602,12 @@ __global__ __launch_bounds__(TPB) void k_batch_gather(const BatchDesc* __restric
 
 // One workgroup per request: its chunks' partial sums -> (head sum, terminals).
 __global__ __launch_bounds__(TPB) void k_batch_reduce(const uint2* __restrict__ part,
-                                                      const uint32_t* __restrict__ boff, uint32_t count,
+                                                      const uint32_t* __restrict__ boff, const BatchHdr* hdr,
                                                       uint2* __restrict__ sums, Gate gate) {
     if (gate.off()) return;
     __shared__ uint64_t shs[TPB / 64];
     __shared__ uint32_t snt[TPB / 64];
+    const uint32_t count = hdr->count;
     for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
         uint64_t hs = 0;
         uint32_t nt = 0;
@@ -1563,13 +1637,16 @@ __global__ __launch_bounds__(TPB) void k_batch_reduce(const uint2* __restrict__ 
 // its head sum (the one-list shortcut per request). Then the heads that are
 // not sampled rulers become the level-0 walk list in request order, and the
 // level-0 marking and compaction are skipped as for a single list; otherwise
-// the forest path runs.
+// the forest path runs. dm (device-side sizes) gives the level-0 size and
+// walk count.
 __global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ sums,
-                                                      const uint32_t* __restrict__ bases, uint32_t count,
+                                                      const uint32_t* __restrict__ bases, const BatchHdr* hdr,
                                                       Ctrl* ctrl, Sampler smp, char* __restrict__ eb, uint32_t S,
-                                                      uint32_t rec_bytes, Gate gate) {
+                                                      uint32_t rec_bytes, const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
+    if (dm) { smp.m = dm[0]; S = dm[1]; }
+    const uint32_t count = hdr->count;
     int ok = 1;
     for (uint32_t q = threadIdx.x; q < count; q += 1024) {
         const uint32_t lo = bases[q], hi = bases[q + 1];
@@ -1821,7 +1898,6 @@ __global__ __launch_bounds__(LC_TPB) void k_lc_chain(const uint32_t* __restrict_
 
 // Exclusive scan of the per-tile start counts (one workgroup); publishes the
 // contracted list's size and the sizes of the ruling-set levels above it.
-struct LevelShifts { uint8_t lg[MAXL]; };
 
 // forced: the contracted path runs alone and this kernel sets its mode
 __global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, uint32_t ntiles, Ctrl* ctrl,
@@ -2484,7 +2560,7 @@ static hipError_t run_place(const RunArgs& a, const Plan& p, const typename Lay<
 // grouped by range in two passes, then written range by range from LDS. The
 // grouping arrays of the placement are free at this point; the marks land on
 // the first of them (hp0), after its grouped targets have been consumed.
-static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl* ctrl) {
+static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl* ctrl, const uint32_t* dm) {
     char* ws = a.ws;
     hipStream_t st = a.stream;
     const uint32_t n = (uint32_t)p.m[0];
@@ -2500,20 +2576,21 @@ static hipError_t run_marks(const RunArgs& a, const Plan& p, uint8_t* hp0, Ctrl*
     const size_t l1 = place_lds_bytes(false, false, p.nb1, false);
     if (vec) {
         LR_TRY(allow_lds(k_mark1<true>, l1));
-        hipLaunchKernelGGL(k_mark1<true>, dim3(grid_for(n, T)), tpb, l1, st, a.succ, n, p.s1, p.nb1, fill1, P, ctrl, mg);
+        hipLaunchKernelGGL(k_mark1<true>, dim3(grid_for(n, T)), tpb, l1, st, a.succ, n, p.s1, p.nb1, fill1, P, ctrl, mg,
+                           0u, NONE, dm);
     } else {
         LR_TRY(allow_lds(k_mark1<false>, l1));
         hipLaunchKernelGGL(k_mark1<false>, dim3(grid_for(n, T)), tpb, l1, st, a.succ, n, p.s1, p.nb1, fill1, P, ctrl,
-                           mg);
+                           mg, 0u, NONE, dm);
     }
     LR_TRY(hipGetLastError());
     const size_t l2 = place_lds_bytes(false, false, 1u << (p.s1 - p.s2), false);
     LR_TRY(allow_lds(k_place2<false, false, false>, l2));
     hipLaunchKernelGGL((k_place2<false, false, false>), dim3(grid_for(n, T)), tpb, l2, st, P, ctrl, n, p.s1, p.s2,
-                       fill2, Q, nullptr, fill1, mg);
+                       fill2, Q, dm, fill1, mg);
     LR_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_mark3<false>, dim3(std::min<uint32_t>(p.nb2, (uint32_t)device_cus() * 8)), tpb,
-                       (size_t)1 << p.s2, st, Q.x, n, p.s2, p.nb2, fill2, hp0, mg);
+                       (size_t)1 << p.s2, st, Q.x, n, p.s2, p.nb2, fill2, hp0, mg, dm);
     return hipGetLastError();
 }
 
@@ -2591,13 +2668,14 @@ static hipError_t run_batch_heads(const RunArgs& a, const Plan& p, Gate g) {
     hipStream_t st = a.stream;
     const uint2* part = reinterpret_cast<const uint2*>(a.ws + p.off_batch_part);
     uint2* sums = reinterpret_cast<uint2*>(a.ws + p.off_batch_sums);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);
     const uint32_t grid = std::max(1u, std::min<uint32_t>(a.count, (uint32_t)device_cus() * 8));
-    hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(TPB), 0, st, part, a.boff, a.count, sums, g);
+    hipLaunchKernelGGL(k_batch_reduce, dim3(grid), dim3(TPB), 0, st, part, a.boff, a.bhdr, sums, g);
     LR_TRY(hipGetLastError());
     const Sampler smp0{(uint32_t)p.m[0], p.log2k[0], p.lseed[0]};
-    hipLaunchKernelGGL(k_batch_heads, dim3(1), dim3(1024), 0, st, sums, a.bases, a.count,
-                       reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl), smp0, a.ws + p.off_eb[0], (uint32_t)p.m[1],
-                       (uint32_t)p.rec_bytes, g);
+    hipLaunchKernelGGL(k_batch_heads, dim3(1), dim3(1024), 0, st, sums, a.bases, a.bhdr, ctrl, smp0,
+                       a.ws + p.off_eb[0], (uint32_t)p.m[1], (uint32_t)p.rec_bytes,
+                       a.dev_sizes ? (const uint32_t*)&ctrl->dm[0] : nullptr, g);
     return hipGetLastError();
 }
 
@@ -2627,13 +2705,16 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     const Gate g = a.gate;
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
     const uint32_t n = (uint32_t)p.m[0];
+    // device-side sizes (a batch planned for a capacity): level l's actual
+    // size and walk count are dm[l], dm[l + 1]; p.m[] are capacities
+    auto dm_at = [&](uint32_t l) -> const uint32_t* { return a.dev_sizes ? &ctrl->dm[l] : nullptr; };
     SrcIn<W, WT> src0{a.succ, a.weight, n};
     if (a.prologue) {
         rec_ev(a, EV_START);
         if (a.validate) LR_TRY(run_validate(a, p, n));
     }
     if (p.levels == 0) {
-        LR_TRY((launch_base<W>(src0, out0, n, ctrl, st, nullptr, g)));
+        LR_TRY((launch_base<W>(src0, out0, n, ctrl, st, dm_at(0), g)));
         for (int i = EV_DETECT; i < EV_COUNT; ++i) rec_ev(a, i);
         return hipSuccess;
     }
@@ -2643,13 +2724,13 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
     {
         if (a.prologue) LR_TRY(a.desc ? run_batch_heads(a, p, Gate{}) : run_headsum(a, p, Gate{}));
         if (p.log0) {
-            LR_TRY(run_marks(a, p, hp0, ctrl));
+            LR_TRY(run_marks(a, p, hp0, ctrl, dm_at(0)));
         } else {
             LR_TRY(fill(hp0, n, 0u, st, ctrl, g));
             const bool vec = ((uintptr_t)a.succ % 16) == 0;
             const uint32_t gd = grid_for(n, TPB * 4 * 4);
-            if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
-            else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, g);
+            if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, dm_at(0), g);
+            else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp0, ctrl, dm_at(0), g);
             LR_TRY(hipGetLastError());
         }
     }
@@ -2666,12 +2747,12 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const Ctrl* skip = (l == 0) ? ctrl : nullptr;
         const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
         hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, skip,
-                           nullptr, g);
+                           dm_at(l), g);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
         LR_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
-                           S, (uint32_t)p.rec_bytes, skip, nullptr, g);
+                           S, (uint32_t)p.rec_bytes, skip, dm_at(l), g);
         LR_TRY(hipGetLastError());
         if (a.validate && !(l == 0 && p.log0))
             LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st, nullptr, g));
@@ -2687,20 +2768,20 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
                                        pr, g);
                     LR_TRY(hipGetLastError());
                     SrcPair<WT> srcp{pr, n};
-                    LR_TRY((launch_chase_log<W, 1>(p, srcp, smp, ctrl, ws, st, nullptr, g)));
+                    LR_TRY((launch_chase_log<W, 1>(p, srcp, smp, ctrl, ws, st, dm_at(0), g)));
                 } else if (p.lane_walks == 2) {
-                    LR_TRY((launch_chase_log<W, 2>(p, src0, smp, ctrl, ws, st, nullptr, g)));
+                    LR_TRY((launch_chase_log<W, 2>(p, src0, smp, ctrl, ws, st, dm_at(0), g)));
                 } else {
-                    LR_TRY((launch_chase_log<W, 1>(p, src0, smp, ctrl, ws, st, nullptr, g)));
+                    LR_TRY((launch_chase_log<W, 1>(p, src0, smp, ctrl, ws, st, dm_at(0), g)));
                 }
             } else {
-                if (p.lane_walks == 2) LR_TRY((launch_chase<W, 0, 2>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
-                else LR_TRY((launch_chase<W, 0, 1>(p, 0, src0, smp, ctrl, ws, st, nullptr, g)));
+                if (p.lane_walks == 2) LR_TRY((launch_chase<W, 0, 2>(p, 0, src0, smp, ctrl, ws, st, dm_at(0), g)));
+                else LR_TRY((launch_chase<W, 0, 1>(p, 0, src0, smp, ctrl, ws, st, dm_at(0), g)));
             }
             rec_ev(a, EV_CHASE0);
         } else {
             SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[l - 1]), m};
-            LR_TRY((launch_chase<W, 0, 1>(p, (int)l, src, smp, ctrl, ws, st, nullptr, g)));
+            LR_TRY((launch_chase<W, 0, 1>(p, (int)l, src, smp, ctrl, ws, st, dm_at(l), g)));
         }
     }
     {
@@ -2708,13 +2789,13 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const uint32_t mL = (uint32_t)p.m[L_];
         SrcLvl<W> src{reinterpret_cast<const typename L::Rec*>(ws + p.off_eb[L_ - 1]), mL};
         OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[L_ - 1])};
-        LR_TRY((launch_base<W>(src, out, mL, ctrl, st, nullptr, g)));
+        LR_TRY((launch_base<W>(src, out, mL, ctrl, st, dm_at(L_), g)));
     }
     for (int l = (int)p.levels - 1; l >= 0; --l) {
         const uint32_t m = (uint32_t)p.m[l];
         const uint32_t S = (uint32_t)p.m[l + 1];
         hipLaunchKernelGGL(k_resolve<W>, dim3(grid_for(m, TPB * 4, 4)), dim3(TPB), 0, st, ws + p.off_eb[l], S,
-                           ctrl, l, nullptr, g);
+                           ctrl, l, dm_at((uint32_t)l), g);
         LR_TRY(hipGetLastError());
         const auto* slot = reinterpret_cast<const typename L::Slot*>(ws + p.off_slot[l]);
         const auto* res = reinterpret_cast<const typename L::Res*>(ws + p.off_eb[l]);
@@ -2723,16 +2804,16 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
             rec_ev(a, EV_UPPER);
             if (p.log0) {
                 LR_TRY((run_place<W, Out0>(a, p, res, S, ctrl, out0, a.desc ? a.any_root : a.root != nullptr,
-                                           nullptr)));
+                                           dm_at(0))));
             } else {
                 rec_ev(a, EV_PART);
                 hipLaunchKernelGGL((k_expand<W, Out0>), dim3(ge), dim3(TPB), 0, st, slot, m, res, S, ctrl, 0, out0,
-                                   nullptr, g);
+                                   dm_at(0), g);
             }
         } else {
             OutLvl<W> out{reinterpret_cast<typename L::Res*>(ws + p.off_eb[l - 1])};
             hipLaunchKernelGGL((k_expand<W, OutLvl<W>>), dim3(ge), dim3(TPB), 0, st, slot, m, res, S, ctrl, l,
-                               out, nullptr, g);
+                               out, dm_at((uint32_t)l), g);
         }
         LR_TRY(hipGetLastError());
     }
@@ -2912,8 +2993,8 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
     {
         const bool vec = ((uintptr_t)a.succ % 16) == 0;
         const uint32_t gd = grid_for(n, TPB * 4 * 4);
-        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp_in, ctrl, g);
-        else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp_in, ctrl, g);
+        if (vec) hipLaunchKernelGGL(k_detect<true>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp_in, ctrl, nullptr, g);
+        else hipLaunchKernelGGL(k_detect<false>, dim3(gd), dim3(TPB), 0, st, a.succ, n, hp_in, ctrl, nullptr, g);
         LR_TRY(hipGetLastError());
     }
     rec_ev(a, EV_DETECT);
@@ -3009,20 +3090,21 @@ static hipError_t run_fallback_t(const RunArgs& a, Out0 out0) {
     for (uint64_t span = J; span < n64; span *= J) ++rounds;
     const Src src{a.succ, a.weight, n};
     uint32_t* err = a.validate ? &ctrl->err : nullptr;
+    const uint32_t* dm = a.dev_sizes ? &ctrl->dm[0] : nullptr;
     for (uint32_t r = 0; r < rounds; ++r) {
         const bool first = r == 0, last = r + 1 == rounds;
         if (first && last)
             hipLaunchKernelGGL((k_fb_round<W, true, true, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A, B,
-                               n, J, out0, err, g);
+                               n, J, out0, err, dm, g);
         else if (first)
             hipLaunchKernelGGL((k_fb_round<W, true, false, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A,
-                               B, n, J, out0, err, g);
+                               B, n, J, out0, err, dm, g);
         else if (last)
             hipLaunchKernelGGL((k_fb_round<W, false, true, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A,
-                               B, n, J, out0, err, g);
+                               B, n, J, out0, err, dm, g);
         else
             hipLaunchKernelGGL((k_fb_round<W, false, false, Src, Out0>), dim3(grid), dim3(TPB), 0, a.stream, src, A,
-                               B, n, J, out0, err, g);
+                               B, n, J, out0, err, dm, g);
         LR_TRY(hipGetLastError());
         std::swap(A, B);  // the round's output is the next round's input
     }
@@ -3056,7 +3138,7 @@ static hipError_t run_weighted(const RunArgs& a) {
 hipError_t run_srs(const RunArgs& a) {
     const Plan& p = *a.plan;
     if (a.desc) {
-        OutBatch out{a.desc, a.bases, a.count};
+        OutBatch out{a.desc, a.bases, a.bhdr};
         return run_any_t<false, 0>(a, out);
     }
     if (!p.weighted) {  // rank is required
@@ -3118,12 +3200,35 @@ hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted) {
     }
 }
 
-hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, const uint32_t* boff, uint32_t count,
-                            uint32_t nchunks, uint32_t* concat, uint8_t* part, hipStream_t st) {
-    if (!nchunks) return hipSuccess;
-    const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)device_cus() * 16);
-    hipLaunchKernelGGL(k_batch_gather, dim3(grid), dim3(TPB), 0, st, desc, bases, boff, count, nchunks, concat,
-                       reinterpret_cast<uint2*>(part));
+hipError_t run_batch_table(const lr_request* reqs, uint32_t count, const Plan& p, char* ws, bool dev_sizes,
+                           uint32_t max_chunks, hipStream_t st) {
+    auto* desc = reinterpret_cast<BatchDesc*>(ws + p.off_batch_desc);
+    auto* bases = reinterpret_cast<uint32_t*>(ws + p.off_batch_bases);
+    uint32_t* boff = bases + p.batch_count + 1;
+    auto* hdr = reinterpret_cast<BatchHdr*>(ws + p.off_batch_hdr);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p.off_ctrl);
+    BatchDescArg arg{};
+    arg.count = count;
+    for (uint32_t first = 0; first < count || first == 0; first += BATCH_ARG_DESC) {
+        arg.first = first;
+        arg.cnt = std::min<uint32_t>(BATCH_ARG_DESC, count - first);
+        for (uint32_t i = 0; i < arg.cnt; ++i) {
+            const lr_request& r = reqs[first + i];
+            arg.d[i] = BatchDesc{r.succ, r.rank, r.root, r.n};
+        }
+        hipLaunchKernelGGL(k_batch_desc, dim3(1), dim3(64), 0, st, arg, desc, hdr);
+        LR_TRY(hipGetLastError());
+        if (count == 0) break;
+    }
+    LevelShifts ks{};
+    for (uint32_t l = 0; l < p.levels; ++l) ks.lg[l] = (uint8_t)p.log2k[l];
+    hipLaunchKernelGGL(k_batch_index, dim3(1), dim3(1024), 0, st, desc, bases, boff, hdr, ctrl,
+                       dev_sizes ? p.levels : 0u, ks);
+    LR_TRY(hipGetLastError());
+    const uint32_t grid = std::max(1u, std::min<uint32_t>(max_chunks, (uint32_t)device_cus() * 16));
+    hipLaunchKernelGGL(k_batch_gather, dim3(grid), dim3(TPB), 0, st, desc, bases, boff, hdr,
+                       reinterpret_cast<uint32_t*>(ws + p.off_batch_succ),
+                       reinterpret_cast<uint2*>(ws + p.off_batch_part));
     return hipGetLastError();
 }
 

@@ -132,6 +132,7 @@ static_assert(LR_PLACE_COARSE_BIAS <= 4 && LR_PLACE_COARSE_BIAS_W <= 4, "fan-out
 // cross a request, each reducing its request's head sum; the host uploads the
 // request bases and each request's first chunk (two tables of count + 1).
 constexpr uint32_t BATCH_CHUNK = 4096;
+constexpr uint32_t BATCH_ARG_DESC = 96;  // request descriptors passed by value per table-writer launch
 inline size_t batch_table_bytes(uint32_t count) { return 2 * ((size_t)count + 1) * 4; }
 
 struct Plan {
@@ -154,6 +155,7 @@ struct Plan {
     size_t off_eb[LR_MAX_LEVELS] = {};
     size_t off_tile[LR_MAX_LEVELS] = {};
     size_t off_batch_succ = 0, off_batch_desc = 0, off_batch_bases = 0;  // bases: then the chunk offsets
+    size_t off_batch_hdr = 0;
     size_t off_batch_part = 0, off_batch_sums = 0;  // per chunk, per request: (head sum, terminals)
     // level 0 in log mode: the chase appends (element, walk, offset) records to
     // a chunked visit log instead of storing at random addresses; after the

@@ -9,6 +9,7 @@
 namespace lr {
 
 struct BatchDesc;
+struct BatchHdr;
 
 enum { EV_START, EV_DETECT, EV_HEADS, EV_CHASE0, EV_UPPER, EV_PART, EV_EXPAND, EV_COUNT };
 
@@ -25,8 +26,11 @@ struct RunArgs {
     const BatchDesc* desc = nullptr;
     const uint32_t* bases = nullptr;
     const uint32_t* boff = nullptr;   // batch: each request's first chunk (BATCH_CHUNK ids), count + 1 entries
-    uint32_t count = 0;
+    const BatchHdr* bhdr = nullptr;   // batch: the device table's header (request count, totals)
+    uint32_t count = 0;               // batch: requests (with device-side sizes, the most a call takes)
     bool any_root = false;            // batch: some request wants roots
+    bool dev_sizes = false;           // batch planned for a capacity: every level kernel reads the
+                                      // actual sizes from Ctrl.dm (written by the table pass)
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     bool validate = false;
@@ -50,13 +54,14 @@ lr_status prefix_sum_records(const uint32_t* succ, const void* weight, int wt, v
 // Wyllie pointer doubling baseline; ws holds two ping-pong record arrays.
 hipError_t run_wyllie(const RunArgs& a, uint64_t n, bool weighted);
 
-// Batch staging: copy the requests' successor arrays into one forest over the
-// concatenated id range (ids shifted by the request's base), chunk by chunk
-// (boff: each request's first chunk of BATCH_CHUNK ids, nchunks in all); each
-// chunk also writes its request's partial head sum and terminal count (16 B)
-// to part.
-hipError_t run_batch_gather(const BatchDesc* desc, const uint32_t* bases, const uint32_t* boff, uint32_t count,
-                            uint32_t nchunks, uint32_t* concat, uint8_t* part, hipStream_t st);
+// Batch staging, all on the device: the request table from descriptors passed
+// as kernel arguments, its bases and chunk offsets (with dev_sizes also the
+// level sizes in Ctrl.dm), then the requests' successor arrays copied into
+// one forest over the concatenated id range (ids shifted by the request's
+// base), chunk by chunk; each chunk also writes its request's partial head
+// sum and terminal count. max_chunks bounds the chunks (grid size only).
+hipError_t run_batch_table(const lr_request* reqs, uint32_t count, const Plan& p, char* ws, bool dev_sizes,
+                           uint32_t max_chunks, hipStream_t st);
 
 // Euler-tour arc weights by grouping (see kernels.hip); *done false: the
 // caller scatters the weights itself.

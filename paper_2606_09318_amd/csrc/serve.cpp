@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <chrono>
+#include <map>
 #include <memory>
 #include <thread>
 #include <vector>
@@ -16,7 +18,13 @@
 namespace lr {
 
 lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t ws_bytes, const lr_opts* opts,
-                        hipStream_t st, void* host_stage, size_t host_cap, hipEvent_t* copy_done);
+                        hipStream_t st);
+
+// Graph buckets: a batch of N elements replays the graph planned for the
+// smallest capacity 2^(j/2) >= N (j >= 2 * GRAPH_MIN_LOG2), captured on first
+// use per slot; all graphs of a slot share its workspace (its batches run one
+// after another on its stream).
+constexpr uint32_t GRAPH_MIN_LOG2 = 16;
 
 class HipExecutor : public Executor {
 public:
@@ -29,14 +37,11 @@ public:
             return LR_ERR_OUT_OF_MEMORY;
         }
         bytes_ = (cfg_.hbm_budget / cfg_.max_inflight) / 256 * 256;
-        const uint32_t mb = cfg_.max_batch ? cfg_.max_batch : 1;
-        stage_cap_ = (size_t)mb * sizeof(BatchDesc) + batch_table_bytes(mb);
         slots_.resize(cfg_.max_inflight);
         for (uint32_t i = 0; i < cfg_.max_inflight; ++i) {
             Slot& s = slots_[i];
             if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return LR_ERR_HIP;
             if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return LR_ERR_HIP;
-            if (hipHostMalloc(&s.stage, stage_cap_, hipHostMallocDefault) != hipSuccess) return LR_ERR_HIP;
             s.ws = static_cast<char*>(pool_) + (size_t)i * bytes_;
         }
         return LR_OK;
@@ -45,9 +50,9 @@ public:
     ~HipExecutor() override {
         for (Slot& s : slots_) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
+            for (auto& kv : s.graphs) lr_batch_graph_destroy(kv.second);
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.stream) (void)hipStreamDestroy(s.stream);
-            if (s.stage) (void)hipHostFree(s.stage);
         }
         if (pool_) (void)hipFree(pool_);
     }
@@ -59,17 +64,15 @@ public:
         return lr_batch_workspace_bytes(reqs, count, &cfg_.opts);
     }
 
+    // A batch after a failed launch needs no wait: every launch of a slot is
+    // ordered on the slot's stream, and no host buffer outlives a call.
     lr_status launch(uint32_t i, const lr_request* reqs, uint32_t count) override {
         Slot& s = slots_[i];
         (void)hipSetDevice(dev_);
-        if (s.failed) {  // a failed launch may have left copies from the staging buffer in flight
-            if (hipEventSynchronize(s.done) != hipSuccess) return LR_ERR_HIP;
-            s.failed = false;
-        }
-        lr_status st = batch_enqueue(reqs, count, s.ws, bytes_, &cfg_.opts, s.stream, s.stage, stage_cap_, nullptr);
-        const bool recorded = hipEventRecord(s.done, s.stream) == hipSuccess;
-        if (st == LR_OK && !recorded) st = LR_ERR_HIP;
-        if (st != LR_OK) s.failed = true;  // the scheduler frees the slot at once
+        lr_status st = LR_ERR_UNSUPPORTED;
+        if (cfg_.graphs) st = launch_graph(s, reqs, count);
+        if (st == LR_ERR_UNSUPPORTED) st = batch_enqueue(reqs, count, s.ws, bytes_, &cfg_.opts, s.stream);
+        if (hipEventRecord(s.done, s.stream) != hipSuccess && st == LR_OK) st = LR_ERR_HIP;
         return st;
     }
 
@@ -80,19 +83,61 @@ public:
         return -1;
     }
 
+    uint64_t graph_launches() const { return graph_launches_.load(); }
+
 private:
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
-        void* stage = nullptr;
         char* ws = nullptr;
-        bool failed = false;  // the last launch failed: wait for s.done before reusing the staging
+        std::map<uint32_t, lr_batch_graph*> graphs;  // by 2 j + roots (capacity 2^(j/2) elements)
     };
+
+    // Replays the bucket's graph; LR_ERR_UNSUPPORTED when the batch should take
+    // the plain enqueue instead (its bucket's workspace does not fit the slot,
+    // or options a graph cannot take).
+    lr_status launch_graph(Slot& s, const lr_request* reqs, uint32_t count) {
+        uint64_t N = 0;
+        bool root = false;
+        for (uint32_t q = 0; q < count; ++q) {
+            N += reqs[q].n;
+            root |= reqs[q].root != nullptr;
+        }
+        uint32_t j = 2 * GRAPH_MIN_LOG2;
+        while (j < 62 && bucket_cap(j) < N) ++j;
+        const uint64_t cap = bucket_cap(j);
+        if (cap >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+        lr_batch_graph_config gc{};
+        gc.max_elements = cap;
+        gc.max_requests = cfg_.max_batch ? cfg_.max_batch : 1;
+        gc.want_root = root ? 1u : 0u;
+        gc.opts = cfg_.opts;
+        const uint32_t key = 2 * j + (root ? 1u : 0u);  // the root column costs placement bandwidth
+        auto it = s.graphs.find(key);
+        if (it == s.graphs.end()) {
+            const size_t need = lr_batch_graph_workspace_bytes(&gc);
+            if (need == 0 || need > bytes_) return LR_ERR_UNSUPPORTED;
+            lr_batch_graph* g = nullptr;
+            const lr_status st = lr_batch_graph_create(&gc, s.ws, bytes_, &g);
+            if (st != LR_OK) return st == LR_ERR_INVALID_ARG ? LR_ERR_UNSUPPORTED : st;
+            it = s.graphs.emplace(key, g).first;
+        }
+        const lr_status st = lr_batch_graph_launch(it->second, reqs, count, s.stream);
+        if (st == LR_OK) graph_launches_++;
+        return st;
+    }
+
+    static uint64_t bucket_cap(uint32_t j) {  // 2^(j/2), rounded up
+        const uint64_t b = 1ull << (j / 2);
+        return (j & 1) ? (uint64_t)((double)b * 1.4142135623730951) + 1 : b;
+    }
+
     lr_server_config cfg_{};
     int dev_ = 0;
     void* pool_ = nullptr;
-    size_t bytes_ = 0, stage_cap_ = 0;
+    size_t bytes_ = 0;
     std::vector<Slot> slots_;
+    std::atomic<uint64_t> graph_launches_{0};
 };
 
 }  // namespace lr
