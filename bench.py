@@ -699,9 +699,9 @@ def serve_bench(count: int) -> dict:
     reqs = lr.requests(items)
     budget = 32 << 30
 
-    def cfg(inflight, max_batch):
+    def cfg(inflight, max_batch, graphs=1):
         c = lr.lr_server_config()
-        c.hbm_budget, c.max_inflight, c.max_batch = budget, inflight, max_batch
+        c.hbm_budget, c.max_inflight, c.max_batch, c.graphs = budget, inflight, max_batch, graphs
         return c
 
     def failures() -> int:
@@ -730,37 +730,41 @@ def serve_bench(count: int) -> dict:
 
     torch.cuda.synchronize()
     mean_n = total / count
-    # saturation throughputs: every request present at t = 0
+    # saturation throughputs: every request present at t = 0 (batched: each
+    # batch replays the captured graph of its size bucket; also without graphs)
     sat_b = replay(cfg(2, count), [0.0] * count)
-    sat_p = replay(cfg(1, 1), [0.0] * count)
+    sat_b_plain = replay(cfg(2, count, 0), [0.0] * count)
+    sat_p = replay(cfg(1, 1, 0), [0.0] * count)
     sat = total / sat_b["makespan_s"]
     rate = 0.8 * sat / mean_n
     arr = arrivals(rate)
     res = {"requests": count, "total_elements": total, "offered_rate_req_per_s": round(rate, 1),
            "hbm_budget_gib": budget >> 30, "saturation_g_elements_per_s": round(sat / 1e9, 3),
            "saturation_per_request_g_elements_per_s": sat_p["throughput_g_elements_per_s"],
-           "saturation_runs": {"batched": sat_b, "per_request": sat_p},
+           "saturation_runs": {"batched": sat_b, "batched_without_graphs": sat_b_plain, "per_request": sat_p},
            "input_generation_s": round(gen_s, 1),
            "latency": "host clock from each request's scheduled arrival to the server seeing it complete",
            "correctness": "closed_form_failures = requests whose ranks differ from the closed form of "
                           "their generated order, all requests checked after every replay"}
     res["batched"] = replay(cfg(2, count), arr)
-    res["per_request"] = replay(cfg(1, 1), arr)
+    res["batched_without_graphs"] = replay(cfg(2, count, 0), arr)
+    res["per_request"] = replay(cfg(1, 1, 0), arr)
     # a load both servers sustain: 0.7 x the per-request saturation, so the
     # latencies compare at equal throughput
     rate_eq = 0.7 * (sat_p["throughput_g_elements_per_s"] * 1e9) / mean_n
     arr_eq = arrivals(rate_eq)
     res["equal_load"] = {"offered_rate_req_per_s": round(rate_eq, 1),
                          "offered_g_elements_per_s": round(rate_eq * mean_n / 1e9, 3),
-                         "batched": replay(cfg(2, count), arr_eq), "per_request": replay(cfg(1, 1), arr_eq)}
+                         "batched": replay(cfg(2, count), arr_eq), "per_request": replay(cfg(1, 1, 0), arr_eq)}
     # offered-load sweep for the batched server (same trace, arrival times scaled)
     res["load_sweep"] = []
-    for load in (0.5, 0.7, 0.9, 1.1):
+    for load in (0.1, 0.5, 0.7, 0.9, 1.1):
         r = replay(cfg(2, count), [a * 0.8 / load for a in arr])
         r["load"] = load
         res["load_sweep"].append(r)
     res["closed_form_failures_total"] = sum(x["closed_form_failures"] for x in
-                                            [sat_b, sat_p, res["batched"], res["per_request"],
+                                            [sat_b, sat_b_plain, sat_p, res["batched"],
+                                             res["batched_without_graphs"], res["per_request"],
                                              res["equal_load"]["batched"], res["equal_load"]["per_request"]]
                                             + res["load_sweep"])
     del items, orders

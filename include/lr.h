@@ -376,7 +376,8 @@ typedef struct lr_server_config {
     lr_opts opts;             /* options for every batch */
     uint32_t graphs;          /* nonzero: a batch replays a captured lr_batch_graph of its
                                  size bucket (capacities 2^(j/2) elements from 2^16 on,
-                                 max_batch requests; captured per slot on first use);
+                                 max_batch requests; captured per slot when the server
+                                 is created, those with root outputs on first use);
                                  batches whose bucket does not fit a slot, or options a
                                  graph cannot take, are enqueued as lr_rank_batch */
     uint32_t pad;

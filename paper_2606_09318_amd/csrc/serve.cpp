@@ -44,6 +44,21 @@ public:
             if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return LR_ERR_HIP;
             s.ws = static_cast<char*>(pool_) + (size_t)i * bytes_;
         }
+        // capture every bucket that fits a slot now (rank-only graphs), so no
+        // capture runs while requests wait; graphs with roots are captured on
+        // first use
+        if (cfg_.graphs) {
+            for (Slot& s : slots_) {
+                for (uint32_t j = 2 * GRAPH_MIN_LOG2; bucket_cap(j) < (1ull << 31); ++j) {
+                    const lr_batch_graph_config gc = graph_config(j, false);
+                    const size_t need = lr_batch_graph_workspace_bytes(&gc);
+                    if (need == 0 || need > bytes_) break;
+                    lr_batch_graph* g = nullptr;
+                    if (lr_batch_graph_create(&gc, s.ws, bytes_, &g) != LR_OK) break;
+                    s.graphs.emplace(2 * j, g);
+                }
+            }
+        }
         return LR_OK;
     }
 
@@ -105,13 +120,8 @@ private:
         }
         uint32_t j = 2 * GRAPH_MIN_LOG2;
         while (j < 62 && bucket_cap(j) < N) ++j;
-        const uint64_t cap = bucket_cap(j);
-        if (cap >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
-        lr_batch_graph_config gc{};
-        gc.max_elements = cap;
-        gc.max_requests = cfg_.max_batch ? cfg_.max_batch : 1;
-        gc.want_root = root ? 1u : 0u;
-        gc.opts = cfg_.opts;
+        if (bucket_cap(j) >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+        const lr_batch_graph_config gc = graph_config(j, root);
         const uint32_t key = 2 * j + (root ? 1u : 0u);  // the root column costs placement bandwidth
         auto it = s.graphs.find(key);
         if (it == s.graphs.end()) {
@@ -125,6 +135,15 @@ private:
         const lr_status st = lr_batch_graph_launch(it->second, reqs, count, s.stream);
         if (st == LR_OK) graph_launches_++;
         return st;
+    }
+
+    lr_batch_graph_config graph_config(uint32_t j, bool root) const {
+        lr_batch_graph_config gc{};
+        gc.max_elements = bucket_cap(j);
+        gc.max_requests = cfg_.max_batch ? cfg_.max_batch : 1;
+        gc.want_root = root ? 1u : 0u;
+        gc.opts = cfg_.opts;
+        return gc;
     }
 
     static uint64_t bucket_cap(uint32_t j) {  // 2^(j/2), rounded up
