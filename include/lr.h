@@ -317,17 +317,39 @@ lr_status lr_euler_tree(const uint32_t* succ, const uint32_t* down, const uint32
 /* Plan autotuner (the paper fixes its ruler-count constants by a parameter
  * study, Section 3 "Methodology"; this does the same on the caller's input).
  * Times lr_rank (w == LR_W_NONE, weight NULL) or lr_prefix_sum (any other w)
- * on `succ` for a set of candidate ruler spacings of the first two levels,
- * keeping `base`'s seed, flags other than LR_VALIDATE, base_max and
- * lane_walks, and writes the fastest option set to *best (its spacing list
- * filled for every level). The trial calls write their outputs to the tail
- * of `ws` (n x 4 B, weighted n x 8 B) and use the rest as their workspace;
- * candidates that do not fit are skipped (LR_ERR_WORKSPACE if none fits).
- * `ms` (may be NULL) receives up to `cap` timings, in the order the
- * candidates were tried; *tried (may be NULL) their number. Synchronises
+ * on `succ` in three stages, each keeping the fastest so far and varying one
+ * group: the ruler spacings of the first two levels (16..128 x 8..32), then
+ * the base-case size, then walks per lane and the refill threshold. It keeps
+ * `base`'s seed and flags other than LR_VALIDATE / LR_PROFILE, writes the
+ * fastest option set to *best (its spacing list filled for every level) and
+ * stores it in the autotune cache under (device, floor(log2 n), weighted):
+ * every later call of this process on that device whose options leave
+ * spacing[0], base_max, lane_walks and refill at 0 (NULL options included)
+ * and do not ask for LR_SPAWN takes the cached entry; its results are the
+ * same whatever the plan, but its workspace size may change, so query
+ * *_workspace_bytes after tuning. The trial calls write their outputs to
+ * the tail of `ws` (n x 4 B, weighted n x 8 B) and use the rest as their
+ * workspace; candidates that do not fit are skipped (LR_ERR_WORKSPACE if
+ * none fits). `ms` (may be NULL) receives up to `cap` timings, in the order
+ * the candidates were tried; *tried (may be NULL) their number. Synchronises
  * `stream`. */
 lr_status lr_autotune(const uint32_t* succ, const void* weight, lr_wtype w, uint64_t n, void* ws, size_t ws_bytes,
                       const lr_opts* base, lr_opts* best, double* ms, int cap, int* tried, void* stream);
+
+/* The autotune cache (host memory, per process, thread-safe). Entries are
+ * keyed by the device ("gfx950:256": architecture and compute units of the
+ * device current at the first use; "none" without a device), the input size
+ * bucket floor(log2 n) and whether the call is weighted.
+ *   lr_autotune_arch: the device key lookups use.
+ *   lr_autotune_cache_save / _load: a text file, one entry per line
+ *     (arch log2n weighted k0 k1 base_max lane_walks refill ms); loading
+ *     checks every value as the planner checks user options, adds or
+ *     replaces entries, and changes nothing on LR_ERR_INVALID_ARG. */
+const char* lr_autotune_arch(void);
+int lr_autotune_cache_entries(void);
+void lr_autotune_cache_clear(void);
+lr_status lr_autotune_cache_save(const char* path);
+lr_status lr_autotune_cache_load(const char* path);
 
 /* Per-phase device times (milliseconds) of the last call made with
  * LR_PROFILE on this thread: [0] predecessor marks, [1] head compaction,

@@ -87,6 +87,11 @@ def load():
         "lr_prefix_sum_wyllie": (st, [vp, vp, st, vp, vp, vp, u64, vp, sz, vp]),
         "lr_profile_last": (st, [P(ctypes.c_double), st]),
         "lr_autotune": (st, [vp, vp, st, u64, vp, sz, P(lr_opts), P(lr_opts), P(ctypes.c_double), st, P(st), vp]),
+        "lr_autotune_arch": (ctypes.c_char_p, []),
+        "lr_autotune_cache_entries": (st, []),
+        "lr_autotune_cache_clear": (None, []),
+        "lr_autotune_cache_save": (st, [ctypes.c_char_p]),
+        "lr_autotune_cache_load": (st, [ctypes.c_char_p]),
         "lr_euler_tree_workspace_bytes": (sz, [u64, P(lr_opts)]),
         "lr_calibrate_workspace_bytes": (sz, []),
         "lr_calibrate": (st, [vp, sz, P(ctypes.c_double), st, vp]),
@@ -275,6 +280,26 @@ def lr_autotune(succ, weight, ws, base=None, stream=None):
                            ws.numel() * ws.element_size(), _opts(base), ctypes.byref(best), ms, 64,
                            ctypes.byref(tried), _stream(stream))
     return s, best, list(ms[:tried.value])
+
+
+def autotune_arch() -> str:
+    return load().lr_autotune_arch().decode()
+
+
+def autotune_cache_entries() -> int:
+    return int(load().lr_autotune_cache_entries())
+
+
+def autotune_cache_clear() -> None:
+    load().lr_autotune_cache_clear()
+
+
+def autotune_cache_save(path: str) -> int:
+    return load().lr_autotune_cache_save(path.encode())
+
+
+def autotune_cache_load(path: str) -> int:
+    return load().lr_autotune_cache_load(path.encode())
 
 
 def lr_profile_last() -> list[float]:

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblr.so")
-SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "tree.hip", "calib.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "tree.hip", "calib.hip", "noalloc.hip", "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -209,6 +209,13 @@ static bool use_log(uint64_t m0, uint32_t levels, const lr_opts* o) {
 lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, PlanSet* ps) {
     *ps = PlanSet{};
     if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    // plan options left at their defaults take the autotune cache's entry
+    // for this device and size bucket, if there is one
+    lr_opts tuned;
+    if (!(o && ((o->flags & LR_SPAWN) || o->spacing[0] || o->base_max || o->lane_walks || o->refill))) {
+        tuned = o ? *o : lr_opts{};
+        if (tune_lookup(n, weighted, &tuned)) o = &tuned;
+    }
     const bool force = o && (o->flags & LR_LOCAL);
     const bool never = o && (o->flags & LR_NO_LOCAL);
     const bool spawn = o && (o->flags & LR_SPAWN);
@@ -672,81 +679,4 @@ extern "C" int lr_profile_last(double* ms, int cap) {
     int k = std::min(cap, 8);
     for (int i = 0; i < k; ++i) ms[i] = out[i];
     return k;
-}
-
-extern "C" lr_status lr_autotune(const uint32_t* succ, const void* weight, lr_wtype w, uint64_t n, void* ws,
-                                 size_t ws_bytes, const lr_opts* base, lr_opts* best, double* ms, int cap,
-                                 int* tried, void* stream) {
-    if (!succ || !best || (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64)) return LR_ERR_INVALID_ARG;
-    if (n == 0 || n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
-    if ((w == LR_W_NONE) != (weight == nullptr)) return LR_ERR_INVALID_ARG;
-    const bool weighted = w != LR_W_NONE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    lr_opts b{};
-    if (base) b = *base;
-    b.flags &= ~(uint32_t)LR_VALIDATE;
-    // trial outputs go to the tail of the caller's workspace; the rest is the
-    // trial calls' workspace
-    const size_t out_bytes = (size_t)n * (weighted ? 8 : 4);
-    if (ws_bytes <= out_bytes + ALIGN) return LR_ERR_WORKSPACE;
-    char* wsb = static_cast<char*>(ws);
-    const size_t trial_ws = (ws_bytes - out_bytes - ALIGN) / ALIGN * ALIGN;
-    void* out = wsb + trial_ws + ALIGN;
-    const uint32_t k0s[] = {16, 32, 64, 128};
-    const uint32_t k1s[] = {8, 16, 32};
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return LR_ERR_HIP;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return LR_ERR_HIP;
-    }
-    float best_ms = 1e30f;
-    bool found = false;
-    int count = 0;
-    lr_status result = LR_OK;
-    for (uint32_t k0 : k0s) {
-        for (uint32_t k1 : k1s) {
-            lr_opts o = b;
-            for (int l = 0; l < LR_MAX_LEVELS; ++l) o.spacing[l] = 0;
-            o.spacing[0] = k0;
-            o.spacing[1] = k1;
-            Plan p;
-            if (make_plan(n, weighted, &o, 0, &p) != LR_OK) continue;
-            if (p.levels < 2 && k1 != k1s[0]) continue;  // second spacing unused: try it once
-            if (p.total > trial_ws) continue;
-            auto run = [&]() -> lr_status {
-                return weighted ? lr_prefix_sum(succ, weight, w, static_cast<int64_t*>(out), nullptr, nullptr, n, ws,
-                                                trial_ws, &o, stream)
-                                : lr_rank(succ, static_cast<uint32_t*>(out), nullptr, n, ws, trial_ws, &o, stream);
-            };
-            lr_status s = run();  // warm-up
-            if (s != LR_OK) { result = s; break; }
-            if (hipEventRecord(e0, st) != hipSuccess) { result = LR_ERR_HIP; break; }
-            const int reps = 3;
-            for (int r = 0; r < reps && s == LR_OK; ++r) s = run();
-            if (s != LR_OK) { result = s; break; }
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                result = LR_ERR_HIP;
-                break;
-            }
-            float t = 0;
-            if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { result = LR_ERR_HIP; break; }
-            t /= reps;
-            if (ms && count < cap) ms[count] = t;
-            ++count;
-            if (t < best_ms) {
-                best_ms = t;
-                *best = o;
-                for (uint32_t l = 0; l < p.levels; ++l) best->spacing[l] = 1u << p.log2k[l];
-                found = true;
-            }
-        }
-        if (result != LR_OK) break;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (tried) *tried = count;
-    if (result != LR_OK) return result;
-    if (base) best->flags = base->flags;
-    return found ? LR_OK : LR_ERR_WORKSPACE;
 }

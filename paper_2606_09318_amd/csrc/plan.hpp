@@ -210,6 +210,11 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
 // The same, keeping only p (its total covers every path).
 lr_status make_plan(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch_count, Plan* p);
 
+// Autotune cache (tune.cpp): fills o's plan options (spacing of the first
+// two levels, base size, walks per lane, refill) from the entry of the
+// current device, n's size bucket (floor(log2 n)) and weighted, if any.
+bool tune_lookup(uint64_t n, bool weighted, lr_opts* o);
+
 // Base-case shared memory bytes for m elements.
 inline size_t base_lds_bytes(uint64_t m, bool weighted) {
     return (size_t)m * (weighted ? 14 : 6) + 64;

@@ -44,8 +44,15 @@ def test_graph_capture_and_replays(n, flags):
         torch.empty(1 << 20, device="cuda").normal_()  # unrelated work between replays
 
 
+@pytest.fixture
+def empty_cache():
+    lr.autotune_cache_clear()
+    yield
+    lr.autotune_cache_clear()
+
+
 @pytest.mark.parametrize("weighted", [False, True])
-def test_autotune_returns_valid_options(weighted):
+def test_autotune_returns_valid_options(weighted, empty_cache):
     n = (1 << 22) + 77
     print(f"case: autotune weighted={weighted}", flush=True)
     F = workloads.forest(n, mean=64, n_long=2, long_len=1 << 20, seed=71)
@@ -108,3 +115,44 @@ def test_graph_capture_prefix_sum_switching_paths():
         assert np.array_equal(sm.cpu().numpy(), es), f"replay {i}"
         assert np.array_equal(host_u32(rank), er), f"replay {i}"
         torch.empty(1 << 20, device="cuda").normal_()
+
+
+def test_autotune_cache_feeds_default_calls(empty_cache, tmp_path):
+    """After lr_autotune on a 2^20-element list, calls with default options on
+    inputs of the same size bucket take the tuned plan (and still equal the
+    oracle), batches of that total too; the entry survives a save/load."""
+    n = (1 << 20) + 5
+    print("case: autotune cache", flush=True)
+    L = workloads.random_list(n, seed=72)
+    succ = dev(L.succ)
+    ws = lr.workspace(4 * lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(spacing=(16, 8))) + n * 8 + 4096)
+    st, best, ms = lr.lr_autotune(succ, None, ws)
+    assert st == lr.LR_OK and len(ms) >= 12
+    assert lr.autotune_cache_entries() == 1
+    tuned = [best.spacing[i] for i in range(lr.LR_MAX_LEVELS) if best.spacing[i]]
+    p = lr.lr_plan_query(n)
+    assert [p.spacing[i] for i in range(p.levels)][:2] == tuned[:2] and p.base_max == best.base_max
+    _, er, et, _ = oracle.rank(L.succ)
+    r, t = lr.rank(succ)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(r), er) and np.array_equal(host_u32(t), et)
+    # another list of the same size bucket, alone and as a batch of two
+    M = workloads.block_list((1 << 20) + 999, 4096, seed=73)
+    m2 = dev(M.succ)
+    r2, _ = lr.rank(m2, want_root=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(r2), oracle.rank(M.succ)[1])
+    half = [workloads.random_list(600000, seed=74), workloads.random_list(500000, seed=75)]
+    items = [(dev(h.succ), torch.full((h.succ.size,), -1, dtype=torch.int32, device="cuda"), None) for h in half]
+    reqs = lr.requests(items)
+    bws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, 2))
+    assert lr.lr_rank_batch(reqs, 2, bws) == lr.LR_OK
+    torch.cuda.synchronize()
+    for h, (_, rk, _) in zip(half, items):
+        assert np.array_equal(host_u32(rk), oracle.rank(h.succ)[1])
+    f = str(tmp_path / "tuned.txt")
+    assert lr.autotune_cache_save(f) == lr.LR_OK
+    lr.autotune_cache_clear()
+    assert lr.autotune_cache_load(f) == lr.LR_OK
+    p2 = lr.lr_plan_query(n)
+    assert [p2.spacing[i] for i in range(p2.levels)] == [p.spacing[i] for i in range(p.levels)]
