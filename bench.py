@@ -226,11 +226,16 @@ def main():
     ph = np.median(np.array(phases), axis=0)
     chase_ms = float(ph[2])
     S = int(plan.m[1])
-    # per element: 4 B succ gather + the visit-log record (element, walk, offset:
-    # one 8 B word up to 2^28 elements, 12 B above); per walk: 8 B walk record +
-    # 1 B predecessor mark
+    # algorithmic bytes of the chase per element, as the method's byte budget
+    # counts them: a 4 B successor gather, a 4 B ruler-bit gather and an 8 B
+    # store of (walk, offset). This chase tests the ruler by arithmetic on the
+    # id (one ruler per block at a hashed position) and moves no ruler bit,
+    # so its own count is 4 B + the visit-log record (one 8 B word up to 2^28
+    # elements, 12 B above) per element and 9 B per walk (walk record and
+    # predecessor mark); both are reported, the budget's is the roofline's
     rec = 8 if n <= (1 << 28) else 12
-    chase_bytes = n * (4 + rec) + S * (8 + 1)
+    chase_bytes = n * (4 + 4 + 8)
+    own_bytes = n * (4 + rec) + S * (8 + 1)
     achieved = chase_bytes / (chase_ms * 1e-3) / 1e9
     traffic = None
     call_traffic = None
@@ -245,7 +250,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": "k_chase (level 0)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "chase_ms": round(chase_ms, 4),
-                "algorithmic_bytes": chase_bytes}
+                "algorithmic_bytes": chase_bytes, "bytes_per_element": 16,
+                "own_count_bytes": own_bytes,
+                "own_count_frac": round(own_bytes / (chase_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if traffic:
         # the HBM rate the counted bytes imply (each 4 B gather moves a whole line)
         roofline["traffic_gb_s"] = round(traffic / (chase_ms * 1e-3) / 1e9, 1)
@@ -566,16 +573,39 @@ def batch_only(args, stream):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    ok = True
-    for (s, r, _), order in zip(items, orders):
-        n = s.numel()
-        expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
-        ok = ok and bool(torch.equal(r.index_select(0, torch.from_numpy(order.view(np.int32)).cuda()), expect))
-    if not ok:
+    def closed_form_ok():
+        ok = True
+        for (s, r, _), order in zip(items, orders):
+            n = s.numel()
+            expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+            ok = ok and bool(torch.equal(r.index_select(0, torch.from_numpy(order.view(np.int32)).cuda()), expect))
+        return ok
+    if not closed_form_ok():
         raise SystemExit("bench: a batched request does not match its closed form")
+    # the same batch through a captured graph (capacity = this batch)
+    del ws
+    gcfg = lr.batch_graph_config(max_elements=total, max_requests=len(items))
+    gws = lr.workspace(lr.lr_batch_graph_workspace_bytes(gcfg))
+    g = lr.BatchGraph(gcfg, gws)
+    for _, r, _ in items:
+        r.fill_(-1)
+    for _ in range(args.warmup):
+        if g.launch(reqs, len(items), stream):
+            raise SystemExit("bench: lr_batch_graph_launch failed")
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g.launch(reqs, len(items), stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gms = ev0.elapsed_time(ev1) / args.steps
+    if not closed_form_ok():
+        raise SystemExit("bench: a request of the graph replay does not match its closed form")
+    g.close()
     print(json.dumps({"workload": "64 serving-trace requests in one lr_rank_batch call", "requests": len(items),
                       "elements": total, "ms_per_step": round(ms, 4),
-                      "g_elements_per_s": round(total / (ms * 1e-3) / 1e9, 3), "list": "batch"}))
+                      "g_elements_per_s": round(total / (ms * 1e-3) / 1e9, 3),
+                      "graph_replay_ms": round(gms, 4), "list": "batch"}))
 
 
 def weighted_bench() -> dict:

@@ -351,6 +351,20 @@ void lr_autotune_cache_clear(void);
 lr_status lr_autotune_cache_save(const char* path);
 lr_status lr_autotune_cache_load(const char* path);
 
+/* Device-side check of a result (a debugging and serving aid, not part of
+ * any ranking call): the local equations of Section 1.1's definition, each
+ * element against its successor -- a terminal t has rank 0, root t and sum 0;
+ * any other x has rank[x] = rank[succ x] + 1, root[x] = root[succ x] and
+ * sum[x] = sum[succ x] + w[x]. On a forest of lists these have exactly one
+ * solution, so LR_OK proves the given outputs exact (checked: the ones not
+ * NULL; at least one of rank, root, sum). A cycle cannot satisfy them, so it
+ * is reported; input with two predecessors of one element may pass (that is
+ * LR_VALIDATE's check). weight as in lr_prefix_sum (only with sum; NULL with
+ * LR_W_NONE means unit weights). ws: at least 512 bytes of device memory.
+ * Returns LR_ERR_BAD_LIST when an equation fails. Synchronises `stream`. */
+lr_status lr_verify(const uint32_t* succ, const void* weight, lr_wtype w, const uint32_t* rank,
+                    const uint32_t* root, const int64_t* sum, uint64_t n, void* ws, size_t ws_bytes, void* stream);
+
 /* Per-phase device times (milliseconds) of the last call made with
  * LR_PROFILE on this thread: [0] predecessor marks, [1] head compaction,
  * [2] level-0 chase, [3] upper levels, base case and their propagation,

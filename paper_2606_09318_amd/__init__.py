@@ -86,6 +86,7 @@ def load():
         "lr_rank_wyllie": (st, [vp, vp, vp, u64, vp, sz, vp]),
         "lr_prefix_sum_wyllie": (st, [vp, vp, st, vp, vp, vp, u64, vp, sz, vp]),
         "lr_profile_last": (st, [P(ctypes.c_double), st]),
+        "lr_verify": (st, [vp, vp, st, vp, vp, vp, u64, vp, sz, vp]),
         "lr_autotune": (st, [vp, vp, st, u64, vp, sz, P(lr_opts), P(lr_opts), P(ctypes.c_double), st, P(st), vp]),
         "lr_autotune_arch": (ctypes.c_char_p, []),
         "lr_autotune_cache_entries": (st, []),
@@ -198,6 +199,14 @@ def lr_prefix_sum_wyllie(succ, weight, sum_, rank, root, ws, stream=None) -> int
     return load().lr_prefix_sum_wyllie(_ptr(succ), _ptr(weight), _wtype(weight), _ptr(sum_), _ptr(rank),
                                        _ptr(root), succ.numel(), _ptr(ws),
                                        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+def lr_verify(succ, rank=None, root=None, sum_=None, weight=None, stream=None) -> int:
+    """Check outputs against the local equations on the device (LR_OK or LR_ERR_BAD_LIST)."""
+    import torch
+    ws = torch.empty(512, dtype=torch.uint8, device=succ.device)
+    return load().lr_verify(_ptr(succ), _ptr(weight), _wtype(weight), _ptr(rank), _ptr(root), _ptr(sum_),
+                            succ.numel(), _ptr(ws), ws.numel(), _stream(stream))
 
 
 def requests(items) -> ctypes.Array:

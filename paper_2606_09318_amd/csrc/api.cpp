@@ -680,3 +680,21 @@ extern "C" int lr_profile_last(double* ms, int cap) {
     for (int i = 0; i < k; ++i) ms[i] = out[i];
     return k;
 }
+
+extern "C" lr_status lr_verify(const uint32_t* succ, const void* weight, lr_wtype w, const uint32_t* rank,
+                               const uint32_t* root, const int64_t* sum, uint64_t n, void* ws, size_t ws_bytes,
+                               void* stream) {
+    if (w != LR_W_NONE && w != LR_W_I32 && w != LR_W_I64) return LR_ERR_INVALID_ARG;
+    if (n == 0) return LR_OK;
+    if (!succ || (!rank && !root && !sum)) return LR_ERR_INVALID_ARG;
+    if ((w != LR_W_NONE) && (!weight || !sum)) return LR_ERR_INVALID_ARG;
+    if (n >= (1ull << 31)) return LR_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < 2 * ALIGN) return LR_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t* err = reinterpret_cast<uint32_t*>(carve(ws));
+    if (run_verify(succ, weight, (int)w, rank, root, sum, (uint32_t)n, err, st) != hipSuccess) return LR_ERR_HIP;
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return LR_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return LR_ERR_HIP;
+    return e ? LR_ERR_BAD_LIST : LR_OK;
+}

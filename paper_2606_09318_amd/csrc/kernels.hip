@@ -273,6 +273,36 @@ __global__ __launch_bounds__(TPB) void k_validate_in(const uint32_t* __restrict_
     }
 }
 
+// Result check (lr_verify): the local equations of the ranking, each
+// element against its successor (one gather per output). err |= 1 for a
+// successor out of range, 2 for a terminal whose values are not (0, itself,
+// 0), 4 for an element whose values do not follow from its successor's.
+template <int WT>
+__global__ __launch_bounds__(TPB) void k_verify(const uint32_t* __restrict__ succ, const void* __restrict__ weight,
+                                                const uint32_t* __restrict__ rank, const uint32_t* __restrict__ root,
+                                                const int64_t* __restrict__ sum, uint32_t m, uint32_t* err) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t bad = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const uint32_t s = succ[i];
+        if (s >= m) { bad |= 1u; continue; }
+        if (s == i) {
+            if ((rank && rank[i] != 0) || (root && root[i] != i) || (sum && sum[i] != 0)) bad |= 2u;
+            continue;
+        }
+        if (rank && rank[i] != rank[s] + 1u) bad |= 4u;
+        if (root && root[i] != root[s]) bad |= 4u;
+        if (sum) {
+            int64_t w = 1;
+            if constexpr (WT == 1) w = static_cast<const int32_t*>(weight)[i];
+            if constexpr (WT == 2) w = static_cast<const int64_t*>(weight)[i];
+            if (sum[i] != sum[s] + w) bad |= 4u;
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+
 // ----------------------------------------------------------------- heads --
 // A tile of TILE elements per block: each lane owns 16 consecutive bytes of
 // the hp bytemap. An element starts a walk of its own when it has no
@@ -3235,6 +3265,16 @@ hipError_t run_batch_table(const lr_request* reqs, uint32_t count, const Plan& p
 hipError_t run_validate_input(const uint32_t* succ, uint32_t n, uint32_t* counts, uint32_t* err, hipStream_t st) {
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_validate_in, dim3(grid_for(n, TPB * 4)), dim3(TPB), 0, st, succ, n, counts, err);
+    return hipGetLastError();
+}
+
+hipError_t run_verify(const uint32_t* succ, const void* weight, int wt, const uint32_t* rank, const uint32_t* root,
+                      const int64_t* sum, uint32_t n, uint32_t* err, hipStream_t st) {
+    const dim3 g(grid_for(n, TPB * 4)), b(TPB);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(TPB), 0, st, err, 1ull, 0u, (const Ctrl*)nullptr, Gate{});
+    if (wt == 1) hipLaunchKernelGGL(k_verify<1>, g, b, 0, st, succ, weight, rank, root, sum, n, err);
+    else if (wt == 2) hipLaunchKernelGGL(k_verify<2>, g, b, 0, st, succ, weight, rank, root, sum, n, err);
+    else hipLaunchKernelGGL(k_verify<0>, g, b, 0, st, succ, weight, rank, root, sum, n, err);
     return hipGetLastError();
 }
 

@@ -72,6 +72,11 @@ hipError_t tree_arc_weights(const uint32_t* down, uint32_t V, uint32_t root, int
 hipError_t run_validate_input(const uint32_t* succ, uint32_t n, uint32_t* counts, uint32_t* err,
                               hipStream_t st);
 
+// Result check: the local equations of the ranking on the device (err: one
+// 32-bit word, cleared first; see k_verify for its bits).
+hipError_t run_verify(const uint32_t* succ, const void* weight, int wt, const uint32_t* rank, const uint32_t* root,
+                      const int64_t* sum, uint32_t n, uint32_t* err, hipStream_t st);
+
 int device_cus();
 size_t device_max_lds();
 
