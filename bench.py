@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--list", choices=["random", "block", "forest", "euler", "tree", "batch"], default="random",
                     help="with --only-main: the random list, the block-local list of the same size, or the "
                          "2^27 forest with int64 weights (prefix sums, rank and root)")
+    ap.add_argument("--batch-graph", action="store_true",
+                    help="with --list batch: replay the batch as a captured graph (lr_batch_graph)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
@@ -557,12 +559,23 @@ def batch_only(args, stream):
         orders.append(Lq.order)
     total = sum(q.n for q in tr)
     reqs = lr.requests(items)
-    ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items)))
+    if args.batch_graph:
+        # captured once for a capacity equal to this batch, replayed per step
+        cfg = lr.batch_graph_config(max_elements=total, max_requests=len(items))
+        ws = lr.workspace(lr.lr_batch_graph_workspace_bytes(cfg))
+        g = lr.BatchGraph(cfg, ws)
 
-    def step():
-        st = lr.lr_rank_batch(reqs, len(items), ws, None, stream)
-        if st:
-            raise lr.LrError(st, "lr_rank_batch")
+        def step():
+            st = g.launch(reqs, len(items), stream)
+            if st:
+                raise lr.LrError(st, "lr_batch_graph_launch")
+    else:
+        ws = lr.workspace(lr.lr_batch_workspace_bytes(reqs, len(items)))
+
+        def step():
+            st = lr.lr_rank_batch(reqs, len(items), ws, None, stream)
+            if st:
+                raise lr.LrError(st, "lr_rank_batch")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -573,39 +586,17 @@ def batch_only(args, stream):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    def closed_form_ok():
-        ok = True
-        for (s, r, _), order in zip(items, orders):
-            n = s.numel()
-            expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
-            ok = ok and bool(torch.equal(r.index_select(0, torch.from_numpy(order.view(np.int32)).cuda()), expect))
-        return ok
-    if not closed_form_ok():
-        raise SystemExit("bench: a batched request does not match its closed form")
-    # the same batch through a captured graph (capacity = this batch)
-    del ws
-    gcfg = lr.batch_graph_config(max_elements=total, max_requests=len(items))
-    gws = lr.workspace(lr.lr_batch_graph_workspace_bytes(gcfg))
-    g = lr.BatchGraph(gcfg, gws)
-    for _, r, _ in items:
-        r.fill_(-1)
-    for _ in range(args.warmup):
-        if g.launch(reqs, len(items), stream):
-            raise SystemExit("bench: lr_batch_graph_launch failed")
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        g.launch(reqs, len(items), stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    gms = ev0.elapsed_time(ev1) / args.steps
-    if not closed_form_ok():
-        raise SystemExit("bench: a request of the graph replay does not match its closed form")
-    g.close()
-    print(json.dumps({"workload": "64 serving-trace requests in one lr_rank_batch call", "requests": len(items),
+    for (s, r, _), order in zip(items, orders):
+        n = s.numel()
+        expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+        if not torch.equal(r.index_select(0, torch.from_numpy(order.view(np.int32)).cuda()), expect):
+            raise SystemExit("bench: a batched request does not match its closed form")
+    if args.batch_graph:
+        g.close()
+    call = "one lr_batch_graph replay" if args.batch_graph else "one lr_rank_batch call"
+    print(json.dumps({"workload": f"64 serving-trace requests in {call}", "requests": len(items),
                       "elements": total, "ms_per_step": round(ms, 4),
-                      "g_elements_per_s": round(total / (ms * 1e-3) / 1e9, 3),
-                      "graph_replay_ms": round(gms, 4), "list": "batch"}))
+                      "g_elements_per_s": round(total / (ms * 1e-3) / 1e9, 3), "list": "batch"}))
 
 
 def weighted_bench() -> dict:
