@@ -379,11 +379,14 @@ int lr_profile_last(double* ms, int cap);
 
 /* Device calibration (diagnostic, not part of any ranking call): on the
  * current device, with `ws` as scratch (at least lr_calibrate_workspace_bytes,
- * about 3 GiB, contents destroyed), times 2^28 accesses of each kind and
+ * about 4 GiB, contents destroyed), times 2^28 accesses of each kind and
  * writes up to `cap` rates to `out`: [0] streaming copy of 1 GiB (GB/s, read +
  * written bytes), [1] 4 B gathers at hashed positions of a 1 GiB array, [2] 8 B
  * stores into 1 GiB, [3] 8 B stores into 256 MiB, [4] 1 B stores into 256 MiB,
- * [5] bit sets (atomic OR) in a 32 MiB bitmap (G accesses/s). These are the
+ * [5] bit sets (atomic OR) in a 32 MiB bitmap, [6] records (x, v) streamed
+ * from two 1 GiB arrays and v stored at x, the x grouped by ranges of 2^15
+ * ids and every range stored by the workgroups of one XCD (G accesses/s).
+ * These are the
  * ceilings the ranking kernels' random accesses are measured against.
  * Synchronises `stream`. Returns the number of rates written, or a negative
  * lr_status. */

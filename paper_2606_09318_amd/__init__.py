@@ -382,10 +382,10 @@ def calibrate(device="cuda", stream=None) -> dict:
     """Device access rates (lr_calibrate): streaming copy GB/s and random
     gather / store / bit-set rates in G accesses/s."""
     ws = workspace(load().lr_calibrate_workspace_bytes(), device)
-    out = (ctypes.c_double * 6)()
-    k = load().lr_calibrate(_ptr(ws), ws.numel(), out, 6, _stream(stream))
+    out = (ctypes.c_double * 7)()
+    k = load().lr_calibrate(_ptr(ws), ws.numel(), out, 7, _stream(stream))
     if k < 0:
         raise LrError(-k, "lr_calibrate")
     names = ["copy_gb_s", "gather4_1gib_g_s", "store8_1gib_g_s", "store8_256mib_g_s", "store1_256mib_g_s",
-             "bitset_32mib_g_s"]
+             "bitset_32mib_g_s", "store4_xcd_ranges_g_s"]
     return {nm: round(out[i], 2) for i, nm in enumerate(names[:k])}

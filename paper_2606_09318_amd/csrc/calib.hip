@@ -64,11 +64,49 @@ __global__ __launch_bounds__(CAL_TPB) void k_cal_bitset(uint32_t* __restrict__ b
     }
 }
 
+// Records (x, v) grouped by ranges of 2^s ids, x a bijection of its range
+// (an odd multiple plus a per-range offset, modulo the range length)
+__global__ __launch_bounds__(CAL_TPB) void k_cal_range_init(uint32_t* __restrict__ x, uint32_t* __restrict__ v,
+                                                            uint32_t s, uint32_t n) {
+    CAL_LOOP {
+        const uint32_t c = i >> s, mask = (1u << s) - 1;
+        x[i] = (c << s) | (((i & mask) * 0x9e3779b1u + cal_hash(c)) & mask);
+        v[i] = i;
+    }
+}
+
+// out[x] = v for every record, each range's records stored by the workgroups
+// of one XCD (workgroup i runs on XCD i mod 8, and XCD x takes ranges x,
+// x + 8, ... in order, tiles of CAL_RANGE_PER x CAL_TPB records): the access
+// pattern of a placement pass that scattered each element range straight
+// into the output through the owning XCD's L2
+constexpr int CAL_RANGE_PER = 8;
+__global__ __launch_bounds__(CAL_TPB) void k_cal_range4(const uint32_t* __restrict__ x, const uint32_t* __restrict__ v,
+                                                        uint32_t* __restrict__ out, uint32_t s, uint32_t n) {
+    constexpr uint32_t T = CAL_TPB * CAL_RANGE_PER;
+    const uint32_t tiles = n / T, tpc = (1u << s) / T;
+    const uint32_t lane8 = blockIdx.x % 8, step = gridDim.x / 8;
+    for (uint32_t q = blockIdx.x / 8;; q += step) {
+        const uint32_t c = lane8 + 8 * (q / tpc);
+        if (c * tpc >= tiles) break;
+        const uint32_t tile = c * tpc + q % tpc;
+        uint32_t xs[CAL_RANGE_PER], vs[CAL_RANGE_PER];
+#pragma unroll
+        for (int j = 0; j < CAL_RANGE_PER; ++j) {
+            const uint32_t i = tile * T + j * CAL_TPB + threadIdx.x;
+            xs[j] = x[i];
+            vs[j] = v[i];
+        }
+#pragma unroll
+        for (int j = 0; j < CAL_RANGE_PER; ++j) out[xs[j]] = vs[j];
+    }
+}
+
 }  // namespace lr
 
 using namespace lr;
 
-extern "C" size_t lr_calibrate_workspace_bytes(void) { return ((size_t)3 << 30) + 256; }
+extern "C" size_t lr_calibrate_workspace_bytes(void) { return ((size_t)4 << 30) + 256; }
 
 extern "C" int lr_calibrate(void* ws, size_t ws_bytes, double* out, int cap, void* stream) {
     const uint32_t N = 1u << 28;
@@ -106,7 +144,7 @@ extern "C" int lr_calibrate(void* ws, size_t ws_bytes, double* out, int cap, voi
     const uint32_t m8g = (1u << 27) - 1;   // 2^27 records of 8 B: 1 GiB
     const uint32_t m8w = (1u << 25) - 1;   // 2^25 records of 8 B: 256 MiB
     const uint32_t m1b = (1u << 28) - 1;   // 2^28 bytes
-    double v[6];
+    double v[7];
     // [0] streaming copy of 1 GiB, GB/s (read + write bytes)
     const double tc = timed([&] { hipLaunchKernelGGL(k_cal_copy, G, B, 0, st, reinterpret_cast<const uint4*>(a),
                                                      reinterpret_cast<uint4*>(b), N / 4); });
@@ -130,9 +168,19 @@ extern "C" int lr_calibrate(void* ws, size_t ws_bytes, double* out, int cap, voi
     const double tb = timed([&] { hipLaunchKernelGGL(k_cal_bitset, G, B, 0, st, reinterpret_cast<uint32_t*>(b), m1b,
                                                      N, 5u); });
     v[5] = N / (tb * 1e-3) / 1e9;
+    // [6] 2^28 records (x, v) of two 1 GiB arrays streamed in, v stored at x,
+    // x grouped in XCD-owned ranges of 2^15 ids (128 KiB of output each); the
+    // records take the gather source and a third GiB past the store targets
+    static_assert(((1u << 15) % (CAL_TPB * CAL_RANGE_PER)) == 0, "a range is whole tiles");
+    uint32_t* rv = reinterpret_cast<uint32_t*>(w + ((size_t)3 << 30));
+    hipLaunchKernelGGL(k_cal_range_init, dim3(8192), B, 0, st, a, rv, 15u, N);
+    if (hipGetLastError() != hipSuccess) fail = true;
+    const double tr = timed([&] { hipLaunchKernelGGL(k_cal_range4, dim3(nblocks / 8 * 8), B, 0, st, a, rv,
+                                                     reinterpret_cast<uint32_t*>(b), 15u, N); });
+    v[6] = N / (tr * 1e-3) / 1e9;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (fail) return -(int)LR_ERR_HIP;
-    for (int i = 0; i < 6 && k < cap; ++i) out[k++] = v[i];
+    for (int i = 0; i < 7 && k < cap; ++i) out[k++] = v[i];
     return k;
 }

@@ -1,4 +1,4 @@
-"""The device calibration entry point returns the six access rates, each in
+"""The device calibration entry point returns the seven access rates, each in
 a plausible range for a device with HBM (diagnostic only)."""
 import pytest
 
@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 def test_calibrate_rates():
     r = lr.calibrate()
-    assert len(r) == 6
+    assert len(r) == 7
     assert r["copy_gb_s"] > 500                       # streaming: far above random access
     assert 1 < r["gather4_1gib_g_s"] < 1000
     assert all(v > 0.5 for v in r.values())
