@@ -30,9 +30,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_MAIN, help="list length (default 2^28)")
     ap.add_argument("--only-main", action="store_true", help="time the main step only (for profilers)")
-    ap.add_argument("--list", choices=["random", "block", "forest", "euler", "tree", "batch"], default="random",
-                    help="with --only-main: the random list, the block-local list of the same size, or the "
-                         "2^27 forest with int64 weights (prefix sums, rank and root)")
+    ap.add_argument("--list", choices=["random", "block", "forest", "euler", "tree", "batch", "rulers-last"],
+                    default="random",
+                    help="with --only-main: the random list, the block-local list of the same size, the "
+                         "2^27 forest with int64 weights (prefix sums, rank and root), the Euler tour / tree, "
+                         "the 64-request batch, or a list of the same size ordered against the ruler sampling")
     ap.add_argument("--batch-graph", action="store_true",
                     help="with --list batch: replay the batch as a captured graph (lr_batch_graph)")
     ap.add_argument("--no-serve", action="store_true")
@@ -156,8 +158,16 @@ def main():
         batch_only(args, stream)
         return
     t0 = time.time()
-    L = workloads.random_list(n, seed=2, stream=0) if args.list == "random" else \
-        workloads.block_list(n, block=4096, seed=2, stream=1)
+    if args.list == "rulers-last":
+        # every level-0 sampled ruler after all other elements: the order the
+        # walk cap and its fallback exist for (test-input builder)
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from adversarial import rulers_last
+        L = rulers_last(n, int(lr.lr_plan_query(n).spacing[0]))
+    elif args.list == "random":
+        L = workloads.random_list(n, seed=2, stream=0)
+    else:
+        L = workloads.block_list(n, block=4096, seed=2, stream=1)
     gen_s = time.time() - t0
     succ = torch.from_numpy(L.succ.view(np.int32)).to(dev)
     rank = torch.empty(n, dtype=torch.int32, device=dev)
@@ -214,8 +224,14 @@ def main():
     if not ok:
         raise SystemExit("bench: ranks/roots do not match the closed form of the generated list")
     if args.only_main:
-        print(json.dumps({"metric": METRIC, "value": round(value, 4), "unit": "G elements/s",
-                          "ms_per_step": round(ms, 4), "n": n, "list": args.list}))
+        line = {"metric": METRIC, "value": round(value, 4), "unit": "G elements/s",
+                "ms_per_step": round(ms, 4), "n": n, "list": args.list}
+        if args.list == "rulers-last":
+            lr.lr_rank(succ, rank, None, ws, lr.make_opts(flags=lr.LR_PROFILE), stream)
+            ph = lr.lr_profile_last()
+            line["fallback_ran"] = bool(ph[7])
+            line["phases_ms"] = [round(v, 4) for v in ph[:7]]
+        print(json.dumps(line))
         return
 
     # per-phase times with HIP events on the launch stream (LR_PROFILE), and

@@ -95,6 +95,18 @@ def test_rulers_last_falls_back_and_matches_oracle(flags):
 
 
 @pytest.mark.gpu
+def test_rulers_last_above_2p21_sixteen_fold_rounds():
+    """Above 2^21 elements the fallback jumps 16 records per round (6 rounds
+    here) instead of 128; level 0 through the visit log as well."""
+    n = (1 << 22) + 5
+    print(f"case: rulers last, n={n}", flush=True)
+    L = rulers_last(n, plan_spacings(n)[0])
+    assert check_rank(L.succ) == 1.0
+    L = rulers_last(n, plan_spacings(n, lr.make_opts(flags=lr.LR_VISIT_LOG | lr.LR_NO_LOCAL))[0])
+    assert check_rank(L.succ, lr.make_opts(flags=lr.LR_VISIT_LOG | lr.LR_NO_LOCAL)) == 1.0
+
+
+@pytest.mark.gpu
 def test_level1_rulers_last_falls_back_and_matches_oracle():
     n = 1 << 18
     o = lr.make_opts(spacing=(16, 16))
