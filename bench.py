@@ -37,6 +37,8 @@ def parse():
                          "the 64-request batch, or a list of the same size ordered against the ruler sampling")
     ap.add_argument("--batch-graph", action="store_true",
                     help="with --list batch: replay the batch as a captured graph (lr_batch_graph)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="the plan autotuner on the random list of --n elements: default plan, search, tuned plan")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
@@ -134,6 +136,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4, "reps": 5}))
+        return
+
+    if args.autotune:
+        autotune_bench(args, stream)
         return
 
     if args.cpu_full:
@@ -613,6 +619,59 @@ def batch_only(args, stream):
     print(json.dumps({"workload": f"64 serving-trace requests in {call}", "requests": len(items),
                       "elements": total, "ms_per_step": round(ms, 4),
                       "g_elements_per_s": round(total / (ms * 1e-3) / 1e9, 3), "list": "batch"}))
+
+
+def autotune_bench(args, stream):
+    """The plan autotuner on the random list (seed 2): default calls timed with
+    the built-in plan, lr_autotune on the same input, then default calls again
+    (the planner now takes the cached entry); every timed result checked
+    against the closed form."""
+    import numpy as np
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    n = args.n
+    L = workloads.random_list(n, seed=2, stream=0)
+    succ = torch.from_numpy(L.succ.view(np.int32)).cuda()
+    rank = torch.empty(n, dtype=torch.int32, device="cuda")
+    order = torch.from_numpy(L.order.view(np.int32)).cuda()
+    expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+
+    def timed():
+        ws = lr.workspace(lr.lr_workspace_bytes(n))
+        for _ in range(max(1, args.warmup)):
+            lr.lr_rank(succ, rank, None, ws, None, stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            if lr.lr_rank(succ, rank, None, ws, None, stream):
+                raise SystemExit("bench: lr_rank failed")
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        if not torch.equal(rank.index_select(0, order), expect):
+            raise SystemExit("bench: ranks do not match the closed form")
+        p = lr.lr_plan_query(n)
+        return round(ev0.elapsed_time(ev1) / args.steps, 4), [int(p.spacing[i]) for i in range(p.levels)]
+
+    lr.autotune_cache_clear()
+    default_ms, default_plan = timed()
+    tws = lr.workspace(lr.lr_workspace_bytes(n, lr.LR_W_NONE, lr.make_opts(spacing=(16, 8))) + n * 4 + 4096)
+    t0 = time.time()
+    st, best, trials = lr.lr_autotune(succ, None, tws, None, stream)
+    tune_s = time.time() - t0
+    if st:
+        raise lr.LrError(st, "lr_autotune")
+    del tws
+    torch.cuda.empty_cache()
+    tuned_ms, tuned_plan = timed()
+    print(json.dumps({"autotune": {"n": n, "list": "random (seed 2)", "default_ms": default_ms,
+                                   "default_spacing": default_plan, "tuned_ms": tuned_ms, "tuned_spacing": tuned_plan,
+                                   "tuned_base_max": int(best.base_max), "tuned_lane_walks": int(best.lane_walks),
+                                   "tuned_refill": int(best.refill), "candidates": len(trials),
+                                   "trial_ms": [round(t, 4) for t in trials], "search_s": round(tune_s, 2)}}))
 
 
 def weighted_bench() -> dict:
