@@ -37,6 +37,15 @@
  *     the call checks the input and the result on the device, synchronises the
  *     stream, and returns LR_ERR_BAD_LIST for such input.
  *   - Errors are returned as lr_status; nothing is thrown across the ABI.
+ *
+ * Debug build: the same sources built with LR_DEBUG_WRITES=1 (liblr_debug.so)
+ * export the same functions. There lr_rank and lr_prefix_sum count the writes
+ * of every store that relies on a single writer (a walk's slot per visited
+ * element, a predecessor mark per element), synchronise, and return
+ * LR_ERR_BAD_LIST unless every slot was written exactly once and every mark
+ * at most once, also without LR_VALIDATE. Their workspaces are larger
+ * (*_workspace_bytes of that library), automatic contraction is off, and
+ * calls must not run on several streams at once.
  */
 #ifndef LR_H
 #define LR_H

@@ -11,6 +11,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblr.so")
+# the same sources with LR_DEBUG_WRITES=1: every call counts its slot and mark
+# writes and fails with LR_ERR_BAD_LIST unless each has its one writer
+DEBUG_LIB = os.path.join(HERE, "liblr_debug.so")
 SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "tree.hip", "calib.hip", "noalloc.hip", "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -254,7 +254,8 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
     }
     // Automatic contraction: the contracted path's arrays share the workspace
     // with the plain path's (only one of them runs), after the common header.
-    ps->autol = !force && !never && !spawn && p->levels >= 1 && n >= LOCAL_AUTO_MIN_N;
+    // (debug builds count the plain path's writes: no automatic contraction there)
+    ps->autol = !force && !never && !spawn && p->levels >= 1 && n >= LOCAL_AUTO_MIN_N && !LR_DEBUG_WRITES;
     if (ps->autol) {
         Plan* q = &ps->lp;
         lr_opts lo = o ? *o : lr_opts{};
@@ -287,6 +288,10 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         off += align_up(((size_t)n / BATCH_CHUNK + batch_count + 1) * 16);
         p->off_batch_sums = off;
         off += align_up((size_t)batch_count * 16);
+    }
+    if (LR_DEBUG_WRITES) {
+        p->off_dbg = off;
+        for (uint32_t l = 0; l < p->levels; ++l) off += align_up((size_t)p->m[l] * 8);
     }
     p->total = off + ALIGN;  // room to align the caller's base pointer
     ps->lp.total = p->total;
@@ -375,6 +380,18 @@ static lr_status rank_common(const uint32_t* succ, const void* weight, int wt, b
     a.validate = opts && (opts->flags & LR_VALIDATE);
     a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
     prof_capped(a, p);
+    if (LR_DEBUG_WRITES) {
+        hipError_t e = run_debug_begin(a, p);
+        if (e == hipSuccess) e = run_srs(a);
+        if (e == hipSuccess) e = run_debug_check(a, p);
+        if (e != hipSuccess) return LR_ERR_HIP;
+        Ctrl c{};
+        if (hipMemcpyAsync(&c, a.ws + p.off_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, a.stream) != hipSuccess ||
+            hipStreamSynchronize(a.stream) != hipSuccess)
+            return LR_ERR_HIP;
+        if (c.err & ERR_DEBUG_WRITES) return LR_ERR_BAD_LIST;
+        return finish(hipSuccess, a, p);
+    }
     return finish(run_srs(a), a, p);
 }
 
@@ -538,6 +555,18 @@ lr_status batch_enqueue(const lr_request* reqs, uint32_t count, void* ws, size_t
     a.validate = opts && (opts->flags & LR_VALIDATE);
     a.ev = prof_events(opts && (opts->flags & LR_PROFILE));
     prof_capped(a, p);
+    if (LR_DEBUG_WRITES) {
+        hipError_t e = run_debug_begin(a, p);
+        if (e == hipSuccess) e = run_srs(a);
+        if (e == hipSuccess) e = run_debug_check(a, p);
+        if (e != hipSuccess) return LR_ERR_HIP;
+        Ctrl c{};
+        if (hipMemcpyAsync(&c, a.ws + p.off_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, a.stream) != hipSuccess ||
+            hipStreamSynchronize(a.stream) != hipSuccess)
+            return LR_ERR_HIP;
+        if (c.err & ERR_DEBUG_WRITES) return LR_ERR_BAD_LIST;
+        return finish(hipSuccess, a, p);
+    }
     return finish(run_srs(a), a, p);
 }
 

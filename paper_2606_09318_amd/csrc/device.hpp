@@ -66,6 +66,7 @@ enum : uint32_t { MODE_PLAIN = 0, MODE_LOCAL = 1, MODE_FALLBACK = 2, MODE_SPAWN 
 // a path stopped by a cap leaves inconsistent state behind.
 constexpr uint32_t ERR_INPUT = 1u | 2u;
 constexpr uint32_t ERR_FALLBACK_CYCLE = 256u;
+constexpr uint32_t ERR_DEBUG_WRITES = 512u;  // debug builds: a slot or mark with another write count
 
 // Walk step cap: a walk at level spacing k stops after WALK_CAP_MULT * k
 // steps. On a list whose order is independent of the sampling, walk lengths

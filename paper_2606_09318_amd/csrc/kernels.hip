@@ -66,6 +66,33 @@ constexpr uint32_t CHASE_GRAB = 64;  // walks a wavefront takes from the pool at
 static_assert(CHASE_TPB % 64 == 0 && CHASE_TPB >= 64 && CHASE_TPB <= 1024, "chase workgroup width");
 static_assert(LR_CHASE_POOL >= 0 && LR_CHASE_POOL < 16, "pool share of the walks, in sixteenths");
 
+// ----------------------------------------------------------- debug writes --
+// Debug builds (LR_DEBUG_WRITES): the stores that rely on having one writer
+// per address (a slot per visited element, a predecessor mark per element)
+// also count themselves, per level, into counters the call sets up; a check
+// after the call wants every slot of a chased level written exactly once and
+// every mark at most once. Null pointers (release builds, and calls outside
+// the plain path) count nothing.
+struct DbgWrites {
+    uint32_t* slot[MAXL];
+    uint32_t* mark[MAXL];
+};
+struct DbgSizes {
+    uint32_t m[MAXL];
+};
+#if LR_DEBUG_WRITES
+__device__ DbgWrites g_dbg;
+#define LR_DBG_COUNT(kind, lvl, i)                  \
+    do {                                            \
+        uint32_t* c_ = g_dbg.kind[(lvl)];           \
+        if (c_) atomicAdd(&c_[(i)], 1u);            \
+    } while (0)
+#else
+#define LR_DBG_COUNT(kind, lvl, i) \
+    do {                           \
+    } while (0)
+#endif
+
 // ------------------------------------------------------------------ fill --
 __global__ __launch_bounds__(TPB) void k_fill(uint32_t* __restrict__ p, uint64_t words, uint32_t val,
                                               const Ctrl* skip_if_single, Gate gate) {
@@ -98,16 +125,19 @@ __global__ __launch_bounds__(TPB) void k_detect(const uint32_t* __restrict__ suc
         for (uint32_t i = g; i < m4; i += stride) {
             const uint4 s = reinterpret_cast<const uint4*>(succ)[i];
             const uint32_t x = 4 * i;
-            if (s.x != x && s.x < m) hp[s.x] = 1;
-            if (s.y != x + 1 && s.y < m) hp[s.y] = 1;
-            if (s.z != x + 2 && s.z < m) hp[s.z] = 1;
-            if (s.w != x + 3 && s.w < m) hp[s.w] = 1;
+            if (s.x != x && s.x < m) { hp[s.x] = 1; LR_DBG_COUNT(mark, 0, s.x); }
+            if (s.y != x + 1 && s.y < m) { hp[s.y] = 1; LR_DBG_COUNT(mark, 0, s.y); }
+            if (s.z != x + 2 && s.z < m) { hp[s.z] = 1; LR_DBG_COUNT(mark, 0, s.z); }
+            if (s.w != x + 3 && s.w < m) { hp[s.w] = 1; LR_DBG_COUNT(mark, 0, s.w); }
         }
         done = m4 * 4;
     }
     for (uint32_t i = done + g; i < m; i += stride) {
         const uint32_t s = succ[i];
-        if (s != i && s < m) hp[s] = 1;
+        if (s != i && s < m) {
+            hp[s] = 1;
+            LR_DBG_COUNT(mark, 0, s);
+        }
     }
 }
 
@@ -687,6 +717,7 @@ __global__ __launch_bounds__(CHASE_TPB) __attribute__((amdgpu_num_sgpr(80))) voi
                 }
             } else {
                 slot[x[k]] = L::slot(w[k], off[k]);
+                LR_DBG_COUNT(slot, lvl, x[k]);
             }
             if (nxt[k] & TERM) {                    // x is a terminal: the walk ends on it
                 eb[w[k]] = L::rec(nxt[k], L::add(off[k], v[k]));
@@ -705,7 +736,10 @@ __global__ __launch_bounds__(CHASE_TPB) __attribute__((amdgpu_num_sgpr(80))) voi
                 } else if (smp.sampled(nxt[k])) {   // reached the next ruler
                     const uint32_t c = nxt[k] >> smp.log2k;
                     eb[w[k]] = L::rec(c, off[k]);
-                    if (hp_next && w[k] < S) hp_next[c] = 1;
+                    if (hp_next && w[k] < S) {
+                        hp_next[c] = 1;
+                        LR_DBG_COUNT(mark, lvl + 1, c);  // hp_next exists below the last level only
+                    }
                     w[k] = NONE;
                 } else {
                     x[k] = nxt[k];
@@ -3275,6 +3309,84 @@ hipError_t run_verify(const uint32_t* succ, const void* weight, int wt, const ui
     if (wt == 1) hipLaunchKernelGGL(k_verify<1>, g, b, 0, st, succ, weight, rank, root, sum, n, err);
     else if (wt == 2) hipLaunchKernelGGL(k_verify<2>, g, b, 0, st, succ, weight, rank, root, sum, n, err);
     else hipLaunchKernelGGL(k_verify<0>, g, b, 0, st, succ, weight, rank, root, sum, n, err);
+    return hipGetLastError();
+}
+
+
+// ----------------------------------------------------------- debug writes --
+// Sets the counters of a call (null: count nothing) and clears them and the
+// control block's debug bit (without validation nothing else clears it).
+__global__ __launch_bounds__(TPB) void k_dbg_begin(DbgWrites d, uint32_t* __restrict__ base, uint64_t words,
+                                                   Ctrl* ctrl) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+#if LR_DEBUG_WRITES
+        g_dbg = d;
+#endif
+        ctrl->err &= ~ERR_DEBUG_WRITES;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) base[i] = 0;
+}
+
+// Every slot of the levels from `slot_from` on written once, every mark at
+// most once (only when the plain path ran to its end); then counting stops.
+__global__ __launch_bounds__(TPB) void k_dbg_check(DbgWrites d, DbgSizes sz, uint32_t levels, uint32_t slot_from,
+                                                   Ctrl* ctrl) {
+#if LR_DEBUG_WRITES
+    if (blockIdx.x == 0 && threadIdx.x == 0) g_dbg = DbgWrites{};
+#endif
+    if (ctrl->mode != MODE_PLAIN) return;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint32_t l = 0; l < levels; ++l) {
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sz.m[l]; i += stride) {
+            if (l >= slot_from && d.slot[l][i] != 1u) bad = true;
+            if (d.mark[l][i] > 1u) bad = true;
+        }
+    }
+    if (bad) atomicOr(&ctrl->err, ERR_DEBUG_WRITES);
+}
+
+hipError_t run_debug_begin(const RunArgs& a, const Plan& p) {
+    if (!LR_DEBUG_WRITES) return hipSuccess;
+    DbgWrites d{};
+    uint64_t words = 0;
+    const bool plain = !p.local && !p.spawn && !a.lplan;
+    if (plain) {
+        size_t off = p.off_dbg;
+        for (uint32_t l = 0; l < p.levels; ++l) {
+            d.slot[l] = reinterpret_cast<uint32_t*>(a.ws + off);
+            d.mark[l] = d.slot[l] + p.m[l];
+            off += (p.m[l] * 8 + ALIGN - 1) / ALIGN * ALIGN;
+        }
+        words = (off - p.off_dbg) / 4;
+    }
+    uint32_t* base = reinterpret_cast<uint32_t*>(a.ws + p.off_dbg);
+    hipLaunchKernelGGL(k_dbg_begin, dim3(std::max<uint32_t>(1, grid_for(words, TPB * 4))), dim3(TPB), 0, a.stream, d,
+                       base, words, reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl));
+    return hipGetLastError();
+}
+
+hipError_t run_debug_check(const RunArgs& a, const Plan& p) {
+    if (!LR_DEBUG_WRITES) return hipSuccess;
+    const bool plain = !p.local && !p.spawn && !a.lplan;
+    DbgWrites d{};
+    DbgSizes sz{};
+    uint32_t levels = 0;
+    if (plain) {
+        size_t off = p.off_dbg;
+        levels = p.levels;
+        for (uint32_t l = 0; l < p.levels; ++l) {
+            d.slot[l] = reinterpret_cast<uint32_t*>(a.ws + off);
+            d.mark[l] = d.slot[l] + p.m[l];
+            sz.m[l] = (uint32_t)p.m[l];
+            off += (p.m[l] * 8 + ALIGN - 1) / ALIGN * ALIGN;
+        }
+    }
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(a.ws + p.off_ctrl);
+    // level 0 writes slots only when it is not chased through the visit log
+    hipLaunchKernelGGL(k_dbg_check, dim3(std::max<uint32_t>(1, grid_for(p.m[0], TPB * 4))), dim3(TPB), 0, a.stream, d,
+                       sz, levels, p.log0 ? 1u : 0u, ctrl);
     return hipGetLastError();
 }
 

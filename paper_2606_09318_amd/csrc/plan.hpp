@@ -84,6 +84,14 @@ static_assert((LR_SPAWN_K2 & (LR_SPAWN_K2 - 1)) == 0, "k2 is a power of two");
 // grouping tiles: lanes x LR_PLACE_PER records (half as many weighted); the
 // passes whose records carry roots or weights use wider workgroups (measured
 // faster there, slower for plain ranks)
+// Debug builds (LR_DEBUG_WRITES=1, a separate library): the plain path counts
+// the writes to every slot and predecessor mark of every level that writes
+// them at the element's address, and a call returns LR_ERR_BAD_LIST unless
+// every slot was written exactly once and every mark at most once.
+#ifndef LR_DEBUG_WRITES
+#define LR_DEBUG_WRITES 0
+#endif
+
 #ifndef LR_PLACE_TPB
 #define LR_PLACE_TPB 512
 #endif
@@ -192,6 +200,7 @@ struct Plan {
     size_t off_sp_slot = 0;  // per element: walk id (flagged for spawned rulers) and offset
     size_t off_sp_hp = 0;    // per element: has-a-predecessor byte
     size_t off_sp_tile = 0;  // head counts per tile, scanned in place
+    size_t off_dbg = 0;      // debug builds: per level, slot then mark write counters (4 B each)
     size_t total = 0;
 };
 

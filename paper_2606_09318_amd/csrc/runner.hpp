@@ -44,6 +44,12 @@ struct RunArgs {
 // Sparse ruling-set ranking over the whole plan. Enqueues only.
 hipError_t run_srs(const RunArgs& a);
 
+// Debug builds (LR_DEBUG_WRITES): set up and clear the write counters of a
+// call before it, check them after it (Ctrl.err |= ERR_DEBUG_WRITES); no-ops
+// in release builds.
+hipError_t run_debug_begin(const RunArgs& a, const Plan& p);
+hipError_t run_debug_check(const RunArgs& a, const Plan& p);
+
 // Weighted ranking whose results land as one 16-byte (rank, root, sum)
 // record per element at `rec` (the root field is not filled: NONE). Same
 // arguments, workspace and checks as lr_prefix_sum otherwise, and one more

@@ -27,6 +27,20 @@ def test_library_exports_every_declared_function():
         assert hasattr(lib, name), name
 
 
+def test_debug_library_exports_the_same_functions_and_larger_workspaces():
+    """liblr_debug.so (write counters) has the release library's ABI; its
+    workspaces hold the counters as well."""
+    from paper_2606_09318_amd import build as lr_build
+    lr.load()
+    dbg = ctypes.CDLL(lr_build.DEBUG_LIB)
+    for name in declared_functions():
+        assert hasattr(dbg, name), name
+    dbg.lr_workspace_bytes.restype = ctypes.c_size_t
+    dbg.lr_workspace_bytes.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+    n = 1 << 20
+    assert dbg.lr_workspace_bytes(n, 0, None) >= lr.lr_workspace_bytes(n, lr.LR_W_NONE) + 8 * (n + n // 16)
+
+
 def test_status_strings():
     for s in range(7):
         assert lr.status_string(s).startswith("LR_")
