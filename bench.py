@@ -330,6 +330,15 @@ def main():
 
     extra["calibration"] = lr.calibrate(dev)
     torch.cuda.empty_cache()
+    # the chase against the part's measured random-access ceiling: its n
+    # dependent 4 B gathers per launch against independent 4 B gathers over a
+    # 1 GiB array (lr_calibrate), the rate a random line fill allows
+    g_ceiling = extra["calibration"].get("gather4_1gib_g_s")
+    if g_ceiling:
+        g_rate = n / (chase_ms * 1e-3) / 1e9
+        roofline["gather_ceiling"] = {"achieved_g_per_s": round(g_rate, 2), "ceiling_g_per_s": g_ceiling,
+                                      "frac": round(g_rate / g_ceiling, 4),
+                                      "ceiling": "independent random 4 B gathers over 1 GiB (lr_calibrate)"}
 
     if not args.no_weighted:
         extra.update(weighted_bench())

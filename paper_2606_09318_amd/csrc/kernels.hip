@@ -326,7 +326,8 @@ __global__ __launch_bounds__(TPB) void k_verify(const uint32_t* __restrict__ suc
             int64_t w = 1;
             if constexpr (WT == 1) w = static_cast<const int32_t*>(weight)[i];
             if constexpr (WT == 2) w = static_cast<const int64_t*>(weight)[i];
-            if (sum[i] != sum[s] + w) bad |= 4u;
+            // two's complement wrap, as the prefix sums themselves
+            if ((uint64_t)sum[i] != (uint64_t)sum[s] + (uint64_t)w) bad |= 4u;
         }
     }
     if (bad) atomicOr(err, bad);
