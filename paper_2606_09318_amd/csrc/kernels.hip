@@ -765,49 +765,101 @@ __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m,
     using L = Lay<W>;
     using Val = typename L::Val;
     extern __shared__ __align__(16) unsigned char lds[];
-    // LDS is carved for the planned size m; a device-side size is at most that
-    int64_t* ds = reinterpret_cast<int64_t*>(lds);
-    uint32_t* dc = reinterpret_cast<uint32_t*>(lds + (W ? 8 * (size_t)m : 0));
-    uint16_t* f = reinterpret_cast<uint16_t*>(lds + (W ? 8 * (size_t)m : 0) + 4 * (size_t)m);
-    if (dm) m = src.m = min(dm[0], m);
+    if (dm) m = src.m = min(dm[0], m);  // LDS is carved for the planned size; a device-side size is at most that
     const uint32_t t = threadIdx.x;
-    for (uint32_t i = t; i < m; i += BASE_TPB) {
-        uint32_t nxt;
-        Val v;
-        src.load(i, nxt, v);
-        const bool term = (nxt & TERM) || nxt >= m;
-        f[i] = (uint16_t)(term ? i : nxt);
-        dc[i] = term ? 0u : v.c;
-        if constexpr (W) ds[i] = term ? 0 : v.s;
-    }
-    __syncthreads();
-    for (int round = 0; round < 40; ++round) {
-        uint16_t ff[BASE_PER];
-        uint32_t fc[BASE_PER];
-        int64_t fs[BASE_PER];
-        int changed = 0;
+    // each lane keeps its own elements' (f, d) in registers and writes them
+    // to LDS after every round, where the other lanes gather them
+    uint32_t f_[BASE_PER], dc_[BASE_PER];
+    int64_t ds_[BASE_PER];
+    if constexpr (!W) {
+        // unweighted: (d << 32) | f in one 8 B word, one gather per element and round
+        uint64_t* fd = reinterpret_cast<uint64_t*>(lds);
 #pragma unroll
         for (int j = 0; j < BASE_PER; ++j) {
             const uint32_t i = t + j * BASE_TPB;
             if (i < m) {
-                const uint32_t fi = f[i];
-                ff[j] = f[fi];
-                fc[j] = dc[fi];
-                if constexpr (W) fs[j] = ds[fi];
-                changed |= (ff[j] != fi);
+                uint32_t nxt;
+                Val v;
+                src.load(i, nxt, v);
+                const bool term = (nxt & TERM) || nxt >= m;
+                f_[j] = term ? i : nxt;
+                dc_[j] = term ? 0u : v.c;
+                fd[i] = ((uint64_t)dc_[j] << 32) | f_[j];
             }
         }
         __syncthreads();
+        for (int round = 0; round < 40; ++round) {
+            int changed = 0;
+#pragma unroll
+            for (int j = 0; j < BASE_PER; ++j) {
+                const uint32_t i = t + j * BASE_TPB;
+                if (i < m) {
+                    const uint64_t w = fd[f_[j]];
+                    const uint32_t nf = (uint32_t)w & 0xffffu;
+                    changed |= (nf != f_[j]);
+                    f_[j] = nf;
+                    dc_[j] += (uint32_t)(w >> 32);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < BASE_PER; ++j) {
+                const uint32_t i = t + j * BASE_TPB;
+                if (i < m) fd[i] = ((uint64_t)dc_[j] << 32) | f_[j];
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
+    } else {
+        int64_t* ds = reinterpret_cast<int64_t*>(lds);
+        uint32_t* dc = reinterpret_cast<uint32_t*>(lds + 8 * (size_t)m);
+        uint16_t* f = reinterpret_cast<uint16_t*>(lds + 12 * (size_t)m);
+        for (uint32_t i = t; i < m; i += BASE_TPB) {
+            uint32_t nxt;
+            Val v;
+            src.load(i, nxt, v);
+            const bool term = (nxt & TERM) || nxt >= m;
+            f[i] = (uint16_t)(term ? i : nxt);
+            dc[i] = term ? 0u : v.c;
+            ds[i] = term ? 0 : v.s;
+        }
+        __syncthreads();
+        for (int round = 0; round < 40; ++round) {
+            uint16_t ff[BASE_PER];
+            uint32_t fc[BASE_PER];
+            int64_t fs[BASE_PER];
+            int changed = 0;
+#pragma unroll
+            for (int j = 0; j < BASE_PER; ++j) {
+                const uint32_t i = t + j * BASE_TPB;
+                if (i < m) {
+                    const uint32_t fi = f[i];
+                    ff[j] = f[fi];
+                    fc[j] = dc[fi];
+                    fs[j] = ds[fi];
+                    changed |= (ff[j] != fi);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < BASE_PER; ++j) {
+                const uint32_t i = t + j * BASE_TPB;
+                if (i < m) {
+                    f[i] = ff[j];
+                    dc[i] += fc[j];
+                    ds[i] += fs[j];
+                }
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
 #pragma unroll
         for (int j = 0; j < BASE_PER; ++j) {
             const uint32_t i = t + j * BASE_TPB;
             if (i < m) {
-                f[i] = ff[j];
-                dc[i] += fc[j];
-                if constexpr (W) ds[i] += fs[j];
+                f_[j] = f[i];
+                dc_[j] = dc[i];
+                ds_[j] = ds[i];
             }
         }
-        if (!__syncthreads_or(changed)) break;
     }
     Val rv[BASE_PER];
     uint32_t rr[BASE_PER];
@@ -815,13 +867,13 @@ __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m,
     for (int j = 0; j < BASE_PER; ++j) {
         const uint32_t i = t + j * BASE_TPB;
         if (i < m) {
-            const uint32_t ti = f[i];
+            const uint32_t ti = f_[j];
             uint32_t nxt;
             Val v;
             src.load(ti, nxt, v);
             Val d;
-            d.c = dc[i];
-            if constexpr (W) d.s = ds[i];
+            d.c = dc_[j];
+            if constexpr (W) d.s = ds_[j];
             if (nxt & TERM) {
                 rv[j] = L::add(d, v);
                 rr[j] = nxt & IDX;

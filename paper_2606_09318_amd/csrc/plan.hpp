@@ -226,7 +226,9 @@ bool tune_lookup(uint64_t n, bool weighted, lr_opts* o);
 
 // Base-case shared memory bytes for m elements.
 inline size_t base_lds_bytes(uint64_t m, bool weighted) {
-    return (size_t)m * (weighted ? 14 : 6) + 64;
+    // unweighted: one 8 B (count, successor) word per element; weighted: 8 B
+    // sum, 4 B count and 2 B successor arrays
+    return (size_t)m * (weighted ? 14 : 8) + 64;
 }
 
 }  // namespace lr
