@@ -40,7 +40,8 @@ struct Ctrl {
     uint32_t multi;                         // plain path with more than one list: predecessor marks needed
     uint32_t spn;                           // ruler spawning: number of spawned rulers
     uint32_t conts;                         // packed visit log: continuation ids handed out
-    uint32_t pad[29];
+    uint32_t hc_done;                       // workgroups of a head-count kernel that have finished
+    uint32_t pad[28];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 

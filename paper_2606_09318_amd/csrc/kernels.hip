@@ -272,6 +272,7 @@ __global__ __launch_bounds__(TPB) void k_headsum_final(const uint32_t* __restric
         for (int i = 1; i < TPB / 64; ++i) { hs += shs[i]; nt += snt[i]; }
         ctrl->nterm = nt;
         ctrl->hsum = hs;
+        ctrl->hc_done = 0;  // the head-count kernels' workgroup counter starts the call at zero
         if (mode != NONE) ctrl->mode = mode;
         const bool single = nt == 1 && hs < smp.m;
         ctrl->single = single ? 1u : 0u;
@@ -399,7 +400,7 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* sh, uint3
 // entries, read and written as 16-byte vectors, so both passes issue all of a
 // lane's loads at once (a must be 16-byte aligned).
 __device__ uint32_t wg_exscan_inplace(uint32_t* __restrict__ a, uint32_t n, uint32_t* sh) {
-    const uint32_t per = (((n + 1023u) >> 10) + 3u) & ~3u;
+    const uint32_t per = (((n + blockDim.x - 1u) / blockDim.x) + 3u) & ~3u;
     const uint32_t lo = min(threadIdx.x * per, n);
     const uint32_t hi = min(lo + per, n);
     const uint32_t nv = (hi - lo) >> 2;  // whole vectors; the rest one by one
@@ -430,19 +431,34 @@ __device__ uint32_t wg_exscan_inplace(uint32_t* __restrict__ a, uint32_t n, uint
     return total;
 }
 
+constexpr int SPL = MAXL - 1;  // Ctrl level entry of the spawning path's input level
+
+// Counts, per tile of TILE elements, the initial elements that are not
+// sampled rulers. With scan_last (levels of at most HEADS_SCAN_LAST_TILES
+// tiles) the last workgroup to finish then scans the counts in place
+// (exclusive) and publishes the walk count of the level, which saves a launch;
+// larger levels leave that to k_heads_scan's wider workgroup. Ctrl.hc_done
+// counts finished workgroups: each writes its tiles' counts, fences, and
+// takes a ticket; the one with the last ticket fences again, sees every
+// count, and resets the counter for the next level. The first kernels of
+// every path (head sum, batch heads, contraction scan) clear it at the start
+// of a call.
+constexpr uint32_t HEADS_SCAN_LAST_TILES = 1024;
 __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__ hp, Sampler smp,
                                                      uint32_t* __restrict__ tilecnt, uint32_t ntiles, uint32_t* zero_p,
-                                                     uint32_t zero_words, const Ctrl* skip_if_single,
-                                                     const uint32_t* dm, Gate gate) {
+                                                     uint32_t zero_words, uint32_t skip_single, uint32_t scan_last,
+                                                     Ctrl* ctrl, int lvl, const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[TPB / 64];
+    __shared__ uint32_t last;
     if (dm) smp.m = dm[0];
     // clear the next level's predecessor marks (free memory at this point)
     if (zero_p) {
         const uint32_t stride = gridDim.x * blockDim.x;
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < zero_words; i += stride) zero_p[i] = 0;
     }
-    if (skip_if_single && skip_if_single->single) return;
+    // one list: its head is known (head sum) and no workgroup counts or scans
+    if (skip_single && ctrl->single) return;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         uint32_t bits;
         const uint32_t c = tile_heads(hp, smp, tile * TILE + threadIdx.x * 16, bits);
@@ -450,17 +466,34 @@ __global__ __launch_bounds__(TPB) void k_heads_count(const uint8_t* __restrict__
         if (threadIdx.x == 0) tilecnt[tile] = t;
         __syncthreads();  // sh is reused by the next tile
     }
+    if (!scan_last) return;
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's counts before its ticket
+        last = atomicAdd(&ctrl->hc_done, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // every other workgroup's counts after the last ticket
+    const uint32_t total = wg_exscan_inplace(tilecnt, ntiles, sh);
+    if (threadIdx.x == 0) {
+        ctrl->hc_done = 0;
+        ctrl->lv[lvl].H = total;
+        ctrl->lv[lvl].q = 0;
+        if (lvl == 0) {
+            ctrl->chunks = 0;
+            ctrl->conts = 0;
+        }
+    }
 }
 
-constexpr int SPL = MAXL - 1;  // Ctrl level entry of the spawning path's input level
-
-// One workgroup: exclusive scan of the tile counts in place; publishes the
-// walk count and resets the chase queue of this level.
+// One workgroup: exclusive scan of the tile counts in place (levels of more
+// than HEADS_SCAN_LAST_TILES tiles); publishes the walk count and resets the
+// chase queue of this level.
 __global__ __launch_bounds__(1024) void k_heads_scan(uint32_t* __restrict__ tilecnt, uint32_t ntiles,
-                                                     Ctrl* ctrl, int lvl, Gate gate) {
+                                                     Ctrl* ctrl, int lvl, uint32_t skip_single, Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
-    if ((lvl == 0 || lvl == SPL) && ctrl->single) return;
+    if (skip_single && ctrl->single) return;
     const uint32_t total = wg_exscan_inplace(tilecnt, ntiles, sh);
     if (threadIdx.x == 0) {
         ctrl->lv[lvl].H = total;
@@ -1762,6 +1795,7 @@ __global__ __launch_bounds__(1024) void k_batch_heads(const uint2* __restrict__ 
                                                       uint32_t rec_bytes, const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
     __shared__ uint32_t sh[1024 / 64];
+    if (threadIdx.x == 0) ctrl->hc_done = 0;  // the head-count kernels' workgroup counter
     if (dm) { smp.m = dm[0]; S = dm[1]; }
     const uint32_t count = hdr->count;
     int ok = 1;
@@ -2024,6 +2058,7 @@ __global__ __launch_bounds__(1024) void k_lc_scan(uint32_t* __restrict__ cnt, ui
     __shared__ uint32_t sh[1024 / 64];
     const uint32_t total = wg_exscan_inplace(cnt, ntiles, sh);
     if (threadIdx.x == 0) {
+        ctrl->hc_done = 0;  // the head-count kernels' workgroup counter
         if (forced) ctrl->mode = MODE_LOCAL;
         if (total > cap) {  // the guess was wrong: more than the contracted levels hold
             ctrl->mode = MODE_PLAIN;  // every later kernel of this path returns; the plain path runs
@@ -2861,15 +2896,18 @@ static hipError_t run_srs_t(const RunArgs& a, Out0 out0) {
         const bool more = l + 1 < p.levels;
         uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
         const uint32_t zw = more ? (S + 3) / 4 : 0;
-        const Ctrl* skip = (l == 0) ? ctrl : nullptr;
         const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
-        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, skip,
-                           dm_at(l), g);
+        const uint32_t last = p.ntiles[l] <= HEADS_SCAN_LAST_TILES;
+        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw,
+                           (uint32_t)(l == 0), last, ctrl, (int)l, dm_at(l), g);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
-        LR_TRY(hipGetLastError());
+        if (!last) {
+            hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l,
+                               (uint32_t)(l == 0), g);
+            LR_TRY(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
-                           S, (uint32_t)p.rec_bytes, skip, dm_at(l), g);
+                           S, (uint32_t)p.rec_bytes, (l == 0) ? ctrl : nullptr, dm_at(l), g);
         LR_TRY(hipGetLastError());
         if (a.validate && !(l == 0 && p.log0))
             LR_TRY(fill(ws + p.off_slot[l], (uint64_t)m * p.rec_bytes, 0xffffffffu, st, nullptr, g));
@@ -2957,11 +2995,14 @@ static hipError_t run_clevels(const RunArgs& a, const Plan& p, typename Lay<W>::
         uint32_t* zp = more ? reinterpret_cast<uint32_t*>(ws + p.off_slot[l + 1]) : nullptr;
         const uint32_t zw = more ? (S + 3) / 4 : 0;
         const uint32_t gt = std::min<uint32_t>(p.ntiles[l], (uint32_t)device_cus() * 8);
-        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, nullptr, dm,
-                           g);
+        const uint32_t last = p.ntiles[l] <= HEADS_SCAN_LAST_TILES;
+        hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], zp, zw, 0u, last,
+                           ctrl, (int)l, dm, g);
         LR_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, g);
-        LR_TRY(hipGetLastError());
+        if (!last) {
+            hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.ntiles[l], ctrl, (int)l, 0u, g);
+            LR_TRY(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp, smp, tile, p.ntiles[l], ws + p.off_eb[l],
                            S, (uint32_t)p.rec_bytes, nullptr, dm, g);
         LR_TRY(hipGetLastError());
@@ -3116,11 +3157,14 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
     }
     rec_ev(a, EV_DETECT);
     const uint32_t gt = std::min<uint32_t>(p.sp_ntiles, (uint32_t)device_cus() * 8);
+    const uint32_t last = p.sp_ntiles <= HEADS_SCAN_LAST_TILES;
     hipLaunchKernelGGL(k_heads_count, dim3(gt), dim3(TPB), 0, st, hp_in, smp, tile, p.sp_ntiles,
-                       reinterpret_cast<uint32_t*>(hp_c), (n + 3) / 4, ctrl, nullptr, g);
+                       reinterpret_cast<uint32_t*>(hp_c), (n + 3) / 4, 1u, last, ctrl, SPL, nullptr, g);
     LR_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.sp_ntiles, ctrl, SPL, g);
-    LR_TRY(hipGetLastError());
+    if (!last) {
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, st, tile, p.sp_ntiles, ctrl, SPL, 1u, g);
+        LR_TRY(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_heads_write, dim3(gt), dim3(TPB), 0, st, hp_in, smp, tile, p.sp_ntiles,
                        reinterpret_cast<char*>(lrec), S0, (uint32_t)p.rec_bytes, ctrl, nullptr, g);
     LR_TRY(hipGetLastError());
