@@ -39,6 +39,7 @@ def parse():
                     help="with --list batch: replay the batch as a captured graph (lr_batch_graph)")
     ap.add_argument("--autotune", action="store_true",
                     help="the plan autotuner on the random list of --n elements: default plan, search, tuned plan")
+    ap.add_argument("--no-largest", action="store_true", help="skip the 2^31 - 1 element list")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
@@ -327,6 +328,10 @@ def main():
     extra["block_local_4096"] = extra["locality"]["block_local_4096"]
     del rank, root, L
     torch.cuda.empty_cache()
+
+    if not args.no_largest:
+        extra["largest_input"] = largest_bench(stream)
+        torch.cuda.empty_cache()
 
     extra["calibration"] = lr.calibrate(dev)
     torch.cuda.empty_cache()
@@ -681,6 +686,42 @@ def autotune_bench(args, stream):
                                    "tuned_base_max": int(best.base_max), "tuned_lane_walks": int(best.lane_walks),
                                    "tuned_refill": int(best.refill), "candidates": len(trials),
                                    "trial_ms": [round(t, 4) for t in trials], "search_s": round(tune_s, 2)}}))
+
+
+def largest_bench(stream, steps: int = 5) -> dict:
+    """The largest input the boundary takes, n = 2^31 - 1: a random list in
+    the order of a keyed Feistel permutation built on the device (the host
+    generator takes minutes at this size), rank output, default options;
+    the timed result is checked against the closed form."""
+    import torch
+
+    import paper_2606_09318_amd as lr
+    import workloads
+
+    n = (1 << 31) - 1
+    print(json.dumps({"bench": "largest input", "n": n}), file=sys.stderr, flush=True)
+    succ, order = workloads.random_list_device(n)
+    torch.cuda.empty_cache()
+    rank = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = lr.workspace(lr.lr_workspace_bytes(n))
+    if lr.lr_rank(succ, rank, None, ws, None, stream):
+        raise SystemExit("bench: lr_rank failed on the largest input")
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        lr.lr_rank(succ, rank, None, ws, None, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    del ws
+    expect = torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda")
+    ok = bool(torch.equal(rank.index_select(0, order), expect))
+    del succ, order, rank, expect
+    if not ok:
+        raise SystemExit("bench: the largest input's ranks do not match the closed form")
+    return {"n": n, "ms": round(ms, 3), "g_elements_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+            "list": "keyed Feistel order built on the device", "steps": steps}
 
 
 def weighted_bench() -> dict:

@@ -36,16 +36,6 @@ def test_wide_visit_log_above_2p28():
     assert closed_form_ok(r, t, L.order)
 
 
-def feistel32_gpu(x, keys):
-    """A keyed balanced Feistel network on 32-bit values (16-bit halves), in
-    int64 tensor arithmetic on the device: a bijection of [0, 2^32)."""
-    lo, hi = x & 0xFFFF, (x >> 16) & 0xFFFF
-    for k in keys:
-        f = ((lo * 0x9E37 + k) ^ (lo >> 5) ^ (lo * 0x85EB >> 7)) & 0xFFFF
-        lo, hi = hi ^ f, lo
-    return (hi << 16) | lo
-
-
 @pytest.mark.timeout(300)
 def test_largest_input_2p31_minus_1():
     """The largest input the boundary takes (n = 2^31 - 1; indices and ranks
@@ -54,22 +44,9 @@ def test_largest_input_2p31_minus_1():
     generator takes minutes at this size). Every rank and root equals the
     closed form of that order, and the result passes lr_verify."""
     n = (1 << 31) - 1
-    keys = [0x3A51, 0x7C2D, 0x1E93, 0x5B07]
     torch.cuda.empty_cache()
-    print(f"case: largest input n={n}: order", flush=True)
-    order = feistel32_gpu(torch.arange(n, dtype=torch.int64, device="cuda"), keys)
-    for _ in range(128):  # cycle walking: a bijection of [0, 2^32) restricted to [0, n)
-        out = order >= n
-        if not bool(out.any()):
-            break
-        order[out] = feistel32_gpu(order[out], keys)
-    assert not bool((order >= n).any())
-    print("case: largest input: successors", flush=True)
-    succ = torch.empty(n, dtype=torch.int32, device="cuda")
-    succ[order[:-1]] = order[1:].to(torch.int32)
-    succ[order[-1:]] = order[-1:].to(torch.int32)
-    order32 = order.to(torch.int32)
-    del order, out
+    print(f"case: largest input n={n}: order and successors", flush=True)
+    succ, order32 = workloads.random_list_device(n)
     torch.cuda.empty_cache()
     print("case: largest input: ranking", flush=True)
     r, t = lr.rank(succ)

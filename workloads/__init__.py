@@ -121,6 +121,42 @@ def random_list(n: int, seed: int = 1, stream: int = 0) -> ListInput:
     return ListInput(link_order(order), order)
 
 
+def feistel32_torch(x, keys):
+    """A keyed balanced Feistel network on 32-bit values (16-bit halves) in
+    int64 tensor arithmetic (any torch device): a bijection of [0, 2^32)."""
+    lo, hi = x & 0xFFFF, (x >> 16) & 0xFFFF
+    for k in keys:
+        f = ((lo * 0x9E37 + k) ^ (lo >> 5) ^ (lo * 0x85EB >> 7)) & 0xFFFF
+        lo, hi = hi ^ f, lo
+    return (hi << 16) | lo
+
+
+DEVICE_ORDER_KEYS = (0x3A51, 0x7C2D, 0x1E93, 0x5B07)
+
+
+def random_list_device(n: int, device="cuda", keys=DEVICE_ORDER_KEYS):
+    """One list over [0, n) (n <= 2^31 - 1) in the order of a keyed Feistel
+    permutation, restricted to [0, n) by cycle walking, built on the device
+    for sizes where the host generator takes minutes. Returns (succ int32,
+    order int32) tensors; rank[order[j]] = n-1-j."""
+    import torch
+    assert 0 < n < (1 << 31)
+    order = feistel32_torch(torch.arange(n, dtype=torch.int64, device=device), keys)
+    for _ in range(256):  # the domain is at most 2^32 / n times larger: each walk step keeps >= n / 2^32
+        out = order >= n
+        if not bool(out.any()):
+            break
+        order[out] = feistel32_torch(order[out], keys)
+    if bool((order >= n).any()):
+        raise RuntimeError("cycle walking did not finish")
+    succ = torch.empty(n, dtype=torch.int32, device=device)
+    succ[order[:-1]] = order[1:].to(torch.int32)
+    succ[order[-1:]] = order[-1:].to(torch.int32)
+    order32 = order.to(torch.int32)
+    del order, out
+    return succ, order32
+
+
 def block_list(n: int, block: int = 4096, seed: int = 2, stream: int = 1) -> ListInput:
     """One list with block locality (blocks of `block` ids, chained in random order)."""
     order = block_order(n, block, seed, stream)
