@@ -2527,31 +2527,28 @@ __global__ __launch_bounds__(TPB) void k_sp_expand(const typename Lay<W>::Slot* 
 
 // ============================================================== host side ==
 
-static int g_cus = 0;
-static size_t g_lds = 0;
-
+// Device properties, looked up once (thread-safe initialisation of local
+// statics) on the device current at the first call.
 int device_cus() {
-    if (!g_cus) {
+    static const int cus = [] {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            g_cus = v;
-        else
-            g_cus = 256;
-    }
-    return g_cus;
+            return v;
+        return 256;
+    }();
+    return cus;
 }
 
 size_t device_max_lds() {
-    if (!g_lds) {
+    static const size_t lds = [] {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-            g_lds = (size_t)v;
-        else
-            g_lds = 65536;
-    }
-    return g_lds;
+            return (size_t)v;
+        return (size_t)65536;
+    }();
+    return lds;
 }
 
 static inline uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap_per_cu = 8) {
@@ -2616,11 +2613,10 @@ static hipError_t launch_chase(const Plan& p, int l, Src src, Sampler smp, Ctrl*
                                const uint32_t* dm = nullptr, Gate gate = Gate{}) {
     using L = Lay<W>;
     auto kern = k_chase<W, Src, LOG, NW>;
-    static uint32_t grid = 0;  // one per template instance
-    if (!grid) {
-        grid = persistent_grid(kern, CHASE_TPB);
-        if (LOG != 0) grid = std::min<uint32_t>(grid, LOG_MAX_WAVES / (CHASE_TPB / 64));  // bounds the log slack
-    }
+    static const uint32_t grid = [kern] {  // one per template instance, found once
+        const uint32_t g = persistent_grid(kern, CHASE_TPB);
+        return LOG != 0 ? std::min<uint32_t>(g, LOG_MAX_WAVES / (CHASE_TPB / 64)) : g;  // bounds the log slack
+    }();
     const uint32_t S = (uint32_t)p.m[l + 1];
     auto* slot = reinterpret_cast<typename L::Slot*>(ws + p.off_slot[l]);
     auto* eb = reinterpret_cast<typename L::Rec*>(ws + p.off_eb[l]);
@@ -3173,9 +3169,8 @@ static hipError_t run_spawn_t(const RunArgs& a, Out0 out0) {
         SrcIn<W, WT> src{a.succ, a.weight, n};
         auto k1 = k_sp_chase1<W, WT>;
         auto k2 = k_sp_chase2<W, WT>;
-        static uint32_t g1 = 0, g2 = 0;  // one per template instance
-        if (!g1) g1 = persistent_grid(k1, SP_TPB);
-        if (!g2) g2 = persistent_grid(k2, SP_TPB);
+        static const uint32_t g1 = persistent_grid(k1, SP_TPB);  // one per template instance, found once
+        static const uint32_t g2 = persistent_grid(k2, SP_TPB);
         const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)LR_SPAWN_CAP << p.sp_log2k, n);
         hipLaunchKernelGGL(k1, dim3(g1), dim3(SP_TPB), 0, st, src, smp, ctrl, slot, lrec, hp_c, cap, g);
         LR_TRY(hipGetLastError());
