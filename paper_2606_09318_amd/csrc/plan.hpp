@@ -226,9 +226,12 @@ bool tune_lookup(uint64_t n, bool weighted, lr_opts* o);
 
 // Base-case shared memory bytes for m elements.
 inline size_t base_lds_bytes(uint64_t m, bool weighted) {
-    // unweighted: one 8 B (count, successor) word per element; weighted: 8 B
+    // unweighted: one 8 B (count, successor) word per slot, 4096, 8192 or
+    // 16384 slots (whole columns of the 1024-lane workgroup); weighted: 8 B
     // sum, 4 B count and 2 B successor arrays
-    return (size_t)m * (weighted ? 14 : 8) + 64;
+    if (weighted) return (size_t)m * 14 + 64;
+    const uint64_t slots = (m <= 4096) ? 4096 : (m <= 8192) ? 8192 : 16384;
+    return (size_t)(m > slots ? m : slots) * 8 + 64;
 }
 
 }  // namespace lr
