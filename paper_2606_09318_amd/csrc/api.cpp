@@ -38,16 +38,20 @@ static uint32_t ilog2(uint32_t k) {
 // they take shorter walks: 8 on the first level below 2^23 elements, 16 up to
 // 2^24, 32 beyond; above the first level 4 below 2^17 elements, 8 up to 2^20,
 // 16 beyond (measured per size on MI355X: 6-18 % faster from 2^17 to 2^23;
-// from 2^25 on the longer walks stay ahead). The last level takes the
-// smallest spacing that brings it under base_max.
+// from 2^25 on the longer walks stay ahead). From 2^25 the first level takes
+// 32 up to 3 * 2^26 elements and 64 beyond (32 is 7 % faster at 2^26 and
+// 2 % at 2^27, 64 is 2 % faster at 2^28); weighted inputs (16 B records)
+// take 64 from 2^26 (32 was 2 % slower on a 2^27 forest). The last level
+// takes the smallest spacing that brings it under base_max.
 constexpr uint64_t SHORT_WALKS_BELOW = 1ull << 25;
-static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max, bool short_walks) {
+static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max, bool short_walks, bool weighted) {
     uint32_t k;
     if (short_walks) {
         if (l == 0) k = (m >= (1ull << 24)) ? 32 : (m >= (1ull << 23)) ? 16 : 8;
         else k = (m >= (1ull << 20)) ? 16 : (m >= (1ull << 17)) ? 8 : 4;
     } else {
-        if (l == 0) k = (m >= (1ull << 26)) ? 64 : (m >= (1ull << 23) ? 32 : 16);
+        const uint64_t k64 = weighted ? (1ull << 26) : (3ull << 26);
+        if (l == 0) k = (m >= k64) ? 64 : (m >= (1ull << 23) ? 32 : 16);
         else k = 16;
     }
     uint32_t kmin = 2;
@@ -72,7 +76,7 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
             uint64_t m = m0;
             uint32_t L = 0;
             while (m > b && L < (uint32_t)LR_MAX_LEVELS) {
-                const uint32_t k = default_spacing(L, m, b, true);
+                const uint32_t k = default_spacing(L, m, b, true, false);
                 m = (m + k - 1) / k;
                 ++L;
             }
@@ -104,7 +108,7 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
             if (L >= max_levels) return LR_ERR_UNSUPPORTED;
             uint32_t k;
             if (user && o->spacing[L]) k = o->spacing[L];
-            else { user = false; k = default_spacing(L, m, bm, sw); }
+            else { user = false; k = default_spacing(L, m, bm, sw, weighted); }
             p->log2k[L] = ilog2(k);
             p->lseed[L] = (uint32_t)mix64(seed * 0x2545f4914f6cdd1dULL + 0x1000 + L);
             m = (m + k - 1) / k;
