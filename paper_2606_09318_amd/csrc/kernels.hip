@@ -842,6 +842,66 @@ __device__ __forceinline__ void base_pd_unweighted(Src& src, uint32_t m, unsigne
     }
 }
 
+// Weighted levels of at most 8192 elements, the same way: a (d << 32) | f
+// word and the 8 B sum per slot, two gathers per element and round.
+template <int COLS, class Src>
+__device__ __forceinline__ void base_pd_weighted(Src& src, uint32_t m, unsigned char* lds, uint32_t* f_,
+                                                 uint32_t* dc_, int64_t* ds_) {
+    using Val = typename Lay<true>::Val;
+    uint64_t* fd = reinterpret_cast<uint64_t*>(lds);
+    int64_t* sd = reinterpret_cast<int64_t*>(lds + 8 * (size_t)(COLS * BASE_TPB));
+    const uint32_t t = threadIdx.x;
+    uint64_t e_[COLS];
+    int64_t s_[COLS];
+#pragma unroll
+    for (int j = 0; j < COLS; ++j) {
+        const uint32_t i = t + j * BASE_TPB;
+        e_[j] = (uint64_t)i;
+        s_[j] = 0;
+        if (i < m) {
+            uint32_t nxt;
+            Val v;
+            src.load(i, nxt, v);
+            if (!((nxt & TERM) || nxt >= m)) {
+                e_[j] = ((uint64_t)v.c << 32) | nxt;
+                s_[j] = v.s;
+            }
+        }
+        fd[i] = e_[j];
+        sd[i] = s_[j];
+    }
+    __syncthreads();
+    for (int round = 0; round < 40; ++round) {
+        uint32_t changed = 0;
+        uint64_t w_[COLS];
+        int64_t v_[COLS];
+#pragma unroll
+        for (int j = 0; j < COLS; ++j) {
+            w_[j] = fd[(uint32_t)e_[j]];
+            v_[j] = sd[(uint32_t)e_[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < COLS; ++j) {
+            changed |= (uint32_t)w_[j] ^ (uint32_t)e_[j];
+            e_[j] = ((uint64_t)((uint32_t)(e_[j] >> 32) + (uint32_t)(w_[j] >> 32)) << 32) | (uint32_t)w_[j];
+            s_[j] += v_[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < COLS; ++j) {
+            fd[t + j * BASE_TPB] = e_[j];
+            sd[t + j * BASE_TPB] = s_[j];
+        }
+        if (!__syncthreads_or(changed != 0)) break;
+    }
+#pragma unroll
+    for (int j = 0; j < COLS; ++j) {
+        f_[j] = (uint32_t)e_[j];
+        dc_[j] = (uint32_t)(e_[j] >> 32);
+        ds_[j] = s_[j];
+    }
+}
+
 template <bool W, class Src, class Out>
 __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m, Ctrl* ctrl, const uint32_t* dm, Gate gate) {
     if (gate.off()) return;
@@ -850,7 +910,6 @@ __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m,
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t mcap = m;            // LDS is carved for the planned size
     if (dm) m = src.m = min(dm[0], m);  // a device-side size is at most that
-    (void)mcap;
     const uint32_t t = threadIdx.x;
     // each lane keeps its own elements' (f, d) in registers and writes them
     // to LDS after every round, where the other lanes gather them
@@ -860,7 +919,13 @@ __global__ __launch_bounds__(BASE_TPB) void k_base(Src src, Out out, uint32_t m,
         if (mcap <= 4 * BASE_TPB) base_pd_unweighted<4>(src, m, lds, f_, dc_);
         else if (mcap <= 8 * BASE_TPB) base_pd_unweighted<8>(src, m, lds, f_, dc_);
         else base_pd_unweighted<16>(src, m, lds, f_, dc_);
+    } else if (mcap <= 4 * BASE_TPB) {
+        base_pd_weighted<4>(src, m, lds, f_, dc_, ds_);
+    } else if (mcap <= 8 * BASE_TPB) {
+        base_pd_weighted<8>(src, m, lds, f_, dc_, ds_);
     } else {
+        // larger weighted levels (a user base size above 8192): 8 B sum,
+        // 4 B count and 2 B successor arrays
         int64_t* ds = reinterpret_cast<int64_t*>(lds);
         uint32_t* dc = reinterpret_cast<uint32_t*>(lds + 8 * (size_t)m);
         uint16_t* f = reinterpret_cast<uint16_t*>(lds + 12 * (size_t)m);

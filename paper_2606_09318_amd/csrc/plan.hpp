@@ -226,11 +226,12 @@ bool tune_lookup(uint64_t n, bool weighted, lr_opts* o);
 
 // Base-case shared memory bytes for m elements.
 inline size_t base_lds_bytes(uint64_t m, bool weighted) {
-    // unweighted: one 8 B (count, successor) word per slot, 4096, 8192 or
-    // 16384 slots (whole columns of the 1024-lane workgroup); weighted: 8 B
-    // sum, 4 B count and 2 B successor arrays
-    if (weighted) return (size_t)m * 14 + 64;
+    // one 8 B (count, successor) word per slot, 4096, 8192 or 16384 slots
+    // (whole columns of the 1024-lane workgroup), weighted with an 8 B sum
+    // per slot as well; weighted levels above 8192 elements: 8 B sum, 4 B
+    // count and 2 B successor arrays
     const uint64_t slots = (m <= 4096) ? 4096 : (m <= 8192) ? 8192 : 16384;
+    if (weighted) return m <= 8192 ? (size_t)slots * 16 + 64 : (size_t)m * 14 + 64;
     return (size_t)(m > slots ? m : slots) * 8 + 64;
 }
 
