@@ -68,10 +68,10 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
     if (bm < 1 || bm > BASE_MAX_LIMIT) return LR_ERR_INVALID_ARG;
     const bool user_spacing_set = user_spacing && o && o->spacing[0];
     const bool short_walks = m0 < SHORT_WALKS_BELOW;
-    if (!(o && o->base_max) && !weighted && !user_spacing_set && short_walks) {
-        // unweighted inputs below 2^25: a base case of 16384 elements where it
-        // saves a level over 8192 (a level costs more than the larger base
-        // case), else 8192
+    if (!(o && o->base_max) && !user_spacing_set && short_walks) {
+        // inputs below 2^25: a base case of twice the size (16384 elements
+        // unweighted, 8192 weighted) where it saves a level (a level costs
+        // more than the larger base case)
         auto levels_for = [m0](uint32_t b) {
             uint64_t m = m0;
             uint32_t L = 0;
