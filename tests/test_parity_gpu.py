@@ -348,3 +348,35 @@ def test_log_mode_invalid_input_is_memory_safe():
     bad = rng.integers(0, n, size=n).astype(np.uint32)
     assert gpu_rank(bad, lr.make_opts(flags=LOG))[0] == lr.LR_OK
     assert gpu_rank(bad)[0] == lr.LR_OK
+
+
+# The base case's slot columns (4096, 8192 or 16384 slots, padded with
+# self-loops): levels of every size around the column boundaries, alone and
+# as the last level under one ruling-set level, unweighted and weighted
+# (weighted levels above 8192 elements take the separate-array layout).
+@pytest.mark.parametrize("n,base,spacing", [
+    (1, 0, ()), (1023, 0, ()), (1025, 0, ()), (4095, 0, ()), (4097, 0, ()), (8191, 0, ()), (8193, 0, ()),
+    (12289, 0, ()), (16383, 0, ()), (16384, 0, ()), (16383 * 2, 16384, (2,)), (8193 * 4, 8193, (4,)),
+    (4097 * 8, 4097, (8,)), (12000 * 8, 12000, (8,))])
+def test_base_case_columns(n, base, spacing):
+    print(f"case: base columns n={n} base={base} spacing={spacing}", flush=True)
+    o = lr.make_opts(base_max=base, spacing=spacing) if (base or spacing) else None
+    check_rank(workloads.random_list(n, seed=300 + n).succ, o)
+    F = workloads.forest(n, mean=5, n_long=1, long_len=max(1, n // 3), seed=400 + n)
+    check_rank(F.succ, o)
+
+
+@pytest.mark.parametrize("n,base,spacing", [
+    (1, 0, ()), (4095, 4096, ()), (4097, 8192, ()), (8192, 8192, ()), (8193, 10000, ()), (10000, 10000, ()),
+    (4097 * 4, 4097, (4,)), (8192 * 4, 8192, (4,)), (10000 * 4, 10000, (4,)), (50001, 0, ())])
+def test_base_case_columns_weighted(n, base, spacing):
+    print(f"case: weighted base columns n={n} base={base} spacing={spacing}", flush=True)
+    o = lr.make_opts(base_max=base, spacing=spacing) if (base or spacing) else None
+    for L in (workloads.random_list(n, seed=500 + n), workloads.forest(n, mean=5, n_long=1,
+                                                                      long_len=max(1, n // 3), seed=600 + n)):
+        w = workloads.weights(n, seed=700 + n, stream=0, lo=-(1 << 40), hi=1 << 40)
+        st, s, r, t = gpu_prefix(L.succ, w, o)
+        assert st == lr.LR_OK, lr.status_string(st)
+        ost, er, et, es = oracle.rank(L.succ, w)
+        assert ost == 0
+        assert np.array_equal(s, es) and np.array_equal(r, er) and np.array_equal(t, et)
