@@ -60,8 +60,12 @@ static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max, bool 
 }
 
 // Levels, spacing and seeds for a level-0 list of (at most) m0 elements.
+// capped: m0 is a capacity (the contracted path's plan), whose actual size
+// is usually far below it; its first level switches to spacing 64 from 2^26
+// as weighted inputs do, which keeps its level count (and the launches it
+// enqueues on every call) down.
 static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool user_spacing, Plan* p,
-                             uint32_t max_levels = LR_MAX_LEVELS) {
+                             uint32_t max_levels = LR_MAX_LEVELS, bool capped = false) {
     p->weighted = weighted;
     p->rec_bytes = weighted ? 16 : 8;
     uint32_t bm = (o && o->base_max) ? o->base_max : (weighted ? 4096u : 8192u);
@@ -108,7 +112,7 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
             if (L >= max_levels) return LR_ERR_UNSUPPORTED;
             uint32_t k;
             if (user && o->spacing[L]) k = o->spacing[L];
-            else { user = false; k = default_spacing(L, m, bm, sw, weighted); }
+            else { user = false; k = default_spacing(L, m, bm, sw, weighted || capped); }
             p->log2k[L] = ilog2(k);
             p->lseed[L] = (uint32_t)mix64(seed * 0x2545f4914f6cdd1dULL + 0x1000 + L);
             m = (m + k - 1) / k;
@@ -300,7 +304,7 @@ lr_status make_plans(uint64_t n, bool weighted, const lr_opts* o, uint32_t batch
         Plan* q = &ps->lp;
         lr_opts lo = o ? *o : lr_opts{};
         for (int l = 0; l < LR_MAX_LEVELS; ++l) lo.spacing[l] = 0;  // user spacing describes the plain levels
-        s = plan_levels(local_auto_cap(n), weighted, &lo, false, q);
+        s = plan_levels(local_auto_cap(n), weighted, &lo, false, q, LR_MAX_LEVELS, true);
         if (s != LR_OK) return s;
         q->off_ctrl = p->off_ctrl;
         q->off_hsum = p->off_hsum;
