@@ -41,16 +41,18 @@ static uint32_t ilog2(uint32_t k) {
 // from 2^25 on the longer walks stay ahead). From 2^25 the first level takes
 // 32 up to 3 * 2^26 elements and 64 beyond (32 is 7 % faster at 2^26 and
 // 2 % at 2^27, 64 is 2 % faster at 2^28); weighted inputs (16 B records)
-// take 64 from 2^26 (32 was 2 % slower on a 2^27 forest). The last level
+// take 64 from 2^27 (32 is 2-6 % faster at 2^26, 2 % slower on a 2^27
+// forest), a plan sized for a capacity (capped) from 2^26. The last level
 // takes the smallest spacing that brings it under base_max.
 constexpr uint64_t SHORT_WALKS_BELOW = 1ull << 25;
-static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max, bool short_walks, bool weighted) {
+static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max, bool short_walks, bool weighted,
+                                bool capped) {
     uint32_t k;
     if (short_walks) {
         if (l == 0) k = (m >= (1ull << 24)) ? 32 : (m >= (1ull << 23)) ? 16 : 8;
         else k = (m >= (1ull << 20)) ? 16 : (m >= (1ull << 17)) ? 8 : 4;
     } else {
-        const uint64_t k64 = weighted ? (1ull << 26) : (3ull << 26);
+        const uint64_t k64 = capped ? (1ull << 26) : weighted ? (1ull << 27) : (3ull << 26);
         if (l == 0) k = (m >= k64) ? 64 : (m >= (1ull << 23) ? 32 : 16);
         else k = 16;
     }
@@ -61,9 +63,9 @@ static uint32_t default_spacing(uint32_t l, uint64_t m, uint32_t base_max, bool 
 
 // Levels, spacing and seeds for a level-0 list of (at most) m0 elements.
 // capped: m0 is a capacity (the contracted path's plan), whose actual size
-// is usually far below it; its first level switches to spacing 64 from 2^26
-// as weighted inputs do, which keeps its level count (and the launches it
-// enqueues on every call) down.
+// is usually far below it; its first level switches to spacing 64 from
+// 2^26, which keeps its level count (and the launches it enqueues on every
+// call) down.
 static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool user_spacing, Plan* p,
                              uint32_t max_levels = LR_MAX_LEVELS, bool capped = false) {
     p->weighted = weighted;
@@ -80,7 +82,7 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
             uint64_t m = m0;
             uint32_t L = 0;
             while (m > b && L < (uint32_t)LR_MAX_LEVELS) {
-                const uint32_t k = default_spacing(L, m, b, true, false);
+                const uint32_t k = default_spacing(L, m, b, true, false, false);
                 m = (m + k - 1) / k;
                 ++L;
             }
@@ -112,7 +114,7 @@ static lr_status plan_levels(uint64_t m0, bool weighted, const lr_opts* o, bool 
             if (L >= max_levels) return LR_ERR_UNSUPPORTED;
             uint32_t k;
             if (user && o->spacing[L]) k = o->spacing[L];
-            else { user = false; k = default_spacing(L, m, bm, sw, weighted || capped); }
+            else { user = false; k = default_spacing(L, m, bm, sw, weighted, capped); }
             p->log2k[L] = ilog2(k);
             p->lseed[L] = (uint32_t)mix64(seed * 0x2545f4914f6cdd1dULL + 0x1000 + L);
             m = (m + k - 1) / k;
