@@ -71,6 +71,44 @@ def test_plan_honours_spacing_and_base():
         lr.lr_plan_query(1000, lr.LR_W_NONE, lr.make_opts(base_max=1 << 20))
 
 
+def plan_of(n, w=lr.LR_W_NONE, opts=None):
+    p = lr.lr_plan_query(n, w, opts)
+    return int(p.base_max), [int(p.spacing[i]) for i in range(p.levels)]
+
+
+def test_default_plans_follow_the_measured_rules():
+    """The planner's defaults (chosen by per-size measurements on MI355X):
+    below 2^25 short walks and a doubled base case where it saves a level,
+    from 2^25 first-level spacing 32, then 64 from 3 * 2^26 elements
+    (weighted: from 2^27); the last level the smallest spacing that fits."""
+    assert plan_of(1 << 14) == (16384, [])
+    assert plan_of(1 << 18) == (8192, [8, 4])
+    assert plan_of(1 << 20) == (16384, [8, 8])
+    assert plan_of(1 << 22) == (16384, [8, 8, 4])
+    assert plan_of(1 << 24) == (16384, [32, 8, 4])
+    assert plan_of(1 << 25) == (8192, [32, 16, 8])
+    assert plan_of(1 << 26) == (8192, [32, 16, 16])
+    assert plan_of(1 << 27) == (8192, [32, 16, 16, 2])
+    assert plan_of(3 << 26) == (8192, [64, 16, 16, 2])
+    assert plan_of(1 << 28) == (8192, [64, 16, 16, 2])
+    w = lr.LR_W_I64
+    assert plan_of(1 << 13, w) == (8192, [])
+    assert plan_of(1 << 14, w) == (4096, [4])
+    assert plan_of(1 << 16, w) == (8192, [8])
+    assert plan_of(1 << 26, w) == (4096, [32, 16, 16, 2])
+    assert plan_of(1 << 27, w) == (4096, [64, 16, 16, 2])
+
+
+def test_plans_stay_within_the_level_limit():
+    """Where short walks would need more than the 8 levels (many user levels
+    of spacing 2, a tiny base), the planner takes the long walks instead."""
+    base, sp = plan_of(30011, opts=lr.make_opts(spacing=(2, 2, 2, 2, 2), base_max=8))
+    assert sp[:5] == [2, 2, 2, 2, 2] and len(sp) <= 8
+    assert plan_of(30011, opts=lr.make_opts(spacing=(64, 2), base_max=1))[1][:2] == [64, 2]
+    p = lr.lr_plan_query(158309, lr.LR_W_NONE, lr.make_opts(flags=lr.LR_SPAWN, spacing=(8, 4, 2), base_max=16))
+    assert p.levels <= 6  # spawning keeps one level entry for its input
+
+
 def test_workspace_monotone_and_weighted_larger():
     prev = 0
     for e in range(0, 31):
