@@ -172,3 +172,46 @@ def test_euler_tree_2p26():
     assert torch.equal(pl[kids[first]], pl[kp[first]] + 1)
     nxt, prev = kids[1:][~first[1:]], kids[:-1][~first[1:]]
     assert torch.equal(pl[nxt], pl[prev] + zl[prev])
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n", [(1 << 25) - 1, 1 << 25, (3 << 26) - 1, 3 << 26])
+def test_planner_thresholds(n):
+    """Sizes on both sides of the planner's switches: short walks, a doubled
+    base case and random slot stores below 2^25, the visit log and
+    first-level spacing 32 from 2^25, spacing 64 from 3 * 2^26. Every rank and
+    root equals the closed form of a device-generated order."""
+    torch.cuda.empty_cache()
+    print(f"case: planner threshold n={n}", flush=True)
+    succ, order = workloads.random_list_device(n)
+    r, t = lr.rank(succ)
+    torch.cuda.synchronize()
+    assert bool((t == order[-1]).all())
+    assert torch.equal(r.index_select(0, order), torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda"))
+    del succ, order, r, t
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n", [(1 << 25) - 1, (1 << 27) - 1, 1 << 27])
+def test_planner_thresholds_weighted(n):
+    """Weighted inputs on both sides of their switches (short walks and an
+    8192-element base case below 2^25, first-level spacing 64 from 2^27):
+    every prefix sum equals the sum of the weights from the element up to its
+    list's tail (the tail's own weight not included), taken in list order."""
+    torch.cuda.empty_cache()
+    print(f"case: weighted planner threshold n={n}", flush=True)
+    succ, order = workloads.random_list_device(n)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n)
+    w = torch.randint(-(1 << 40), 1 << 40, (n,), dtype=torch.int64, device="cuda", generator=g)
+    s, r, t = lr.prefix_sum(succ, w)
+    torch.cuda.synchronize()
+    ws = w.index_select(0, order)
+    ws[-1] = 0
+    expect = torch.flip(torch.cumsum(torch.flip(ws, [0]), 0), [0])
+    assert torch.equal(s.index_select(0, order), expect)
+    assert torch.equal(r.index_select(0, order), torch.arange(n - 1, -1, -1, dtype=torch.int32, device="cuda"))
+    assert bool((t == order[-1]).all())
+    del succ, order, w, s, r, t, ws, expect
+    torch.cuda.empty_cache()

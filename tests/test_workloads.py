@@ -86,3 +86,18 @@ def test_striped_list(n):
     for t in range(0, (n + 4095) // 4096, 16):
         ids = np.arange(t * 4096, min(n, (t + 1) * 4096))
         assert np.all(np.diff(pos[ids]) == 1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 1000, 65537, (1 << 20) + 3])
+def test_device_generator_is_one_list(n):
+    """The device-side generator (keyed Feistel over the smallest even-width
+    domain holding [0, n), cycle walking), run on the CPU: its order is a
+    permutation of [0, n) and its successors link that order into one list."""
+    import torch
+    succ, order = workloads.random_list_device(n, device="cpu")
+    o = order.numpy().astype(np.int64)
+    assert np.array_equal(np.sort(o), np.arange(n))
+    s = succ.numpy().astype(np.int64)
+    assert np.array_equal(s[o[:-1]], o[1:]) and s[o[-1]] == o[-1]
+    again, _ = workloads.random_list_device(n, device="cpu")
+    assert torch.equal(succ, again)

@@ -121,14 +121,21 @@ def random_list(n: int, seed: int = 1, stream: int = 0) -> ListInput:
     return ListInput(link_order(order), order)
 
 
-def feistel32_torch(x, keys):
-    """A keyed balanced Feistel network on 32-bit values (16-bit halves) in
-    int64 tensor arithmetic (any torch device): a bijection of [0, 2^32)."""
-    lo, hi = x & 0xFFFF, (x >> 16) & 0xFFFF
+def feistel_torch(x, keys, half=16):
+    """A keyed balanced Feistel network on 2 * half-bit values (half-bit
+    halves) in int64 tensor arithmetic (any torch device): a bijection of
+    [0, 2^(2 half)), half <= 16."""
+    mask = (1 << half) - 1
+    lo, hi = x & mask, (x >> half) & mask
     for k in keys:
-        f = ((lo * 0x9E37 + k) ^ (lo >> 5) ^ (lo * 0x85EB >> 7)) & 0xFFFF
+        f = ((lo * 0x9E37 + k) ^ (lo >> 5) ^ (lo * 0x85EB >> 7)) & mask
         lo, hi = hi ^ f, lo
-    return (hi << 16) | lo
+    return (hi << half) | lo
+
+
+def feistel32_torch(x, keys):
+    """feistel_torch on 32-bit values (16-bit halves)."""
+    return feistel_torch(x, keys, 16)
 
 
 DEVICE_ORDER_KEYS = (0x3A51, 0x7C2D, 0x1E93, 0x5B07)
@@ -141,12 +148,17 @@ def random_list_device(n: int, device="cuda", keys=DEVICE_ORDER_KEYS):
     order int32) tensors; rank[order[j]] = n-1-j."""
     import torch
     assert 0 < n < (1 << 31)
-    order = feistel32_torch(torch.arange(n, dtype=torch.int64, device=device), keys)
-    for _ in range(256):  # the domain is at most 2^32 / n times larger: each walk step keeps >= n / 2^32
+    bits = 2
+    while (1 << bits) < n:
+        bits += 1
+    bits += bits & 1
+    half = bits // 2  # the smallest even-width domain that holds [0, n): at most 4 n values
+    order = feistel_torch(torch.arange(n, dtype=torch.int64, device=device), keys, half)
+    for _ in range(256):  # each walk step leaves a value outside [0, n) with probability <= 3/4
         out = order >= n
         if not bool(out.any()):
             break
-        order[out] = feistel32_torch(order[out], keys)
+        order[out] = feistel_torch(order[out], keys, half)
     if bool((order >= n).any()):
         raise RuntimeError("cycle walking did not finish")
     succ = torch.empty(n, dtype=torch.int32, device=device)
