@@ -63,6 +63,7 @@ constexpr uint32_t CHASE_GRAB = 64;  // walks a wavefront takes from the pool at
 #ifndef LR_XCD_GROUPS
 #define LR_XCD_GROUPS 1   // second grouping pass: the tiles of one coarse range on one XCD
 #endif
+static_assert(LR_XCD_GROUPS == 0 || LR_XCD_GROUPS == 1, "XCD grouping is on (1) or off (0)");
 static_assert(CHASE_TPB % 64 == 0 && CHASE_TPB >= 64 && CHASE_TPB <= 1024, "chase workgroup width");
 static_assert(LR_CHASE_POOL >= 0 && LR_CHASE_POOL < 16, "pool share of the walks, in sixteenths");
 
@@ -1943,6 +1944,7 @@ constexpr int LC_TPB = 512;
 #ifndef LR_LC_GRID_PER_CU
 #define LR_LC_GRID_PER_CU 64  // chain kernel workgroups per CU, each looping over tiles; 0 = one per tile
 #endif
+static_assert(LR_LC_GRID_PER_CU >= 0 && LR_LC_GRID_PER_CU <= 1024, "chain kernel workgroups per CU");
 constexpr uint32_t LC_T = LOCAL_TILE;
 constexpr int LC_PER = LC_T / LC_TPB;   // elements per lane
 constexpr int LC_ROUNDS = 14;           // > log2(LC_T): chains of a tile converge within this many rounds

@@ -21,6 +21,7 @@ constexpr uint32_t LOG_MAX_WAVES = 8192;     // chase waves in log mode (caps th
 #ifndef LR_LOG_MIN_LOG2
 #define LR_LOG_MIN_LOG2 25
 #endif
+static_assert(LR_LOG_MIN_LOG2 >= 16 && LR_LOG_MIN_LOG2 <= 31, "visit-log threshold: 2^16 .. 2^31 elements");
 constexpr uint64_t LOG_MIN_N = 1ull << LR_LOG_MIN_LOG2;  // smallest level 0 that uses the visit log
 constexpr uint64_t LOG_FORCE_MIN_N = 1ull << 16;          // smallest level 0 LR_VISIT_LOG applies to
 // Packed visit-log records (one 64-bit word) up to 2^28 elements: then the
